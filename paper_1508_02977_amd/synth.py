@@ -1,0 +1,174 @@
+"""Seeded synthetic image pairs for the optical-flow workloads.
+
+This module draws and evaluates test images only; it holds none of the
+method's arithmetic (no gradients, no finite elements, no solver).  Both the
+GPU path's tests/benchmarks and the FP64 CPU oracle's tests take their inputs
+from here, so both sides see bit-identical frames.
+
+Conventions (paper, Section 2, brightness constancy with the Gennert-
+Negahdaripour illumination law, M = 1 + dm and a negligible translator T):
+  * node (x, y) is the centre of pixel (x, y); x is the column, y the row;
+    arrays are indexed ``[y, x]`` and stored row-major in float64;
+  * the second frame is ``I1(x) = m(x) * I0(x - w(x))``, evaluated analytically
+    from the closed-form bump sum, so no interpolation enters the inputs;
+  * ground truth is the flow ``w`` and the gain ``m``; to first order the
+    illumination unknown of the model is ``m - 1``.
+
+Workload recipes (sizes and distributions of the paper's experiments, which
+used real sequences that are not available here):
+  * ``plain64``  : 64x64, 40 Gaussian bumps (sigma U[3,8], amplitude
+    U[0.2,1]), affine flow ``t + J (x - xc)`` rescaled to max |w| <= 1.5,
+    gain ``1 + 0.1 b/max|b|`` with b four signed bumps of scale W/4.
+  * ``plain640`` : 640x480, 200 bumps, flow ``(R(2 deg) - I)(x - xc) + t`` with
+    |t| <= 3, gain ``1 + 0.15 b/max|b|``, i.i.d. N(0, 0.01^2) noise added to
+    both frames after warping.
+  * ``linear``   : ``I0 = 0.5 + p x + q y``, uniform translation, used by the
+    exact-recovery pins.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+
+@dataclasses.dataclass
+class Bumps:
+    """A sum of isotropic Gaussian bumps ``sum_k a_k exp(-|x-c_k|^2 / (2 s_k^2))``."""
+
+    cx: np.ndarray
+    cy: np.ndarray
+    s: np.ndarray
+    a: np.ndarray
+    base: float = 0.0
+
+    def __call__(self, X: np.ndarray, Y: np.ndarray) -> np.ndarray:
+        out = np.full(np.broadcast(X, Y).shape, self.base, dtype=np.float64)
+        for cx, cy, s, a in zip(self.cx, self.cy, self.s, self.a):
+            out += a * np.exp(-((X - cx) ** 2 + (Y - cy) ** 2) / (2.0 * s * s))
+        return out
+
+
+def random_bumps(rng: np.random.Generator, W: int, H: int, n: int,
+                 s_range=(3.0, 8.0), a_range=(0.2, 1.0), signed=False) -> Bumps:
+    cx = rng.uniform(0.0, W - 1.0, n)
+    cy = rng.uniform(0.0, H - 1.0, n)
+    s = rng.uniform(s_range[0], s_range[1], n)
+    a = rng.uniform(a_range[0], a_range[1], n)
+    if signed:
+        a = a * rng.choice([-1.0, 1.0], n)
+    return Bumps(cx, cy, s, a)
+
+
+@dataclasses.dataclass
+class Pair:
+    """One synthetic frame pair with its ground truth."""
+
+    I0: np.ndarray        # [H, W] float64
+    I1: np.ndarray        # [H, W] float64
+    w: np.ndarray         # [2, H, W] ground-truth flow (w1 = x-displacement)
+    gain: np.ndarray      # [H, W] multiplicative illumination m(x)
+    name: str = ""
+
+    @property
+    def shape(self):
+        return self.I0.shape
+
+
+def _grid(W: int, H: int):
+    X, Y = np.meshgrid(np.arange(W, dtype=np.float64),
+                       np.arange(H, dtype=np.float64))
+    return X, Y
+
+
+def _gain_field(rng, W, H, X, Y, amp):
+    b = random_bumps(rng, W, H, 4, s_range=(W / 4.0, W / 4.0),
+                     a_range=(0.5, 1.0), signed=True)
+    bv = b(X, Y)
+    return 1.0 + amp * bv / np.max(np.abs(bv))
+
+
+def make_pair(kind: str, seed: int, W: int | None = None, H: int | None = None,
+              noise: float | None = None) -> Pair:
+    """Draw one pair of the named recipe; ``W``/``H`` override the size."""
+    rng = np.random.default_rng(seed)
+    if kind == "plain64":
+        W = W or 64
+        H = H or 64
+        nb = max(1, round(40 * W * H / (64 * 64)))
+        X, Y = _grid(W, H)
+        img = random_bumps(rng, W, H, nb)
+        t = rng.uniform(-1.0, 1.0, 2)
+        J = rng.uniform(-0.02, 0.02, (2, 2))
+        xc, yc = (W - 1) / 2.0, (H - 1) / 2.0
+        w1 = t[0] + J[0, 0] * (X - xc) + J[0, 1] * (Y - yc)
+        w2 = t[1] + J[1, 0] * (X - xc) + J[1, 1] * (Y - yc)
+        mx = np.max(np.hypot(w1, w2))
+        if mx > 1.5:
+            w1 *= 1.5 / mx
+            w2 *= 1.5 / mx
+        gain = _gain_field(rng, W, H, X, Y, 0.1)
+        I0 = img(X, Y)
+        I1 = gain * img(X - w1, Y - w2)
+        sig = 0.0 if noise is None else noise
+    elif kind == "plain640":
+        W = W or 640
+        H = H or 480
+        nb = max(1, round(200 * W * H / (640 * 480)))
+        X, Y = _grid(W, H)
+        img = random_bumps(rng, W, H, nb)
+        th = math.radians(2.0)
+        R = np.array([[math.cos(th), -math.sin(th)], [math.sin(th), math.cos(th)]])
+        D = R - np.eye(2)
+        r_t = 3.0 * math.sqrt(rng.uniform())
+        phi = rng.uniform(0.0, 2.0 * math.pi)
+        t = np.array([r_t * math.cos(phi), r_t * math.sin(phi)])
+        xc, yc = (W - 1) / 2.0, (H - 1) / 2.0
+        w1 = D[0, 0] * (X - xc) + D[0, 1] * (Y - yc) + t[0]
+        w2 = D[1, 0] * (X - xc) + D[1, 1] * (Y - yc) + t[1]
+        gain = _gain_field(rng, W, H, X, Y, 0.15)
+        I0 = img(X, Y)
+        I1 = gain * img(X - w1, Y - w2)
+        sig = 0.01 if noise is None else noise
+    else:
+        raise ValueError(f"unknown pair kind {kind!r}")
+    if sig > 0.0:
+        I0 = I0 + rng.normal(0.0, sig, I0.shape)
+        I1 = I1 + rng.normal(0.0, sig, I1.shape)
+    return Pair(np.ascontiguousarray(I0), np.ascontiguousarray(I1),
+                np.stack([w1, w2]), gain, name=f"{kind}:{seed}:{W}x{H}")
+
+
+def linear_pair(W: int, H: int, p: float, q: float, w=(0.3, -0.2)) -> Pair:
+    """``I0 = 0.5 + p x + q y`` translated by the constant ``w``."""
+    X, Y = _grid(W, H)
+    I0 = 0.5 + p * X + q * Y
+    I1 = 0.5 + p * (X - w[0]) + q * (Y - w[1])
+    wf = np.stack([np.full_like(X, w[0]), np.full_like(X, w[1])])
+    return Pair(I0, I1, wf, np.ones_like(X), name=f"linear:{W}x{H}")
+
+
+def gain_pair(W: int, H: int, c: float, seed: int = 7) -> Pair:
+    """Textured ``I0`` and ``I1 = (1 + c) I0``: pure illumination change, no motion."""
+    rng = np.random.default_rng(seed)
+    X, Y = _grid(W, H)
+    img = random_bumps(rng, W, H, max(4, W * H // 100))
+    I0 = 0.2 + img(X, Y)
+    I1 = (1.0 + c) * I0
+    return Pair(I0, I1, np.zeros((2, H, W)), np.full_like(X, 1.0 + c),
+                name=f"gain:{W}x{H}")
+
+
+def constant_alpha(W: int, H: int, alpha: float = 0.1, batch: int | None = None) -> np.ndarray:
+    """Per-element regularisation array ``[H-1, W-1, 2]`` (``[B, ...]`` if batched)."""
+    a = np.full((H - 1, W - 1, 2), alpha, dtype=np.float64)
+    if batch is not None:
+        a = np.broadcast_to(a, (batch,) + a.shape).copy()
+    return a
+
+
+def random_alpha(W: int, H: int, seed: int, lo=0.02, hi=0.2) -> np.ndarray:
+    """Piecewise-constant α drawn per element (log-uniform in [lo, hi])."""
+    rng = np.random.default_rng(seed)
+    return np.exp(rng.uniform(math.log(lo), math.log(hi), (H - 1, W - 1, 2)))
