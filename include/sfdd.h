@@ -1,0 +1,166 @@
+/*
+ * sfdd.h - C ABI of the overlapping-Schwarz optical-flow solver for MI355X.
+ *
+ * Method: Gilliocq-Hirtz & Belhachmi, "A massively parallel multi-level
+ * approach to a domain decomposition method for the optical flow estimation
+ * with varying illumination".  The library solves the P1 finite-element
+ * discretisation (Section 3.2) of the Euler-Lagrange system of functional
+ * (BW2) (Section 2), Horn-Schunck regularisation with a per-element alpha and
+ * the Gennert-Negahdaripour illumination unknown m, by additive Schwarz with
+ * overlapping rectangular subdomains and Dirichlet transmission (Section 4.2,
+ * equation (schwarz)), each subdomain solved directly by a Cholesky
+ * factorisation of its banded matrix; alpha is adapted with the residual
+ * indicator of Section 3.3.
+ *
+ * Conventions shared by every call:
+ *   - W x H nodes, one per pixel centre; node (x, y), x = column, y = row.
+ *   - Each pixel square (x,y)-(x+1,y+1) is cut by its (x,y)-(x+1,y+1)
+ *     diagonal into T0 = {(x,y),(x+1,y),(x+1,y+1)} and T1 = {(x,y),(x+1,y+1),(x,y+1)}.
+ *   - Frames I0, I1:    double [B][H][W], row-major.
+ *   - alpha, eta:       double [B][H-1][W-1][2], last index T0/T1.
+ *   - U, F, residuals:  double [B][3][H][W], field planes u1 (x-flow),
+ *                       u2 (y-flow), m (illumination derivative m_t).
+ *   - All array pointers are DEVICE pointers (HIP memory on the context's
+ *     device) unless a parameter says "host".  The caller owns them; the
+ *     library never frees or retains caller pointers past a call.
+ *   - Work is enqueued on the stream given to sf_create.  Calls that return
+ *     host scalars synchronise that stream before returning.
+ *   - Return value: SF_OK (0), a negative error (nothing useful was
+ *     computed) or a positive numerical status (outputs are written).
+ *   - A context is not thread-safe; use one context per host thread/stream.
+ */
+#ifndef SFDD_H
+#define SFDD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define SF_OK              0
+#define SF_ERR_INVALID    (-1)  /* bad argument or configuration             */
+#define SF_ERR_HIP        (-2)  /* a HIP runtime call failed                  */
+#define SF_ERR_OOM        (-3)  /* device allocation failed                   */
+#define SF_ERR_STATE      (-4)  /* calls out of order (e.g. solve before factor) */
+#define SF_ERR_DEVICE     (-5)  /* a device-side wait gave up (see sf_error_detail) */
+#define SF_NOT_SPD          1   /* a subdomain matrix is not positive definite */
+#define SF_NOT_CONVERGED    2   /* max_sweeps reached above rtol; U is written */
+#define SF_NONFINITE        3   /* NaN/Inf in the inputs or in a residual norm */
+
+/* factor_precision */
+#define SF_FP64      0          /* subdomain factors stored and applied in FP64 */
+
+typedef struct sf_config {
+    int32_t width;            /* W >= 2 nodes                                    */
+    int32_t height;           /* H >= 2 nodes                                    */
+    int32_t batch;            /* B >= 1 independent frame pairs                   */
+    int32_t parts_x;          /* tiles across, 1 <= parts_x <= W                  */
+    int32_t parts_y;          /* tiles down,   1 <= parts_y <= H                  */
+    int32_t overlap;          /* delta >= 0: nodes shared by neighbouring boxes   */
+    double  lambda;           /* regularisation of m (> 0), constant (Section 3.3) */
+    double  sigma;            /* Gaussian presmoothing of the frames; must be 0   */
+    int32_t factor_precision; /* SF_FP64                                          */
+    int32_t band_tile;        /* workgroups per subdomain in a sweep; 0 = auto    */
+} sf_config;
+
+typedef struct sf_context sf_context;
+
+/* Create a context for one geometry (Section 4.1: tile (p,q) owns nodes
+ * [floor(pW/Px), floor((p+1)W/Px)) x [floor(qH/Py), floor((q+1)H/Py));
+ * its box extends every side interior to the image by floor(delta/2)
+ * (left/top) or ceil(delta/2) (right/bottom) nodes).  `stream` is a
+ * hipStream_t (NULL = default stream).  Allocates all device storage the
+ * geometry needs (factors: about 4*m*(m+32) bytes per grid line of every
+ * subdomain, m = 3 x the shorter box side).  On success *out owns it.       */
+int sf_create(const sf_config* cfg, void* stream, sf_context** out);
+
+/* Release everything the context owns (NULL is accepted). */
+void sf_destroy(sf_context* ctx);
+
+/* Section 2 and 3.2: copy I0, I1 and alpha into the context and build the
+ * right-hand side F_i = -int f_t a phi_i, a = (f_x, f_y, -f), f = I0 (P1),
+ * f_t = I1 - I0 (P1), integrated exactly.  Returns SF_NONFINITE if a frame
+ * value is not finite and SF_ERR_INVALID if an alpha is not finite or <= 0.
+ * Makes previous factors stale.                                             */
+int sf_assemble(sf_context* ctx, const double* I0, const double* I1, const double* alpha);
+
+/* Section 4.2, local problems: factor every subdomain matrix A_i = A[S_i,S_i]
+ * (ordering: lines along the shorter box side, 3 unknowns per node, band
+ * half-width 3*ms+5).  Block Cholesky over the lines: S_t = A_tt -
+ * B_t S_{t-1}^{-1} B_t^T, each S_t factored by Cholesky and stored inverted.
+ * Returns SF_NOT_SPD (with sf_error_detail) if a pivot is not positive.    */
+int sf_factor_subdomains(sf_context* ctx);
+
+/* Section 4.2, equation (schwarz), restricted additive form: from the
+ * initial guess in U, repeat r = F - A U, relres = ||r||/||F|| (per pair);
+ * stop a pair when relres <= rtol or after max_sweeps sweeps; otherwise
+ * U[O_i] += (A_i^{-1} r[S_i])[O_i] for every subdomain i (O_i its owned
+ * nodes).  U [B][3][H][W] is read and overwritten.  sweeps [B] and relres
+ * [B] are HOST arrays (either may be NULL).  A pair with F = 0 returns
+ * U = 0 after 0 sweeps.  Returns SF_NOT_CONVERGED if a pair stopped on
+ * max_sweeps above rtol (U still written), SF_NONFINITE on a NaN norm.   */
+int sf_schwarz_solve(sf_context* ctx, double* U, double rtol, int32_t max_sweeps,
+                     int32_t* sweeps, double* relres);
+
+/* Section 3.3: residual indicator eta_K (flow components, alpha weights,
+ * element residual + half the flux jumps) and the decrease rule
+ * alpha <- max(alpha / (1 + kappa max(eta/||eta||_inf - eta_thr, 0)), alpha_th)
+ * with ||eta||_inf per pair.  alpha [B][H-1][W-1][2] is overwritten with
+ * the new values, which also replace the context's copy; factors become
+ * stale (call sf_factor_subdomains before the next solve; F is unchanged).
+ * eta_max [B] is a HOST array or NULL.                                     */
+int sf_update_alpha(sf_context* ctx, const double* U, double* alpha,
+                    double kappa, double eta_thr, double alpha_th, double* eta_max);
+
+/* Detail of the last SF_NOT_SPD / SF_ERR_DEVICE status: pair, subdomain
+ * index (row-major tile order within the pair) and local row.  Host outputs,
+ * any may be NULL.  Returns the status it describes.                       */
+int sf_error_detail(const sf_context* ctx, int32_t* pair, int32_t* subdomain, int64_t* row);
+
+/* Static text for a status code. */
+const char* sf_status_string(int status);
+
+/* ---- diagnostics (same math, exposed for verification) ------------------ */
+
+/* Copy F [B][3][H][W] (valid after sf_assemble) into `F`.                   */
+int sf_rhs(sf_context* ctx, double* F);
+
+/* r = F - A U for U [B][3][H][W]; rnorm2 [B] HOST (||r||^2) or NULL.       */
+int sf_residual(sf_context* ctx, const double* U, double* r, double* rnorm2);
+
+/* eta_K of sf_update_alpha without changing alpha; eta [B][H-1][W-1][2].   */
+int sf_indicator(sf_context* ctx, const double* U, double* eta);
+
+/* Host-only geometry plan (no device needed): returns the number of
+ * subdomains of `cfg` (or a negative error) and, if geom != NULL, fills
+ * geom[10*i .. 10*i+9] (HOST) with pair, box x0, x1, y0, y1, owned x0, x1,
+ * y0, y1 and the lines-are-columns flag of subdomain i (same order as the
+ * context uses: pair-major, then row-major tiles).                          */
+int sf_plan(const sf_config* cfg, int32_t* geom);
+
+/* Kernel timing with HIP events recorded on the context stream around every
+ * launch of the sweep, factor and residual kernels (off by default; adds
+ * one event pair per launch).  ms[4] / launches[4] (HOST, may be NULL)
+ * receive the totals so far for classes 0 sweep, 1 factor, 2 residual +
+ * stop test, 3 other.  enable: 1 = reset and start, 0 = reset and stop,
+ * -1 = only read.                                                          */
+int sf_profile(sf_context* ctx, int32_t enable, double* ms, int64_t* launches);
+
+/* Number of subdomains over all pairs (B * parts_x * parts_y).             */
+int sf_num_subdomains(const sf_context* ctx);
+
+/* geom[11] (HOST): pair, box x0, x1, y0, y1 (half-open), owned x0, x1, y0,
+ * y1, lines-are-columns flag, workgroups per subdomain used by a sweep.    */
+int sf_subdomain_geometry(const sf_context* ctx, int32_t sub, int32_t* geom);
+
+/* x = A_i^{-1} b for subdomain `sub` from its factors; b and x hold
+ * 3*bw*bh doubles in the local ordering 3*(t*ms + s) + c (line t, position s
+ * along the line, field c).  Device pointers, may not alias.               */
+int sf_subdomain_solve(sf_context* ctx, int32_t sub, const double* b, double* x);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SFDD_H */

@@ -1,0 +1,321 @@
+"""Python binding of the sfdd C ABI (``include/sfdd.h``).
+
+Argument marshalling only: every step of the method runs in the HIP library
+``libsfdd.so``.  Functions carry the C names; arrays are torch tensors on the
+GPU (float64, contiguous, the layouts of ``sfdd.h``).  Negative statuses and
+SF_NOT_SPD / SF_NONFINITE raise :class:`SfError`; SF_NOT_CONVERGED is returned
+by :func:`sf_schwarz_solve` because the iterate is still written.
+
+There is no fallback: if the library is missing the import of a function
+raises.  Build it with ``python -m paper_1508_02977_amd.build``.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsfdd.so")
+
+SF_OK = 0
+SF_ERR_INVALID = -1
+SF_ERR_HIP = -2
+SF_ERR_OOM = -3
+SF_ERR_STATE = -4
+SF_ERR_DEVICE = -5
+SF_NOT_SPD = 1
+SF_NOT_CONVERGED = 2
+SF_NONFINITE = 3
+SF_FP64 = 0
+
+c_int32 = ctypes.c_int32
+c_double = ctypes.c_double
+c_void_p = ctypes.c_void_p
+
+
+class sf_config(ctypes.Structure):
+    _fields_ = [
+        ("width", c_int32), ("height", c_int32), ("batch", c_int32),
+        ("parts_x", c_int32), ("parts_y", c_int32), ("overlap", c_int32),
+        ("lambda_", c_double), ("sigma", c_double),
+        ("factor_precision", c_int32), ("band_tile", c_int32),
+    ]
+
+
+class SfError(RuntimeError):
+    def __init__(self, code: int, where: str, detail=None):
+        self.code = code
+        self.detail = detail
+        msg = f"{where}: {status_string(code)} ({code})"
+        if detail is not None:
+            msg += f" detail={detail}"
+        super().__init__(msg)
+
+
+# name -> (restype, argtypes)
+_SIGS = {
+    "sf_create": (c_int32, [ctypes.POINTER(sf_config), c_void_p, ctypes.POINTER(c_void_p)]),
+    "sf_destroy": (None, [c_void_p]),
+    "sf_assemble": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
+    "sf_factor_subdomains": (c_int32, [c_void_p]),
+    "sf_schwarz_solve": (c_int32, [c_void_p, c_void_p, c_double, c_int32, c_void_p, c_void_p]),
+    "sf_update_alpha": (c_int32, [c_void_p, c_void_p, c_void_p, c_double, c_double, c_double, c_void_p]),
+    "sf_error_detail": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
+    "sf_status_string": (ctypes.c_char_p, [c_int32]),
+    "sf_rhs": (c_int32, [c_void_p, c_void_p]),
+    "sf_residual": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
+    "sf_indicator": (c_int32, [c_void_p, c_void_p, c_void_p]),
+    "sf_plan": (c_int32, [ctypes.POINTER(sf_config), c_void_p]),
+    "sf_num_subdomains": (c_int32, [c_void_p]),
+    "sf_subdomain_geometry": (c_int32, [c_void_p, c_int32, c_void_p]),
+    "sf_subdomain_solve": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p]),
+    "sf_profile": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p]),
+}
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load ``libsfdd.so`` (after torch, so both share one HIP runtime)."""
+    global _lib
+    if _lib is None:
+        import torch  # noqa: F401  (its libamdhip64 becomes the process HIP runtime)
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_1508_02977_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def exported_symbols() -> list[str]:
+    return list(_SIGS)
+
+
+def status_string(code: int) -> str:
+    try:
+        return lib().sf_status_string(code).decode()
+    except ImportError:
+        return f"status {code}"
+
+
+# ---- argument helpers ----------------------------------------------------
+
+def _dev(t, shape, name):
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.device.type != "cuda" or t.dtype != torch.float64 or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous float64 CUDA tensor")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return c_void_p(t.data_ptr())
+
+
+def _check(code: int, where: str, ctx=None, allow=()):
+    if code == SF_OK or code in allow:
+        return code
+    detail = None
+    if ctx is not None and code in (SF_NOT_SPD, SF_ERR_DEVICE):
+        detail = sf_error_detail(ctx)
+    raise SfError(code, where, detail)
+
+
+@dataclasses.dataclass
+class Context:
+    """Owning handle of an ``sf_context``; shapes of its arrays."""
+
+    handle: c_void_p
+    cfg: sf_config
+
+    @property
+    def W(self):
+        return self.cfg.width
+
+    @property
+    def H(self):
+        return self.cfg.height
+
+    @property
+    def B(self):
+        return self.cfg.batch
+
+    def frame_shape(self):
+        return (self.B, self.H, self.W)
+
+    def alpha_shape(self):
+        return (self.B, self.H - 1, self.W - 1, 2)
+
+    def field_shape(self):
+        return (self.B, 3, self.H, self.W)
+
+    def close(self):
+        if self.handle:
+            lib().sf_destroy(self.handle)
+            self.handle = c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def make_config(width, height, batch=1, parts_x=1, parts_y=1, overlap=0, lam=1.0, sigma=0.0,
+                factor_precision=SF_FP64, band_tile=0) -> sf_config:
+    return sf_config(width, height, batch, parts_x, parts_y, overlap, lam, sigma, factor_precision, band_tile)
+
+
+# ---- the C entry points --------------------------------------------------
+
+def sf_create(width, height, batch=1, parts_x=1, parts_y=1, overlap=0, lam=1.0, sigma=0.0,
+              factor_precision=SF_FP64, band_tile=0, stream=None) -> Context:
+    import torch
+    cfg = make_config(width, height, batch, parts_x, parts_y, overlap, lam, sigma, factor_precision, band_tile)
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    h = c_void_p()
+    _check(lib().sf_create(ctypes.byref(cfg), c_void_p(stream.cuda_stream), ctypes.byref(h)), "sf_create")
+    return Context(h, cfg)
+
+
+def sf_destroy(ctx: Context) -> None:
+    ctx.close()
+
+
+def sf_assemble(ctx: Context, I0, I1, alpha) -> None:
+    _check(lib().sf_assemble(ctx.handle, _dev(I0, ctx.frame_shape(), "I0"), _dev(I1, ctx.frame_shape(), "I1"),
+                             _dev(alpha, ctx.alpha_shape(), "alpha")), "sf_assemble")
+
+
+def sf_factor_subdomains(ctx: Context) -> None:
+    _check(lib().sf_factor_subdomains(ctx.handle), "sf_factor_subdomains", ctx)
+
+
+def sf_schwarz_solve(ctx: Context, U, rtol: float, max_sweeps: int):
+    """Returns (status, sweeps[B], relres[B]); status is SF_OK or SF_NOT_CONVERGED."""
+    sw = (c_int32 * ctx.B)()
+    rr = (c_double * ctx.B)()
+    code = lib().sf_schwarz_solve(ctx.handle, _dev(U, ctx.field_shape(), "U"), float(rtol), int(max_sweeps),
+                                  ctypes.cast(sw, c_void_p), ctypes.cast(rr, c_void_p))
+    _check(code, "sf_schwarz_solve", ctx, allow=(SF_NOT_CONVERGED,))
+    return code, list(sw), list(rr)
+
+
+def sf_update_alpha(ctx: Context, U, alpha, kappa=1.0, eta_thr=0.1, alpha_th=1e-3):
+    """Updates ``alpha`` in place; returns ||eta||_inf per pair."""
+    em = (c_double * ctx.B)()
+    _check(lib().sf_update_alpha(ctx.handle, _dev(U, ctx.field_shape(), "U"),
+                                 _dev(alpha, ctx.alpha_shape(), "alpha"), float(kappa), float(eta_thr),
+                                 float(alpha_th), ctypes.cast(em, c_void_p)), "sf_update_alpha")
+    return list(em)
+
+
+def sf_error_detail(ctx: Context):
+    p, s, r = c_int32(), c_int32(), ctypes.c_int64()
+    code = lib().sf_error_detail(ctx.handle, ctypes.byref(p), ctypes.byref(s), ctypes.byref(r))
+    return dict(code=code, pair=p.value, subdomain=s.value, row=r.value)
+
+
+def sf_status_string(code: int) -> str:
+    return status_string(code)
+
+
+def sf_rhs(ctx: Context, F) -> None:
+    _check(lib().sf_rhs(ctx.handle, _dev(F, ctx.field_shape(), "F")), "sf_rhs")
+
+
+def sf_residual(ctx: Context, U, r):
+    n2 = (c_double * ctx.B)()
+    _check(lib().sf_residual(ctx.handle, _dev(U, ctx.field_shape(), "U"), _dev(r, ctx.field_shape(), "r"),
+                             ctypes.cast(n2, c_void_p)), "sf_residual")
+    return list(n2)
+
+
+def sf_indicator(ctx: Context, U, eta) -> None:
+    _check(lib().sf_indicator(ctx.handle, _dev(U, ctx.field_shape(), "U"), _dev(eta, ctx.alpha_shape(), "eta")),
+           "sf_indicator")
+
+
+def sf_plan(width, height, batch=1, parts_x=1, parts_y=1, overlap=0, lam=1.0):
+    """Host-only geometry: list of dicts per subdomain (no GPU needed)."""
+    cfg = make_config(width, height, batch, parts_x, parts_y, overlap, lam)
+    n = lib().sf_plan(ctypes.byref(cfg), None)
+    _check(min(n, 0), "sf_plan")
+    g = (c_int32 * (10 * n))()
+    lib().sf_plan(ctypes.byref(cfg), ctypes.cast(g, c_void_p))
+    return [_geom(list(g[10 * i:10 * i + 10])) for i in range(n)]
+
+
+def _geom(g):
+    return dict(pair=g[0], box=(g[1], g[2], g[3], g[4]), own=(g[5], g[6], g[7], g[8]), cols=bool(g[9]),
+                P=g[10] if len(g) > 10 else None)
+
+
+PROFILE_CLASSES = ("sweep", "factor", "residual", "other")
+
+
+def sf_profile(ctx: Context, enable: int = -1):
+    """Per-kernel-class event timings: {class: (total_ms, launches)}."""
+    ms = (c_double * 4)()
+    n = (ctypes.c_int64 * 4)()
+    _check(lib().sf_profile(ctx.handle, int(enable), ctypes.cast(ms, c_void_p), ctypes.cast(n, c_void_p)),
+           "sf_profile")
+    return {k: (ms[i], n[i]) for i, k in enumerate(PROFILE_CLASSES)}
+
+
+def sf_num_subdomains(ctx: Context) -> int:
+    return lib().sf_num_subdomains(ctx.handle)
+
+
+def sf_subdomain_geometry(ctx: Context, sub: int):
+    g = (c_int32 * 11)()
+    _check(lib().sf_subdomain_geometry(ctx.handle, int(sub), ctypes.cast(g, c_void_p)), "sf_subdomain_geometry")
+    return _geom(list(g))
+
+
+def sf_subdomain_solve(ctx: Context, sub: int, b, x) -> None:
+    geo = sf_subdomain_geometry(ctx, sub)
+    x0, x1, y0, y1 = geo["box"]
+    n = 3 * (x1 - x0) * (y1 - y0)
+    _check(lib().sf_subdomain_solve(ctx.handle, int(sub), _dev(b, (n,), "b"), _dev(x, (n,), "x")),
+           "sf_subdomain_solve", ctx)
+
+
+# ---- the adaptive pipeline (Section 3.3 loop on the fixed pixel mesh) ------
+
+@dataclasses.dataclass
+class PipelineResult:
+    sweeps: list          # per solve: list over pairs
+    relres: list
+    eta_max: list         # per alpha update: list over pairs
+    status: int
+
+
+def run_pipeline(ctx: Context, I0, I1, alpha, U, rtol=1e-8, max_sweeps=1000, passes=0, kappa=1.0,
+                 eta_thr=0.1, alpha_th=1e-3, sweeps_per_solve=None) -> PipelineResult:
+    """assemble -> factor -> solve -> (update_alpha -> factor -> solve) x passes.
+
+    ``alpha`` is updated in place and ``U`` holds the final iterate (each solve
+    warm-starts from the previous one).  ``sweeps_per_solve`` forces exact
+    sweep counts (rtol 0), for comparisons at equal sweep counts.
+    """
+    sf_assemble(ctx, I0, I1, alpha)
+    sweeps, rels, etas = [], [], []
+    status = SF_OK
+    for it in range(passes + 1):
+        sf_factor_subdomains(ctx)
+        if sweeps_per_solve is not None:
+            code, sw, rr = sf_schwarz_solve(ctx, U, 0.0, sweeps_per_solve[it])
+        else:
+            code, sw, rr = sf_schwarz_solve(ctx, U, rtol, max_sweeps)
+            status = max(status, code)
+        sweeps.append(sw)
+        rels.append(rr)
+        if it < passes:
+            etas.append(sf_update_alpha(ctx, U, alpha, kappa, eta_thr, alpha_th))
+    return PipelineResult(sweeps, rels, etas, status)

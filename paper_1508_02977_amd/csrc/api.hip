@@ -1,0 +1,507 @@
+// C ABI of the sfdd library: context, geometry, entry points.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "sfdd_internal.h"
+
+using sfdd::SubDesc;
+
+namespace {
+
+constexpr int ST_CREATED = 0, ST_ASSEMBLED = 1, ST_FACTORED = 2;
+
+template <class T>
+int dalloc(T** p, size_t count) {
+    *p = nullptr;
+    if (count == 0) count = 1;
+    if (hipMalloc((void**)p, count * sizeof(T)) != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return SF_ERR_OOM;
+    }
+    return SF_OK;
+}
+
+#define SF_TRY(x)                    \
+    do {                             \
+        int rc_ = (x);               \
+        if (rc_ != SF_OK) return rc_; \
+    } while (0)
+#define SF_HIP(x)                                   \
+    do {                                            \
+        if ((x) != hipSuccess) return SF_ERR_HIP;   \
+    } while (0)
+
+__global__ void k_fill_i32(int32_t* p, int n, int32_t v) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ void k_zero_status_api(sfdd::DevStatus* st) {
+    st->code = 0;
+    st->sub = -1;
+    st->row = -1;
+}
+
+int fill_i32(sf_context* c, int32_t* p, int n, int32_t v) {
+    hipLaunchKernelGGL(k_fill_i32, dim3((n + 255) / 256), dim3(256), 0, c->stream, p, n, v);
+    return hipGetLastError() == hipSuccess ? SF_OK : SF_ERR_HIP;
+}
+
+// Pinned staging layout: status word at 0, flags at 64, then three arrays of
+// B 8-byte slots (A: done flags / norms, B: relres, C: sweeps).
+constexpr size_t STAGE_FLAGS = 64, STAGE_A = 128;
+inline char* stage_a(sf_context* c) { return (char*)c->host_stage + STAGE_A; }
+inline char* stage_b(sf_context* c) { return stage_a(c) + 8 * (size_t)c->B; }
+inline char* stage_c(sf_context* c) { return stage_b(c) + 8 * (size_t)c->B; }
+
+int pull_status(sf_context* c) {
+    sfdd::DevStatus* hs = (sfdd::DevStatus*)c->host_stage;
+    SF_HIP(hipMemcpyAsync(hs, c->status_d, sizeof(sfdd::DevStatus), hipMemcpyDeviceToHost, c->stream));
+    SF_HIP(hipStreamSynchronize(c->stream));
+    c->status_h = *hs;
+    return c->status_h.code;
+}
+
+// Tile cuts c_k = floor(k N / P).
+int cut(int k, int N, int P) { return (int)(((int64_t)k * N) / P); }
+
+int check_config(const sf_config& k) {
+    if (k.width < 2 || k.height < 2 || k.batch < 1) return SF_ERR_INVALID;
+    if (k.parts_x < 1 || k.parts_y < 1 || k.parts_x > k.width || k.parts_y > k.height) return SF_ERR_INVALID;
+    if (k.overlap < 0 || !(k.lambda > 0.0) || !std::isfinite(k.lambda)) return SF_ERR_INVALID;
+    if (k.sigma != 0.0 || k.factor_precision != SF_FP64 || k.band_tile < 0) return SF_ERR_INVALID;
+    if ((int64_t)k.width * k.height * k.batch > (1ll << 31)) return SF_ERR_INVALID;
+    return SF_OK;
+}
+
+// Subdomains of all pairs, row-major tile order within a pair (Section 4.1):
+// tile (p, q) owns [cx_p, cx_{p+1}) x [cy_q, cy_{q+1}); its box grows by
+// floor(delta/2) on interior left/top sides and ceil(delta/2) on interior
+// right/bottom sides; lines run along the shorter box side.
+std::vector<SubDesc> plan_subdomains(const sf_config& k) {
+    std::vector<SubDesc> out;
+    const int lo = k.overlap / 2, hi = k.overlap - lo;
+    for (int pair = 0; pair < k.batch; ++pair)
+        for (int q = 0; q < k.parts_y; ++q)
+            for (int p = 0; p < k.parts_x; ++p) {
+                SubDesc d;
+                std::memset(&d, 0, sizeof(d));
+                d.pair = pair;
+                d.ox0 = cut(p, k.width, k.parts_x);
+                d.ox1 = cut(p + 1, k.width, k.parts_x);
+                d.oy0 = cut(q, k.height, k.parts_y);
+                d.oy1 = cut(q + 1, k.height, k.parts_y);
+                const int bx0 = p > 0 ? std::max(0, d.ox0 - lo) : 0;
+                const int bx1 = p < k.parts_x - 1 ? std::min(k.width, d.ox1 + hi) : k.width;
+                const int by0 = q > 0 ? std::max(0, d.oy0 - lo) : 0;
+                const int by1 = q < k.parts_y - 1 ? std::min(k.height, d.oy1 + hi) : k.height;
+                d.bx0 = bx0;
+                d.by0 = by0;
+                d.bw = bx1 - bx0;
+                d.bh = by1 - by0;
+                d.cols = d.bh <= d.bw;
+                d.ms = d.cols ? d.bh : d.bw;
+                d.nt = d.cols ? d.bw : d.bh;
+                d.m = 3 * d.ms;
+                d.NT = (d.m + sfdd::TS - 1) / sfdd::TS;
+                d.mp = d.NT * sfdd::TS;
+                d.ntiles = d.NT * (d.NT + 1) / 2;
+                out.push_back(d);
+            }
+    return out;
+}
+
+}  // namespace
+
+namespace sfdd {
+
+int prof_begin(sf_context* c, int kind) {
+    if (!c->profiling) return SF_OK;
+    const int need = 2 * (c->ev_used + 1);
+    while ((int)c->ev_pool.size() < need) {
+        hipEvent_t e;
+        SF_HIP(hipEventCreate(&e));
+        c->ev_pool.push_back(e);
+    }
+    c->ev_kind.resize(c->ev_used + 1);
+    c->ev_kind[c->ev_used] = kind;
+    SF_HIP(hipEventRecord(c->ev_pool[2 * c->ev_used], c->stream));
+    return SF_OK;
+}
+
+int prof_end(sf_context* c) {
+    if (!c->profiling) return SF_OK;
+    SF_HIP(hipEventRecord(c->ev_pool[2 * c->ev_used + 1], c->stream));
+    ++c->ev_used;
+    return SF_OK;
+}
+
+int prof_harvest(sf_context* c) {
+    if (!c->profiling || c->ev_used == 0) return SF_OK;
+    SF_HIP(hipEventSynchronize(c->ev_pool[2 * c->ev_used - 1]));
+    for (int i = 0; i < c->ev_used; ++i) {
+        float ms = 0.f;
+        SF_HIP(hipEventElapsedTime(&ms, c->ev_pool[2 * i], c->ev_pool[2 * i + 1]));
+        c->prof_ms[c->ev_kind[i]] += ms;
+        c->prof_n[c->ev_kind[i]] += 1;
+    }
+    c->ev_used = 0;
+    return SF_OK;
+}
+
+}  // namespace sfdd
+
+extern "C" {
+
+const char* sf_status_string(int s) {
+    switch (s) {
+        case SF_OK: return "ok";
+        case SF_ERR_INVALID: return "invalid argument";
+        case SF_ERR_HIP: return "HIP runtime error";
+        case SF_ERR_OOM: return "device out of memory";
+        case SF_ERR_STATE: return "call out of order";
+        case SF_ERR_DEVICE: return "device-side wait abandoned";
+        case SF_NOT_SPD: return "subdomain matrix not positive definite";
+        case SF_NOT_CONVERGED: return "not converged within max_sweeps";
+        case SF_NONFINITE: return "non-finite value";
+        default: return "unknown status";
+    }
+}
+
+void sf_destroy(sf_context* c) {
+    if (!c) return;
+    void* ptrs[] = {c->d_subs, c->d_wgmap, c->f0, c->ft, c->alpha, c->F, c->r, c->eta, c->Fn2,
+                    c->partials, c->relres_d, c->sweeps_d, c->done_d, c->counters, c->etamax_bits,
+                    c->flags_d, c->factors, c->work, c->status_d};
+    for (void* p : ptrs)
+        if (p) (void)hipFree(p);
+    if (c->host_stage) (void)hipHostFree(c->host_stage);
+    for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+    delete c;
+}
+
+int sf_create(const sf_config* cfg, void* stream, sf_context** out) {
+    if (!cfg || !out) return SF_ERR_INVALID;
+    *out = nullptr;
+    const sf_config k = *cfg;
+    SF_TRY(check_config(k));
+
+    sf_context* c = new (std::nothrow) sf_context();   // value-initialised: null pointers
+    if (!c) return SF_ERR_OOM;
+    c->cfg = k;
+    c->stream = (hipStream_t)stream;
+    c->W = k.width;
+    c->H = k.height;
+    c->B = k.batch;
+    if (hipGetDevice(&c->device) != hipSuccess) { sf_destroy(c); return SF_ERR_HIP; }
+
+    // ---- geometry (Section 4.1) --------------------------------------------
+    c->subs = plan_subdomains(k);
+    int maxmp = 0, min_tiles = 1 << 30;
+    for (const auto& d : c->subs) {
+        maxmp = std::max(maxmp, d.mp);
+        min_tiles = std::min(min_tiles, d.ntiles);
+    }
+    if (maxmp > 512) { sf_destroy(c); return SF_ERR_INVALID; }   // line matrices up to 512 x 512
+    c->nsub = (int)c->subs.size();
+
+    // ---- workgroups per subdomain in a sweep --------------------------------
+    int ncu = 0, occ = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess) {
+        sf_destroy(c);
+        return SF_ERR_HIP;
+    }
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, sfdd::sweep_kernel(), sfdd::SOLVE_THREADS, 0) !=
+            hipSuccess || occ < 1)
+        occ = 1;
+    const int capacity = ncu * occ;
+    int P = k.band_tile > 0 ? k.band_tile : std::max(1, std::min(capacity / c->nsub, min_tiles / 2));
+    P = std::min(P, min_tiles);
+    P = std::min(P, 255);
+    if ((int64_t)P * c->nsub > capacity) P = std::max(1, capacity / c->nsub);
+    c->maxP = P;
+    c->sweep_grid = P * c->nsub;
+
+    // ---- storage offsets -----------------------------------------------------
+    int64_t foff = 0, woff = 0;
+    for (auto& d : c->subs) {
+        d.P = P;
+        d.foff = foff;
+        foff += (int64_t)d.nt * d.ntiles * sfdd::TSZ;
+        d.boff = foff;
+        foff += (int64_t)d.nt * d.m * 6;
+        d.woff = woff;
+        woff += (int64_t)d.nt * d.mp;
+        d.poff = woff;
+        woff += (int64_t)2 * P * d.mp;
+        d.soff = woff;
+        woff += (int64_t)3 * d.mp * d.mp;
+    }
+    c->factor_doubles = foff;
+    c->work_doubles = woff;
+
+    // workgroup map: XCD-aware when the subdomains split evenly over the
+    // 8 XCDs (workgroup g runs on XCD g % 8): all ranks of a subdomain then
+    // share one L2.  Second half: subdomain-major order.
+    std::vector<int32_t> map(2 * (size_t)c->sweep_grid);
+    const int G = c->sweep_grid;
+    for (int g = 0; g < G; ++g) map[G + g] = ((g / P) << 8) | (g % P);
+    if (c->nsub % 8 == 0 && ncu % 8 == 0) {
+        for (int g = 0; g < G; ++g) {
+            const int x = g % 8, slot = g / 8;
+            const int sub = x + 8 * (slot / P), rank = slot % P;
+            map[g] = (sub << 8) | rank;
+        }
+    } else {
+        for (int g = 0; g < G; ++g) map[g] = map[G + g];
+    }
+
+    const int64_t nn = (int64_t)c->W * c->H, ne = (int64_t)(c->W - 1) * (c->H - 1) * 2;
+    c->npart = (int)((nn + 255) / 256);
+    int rc = SF_OK;
+    rc |= dalloc(&c->d_subs, c->subs.size());
+    rc |= dalloc(&c->d_wgmap, map.size());
+    rc |= dalloc(&c->f0, nn * c->B);
+    rc |= dalloc(&c->ft, nn * c->B);
+    rc |= dalloc(&c->alpha, ne * c->B);
+    rc |= dalloc(&c->eta, ne * c->B);
+    rc |= dalloc(&c->F, 3 * nn * c->B);
+    rc |= dalloc(&c->r, 3 * nn * c->B);
+    rc |= dalloc(&c->Fn2, c->B);
+    rc |= dalloc(&c->partials, (size_t)c->npart * c->B);
+    rc |= dalloc(&c->relres_d, c->B);
+    rc |= dalloc(&c->sweeps_d, c->B);
+    rc |= dalloc(&c->done_d, c->B);
+    rc |= dalloc(&c->counters, c->nsub);
+    rc |= dalloc(&c->etamax_bits, c->B);
+    rc |= dalloc(&c->flags_d, 4);
+    rc |= dalloc(&c->factors, (size_t)c->factor_doubles);
+    rc |= dalloc(&c->work, (size_t)c->work_doubles);
+    rc |= dalloc(&c->status_d, 1);
+    if (rc != SF_OK) { sf_destroy(c); return SF_ERR_OOM; }
+    const size_t stage = STAGE_A + 24 * (size_t)c->B + 64;
+    if (hipHostMalloc(&c->host_stage, stage, hipHostMallocDefault) != hipSuccess) {
+        c->host_stage = nullptr;
+        sf_destroy(c);
+        return SF_ERR_OOM;
+    }
+    if (hipMemcpy(c->d_subs, c->subs.data(), c->subs.size() * sizeof(SubDesc), hipMemcpyHostToDevice) !=
+            hipSuccess ||
+        hipMemcpy(c->d_wgmap, map.data(), map.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess) {
+        sf_destroy(c);
+        return SF_ERR_HIP;
+    }
+    hipLaunchKernelGGL(k_zero_status_api, dim3(1), dim3(1), 0, c->stream, c->status_d);
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess) {
+        sf_destroy(c);
+        return SF_ERR_HIP;
+    }
+    c->state = ST_CREATED;
+    *out = c;
+    return SF_OK;
+}
+
+int sf_assemble(sf_context* c, const double* I0, const double* I1, const double* alpha) {
+    if (!c || !I0 || !I1 || !alpha) return SF_ERR_INVALID;
+    c->state = ST_CREATED;
+    SF_TRY(fill_i32(c, c->flags_d, 4, 0));
+    SF_TRY(sfdd::launch_validate(c, I0, I1, alpha));
+    int32_t* hf = (int32_t*)((char*)c->host_stage + STAGE_FLAGS);
+    SF_HIP(hipMemcpyAsync(hf, c->flags_d, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+    SF_HIP(hipStreamSynchronize(c->stream));
+    if (hf[0]) return SF_NONFINITE;
+    if (hf[1]) return SF_ERR_INVALID;
+    SF_TRY(sfdd::launch_assemble(c, I0, I1, alpha));
+    c->state = ST_ASSEMBLED;
+    return SF_OK;
+}
+
+int sf_factor_subdomains(sf_context* c) {
+    if (!c) return SF_ERR_INVALID;
+    if (c->state < ST_ASSEMBLED) return SF_ERR_STATE;
+    SF_TRY(sfdd::prof_begin(c, sfdd::PROF_FACTOR));
+    SF_TRY(sfdd::launch_factor(c));
+    SF_TRY(sfdd::prof_end(c));
+    const int code = pull_status(c);
+    SF_TRY(sfdd::prof_harvest(c));
+    if (code != SF_OK) {
+        c->state = ST_ASSEMBLED;
+        return code;
+    }
+    c->state = ST_FACTORED;
+    return SF_OK;
+}
+
+int sf_schwarz_solve(sf_context* c, double* U, double rtol, int32_t max_sweeps, int32_t* sweeps, double* relres) {
+    if (!c || !U || max_sweeps < 0 || !(rtol >= 0.0)) return SF_ERR_INVALID;
+    if (c->state != ST_FACTORED) return SF_ERR_STATE;
+    SF_TRY(fill_i32(c, c->done_d, c->B, 0));
+    hipLaunchKernelGGL(k_zero_status_api, dim3(1), dim3(1), 0, c->stream, c->status_d);
+    SF_HIP(hipGetLastError());
+    int32_t* hd = (int32_t*)stage_a(c);
+    const int check_every = 4;
+    sfdd::DevStatus* hst = (sfdd::DevStatus*)c->host_stage;
+    for (int k = 0; k <= max_sweeps; ++k) {
+        SF_TRY(sfdd::prof_begin(c, sfdd::PROF_RESIDUAL));
+        SF_TRY(sfdd::launch_residual(c, U, c->r, 1, rtol, k, max_sweeps));
+        SF_TRY(sfdd::prof_end(c));
+        if (k == max_sweeps) break;
+        SF_TRY(sfdd::prof_begin(c, sfdd::PROF_SWEEP));
+        SF_TRY(sfdd::launch_sweep(c, U, c->r, -1, nullptr, nullptr));
+        SF_TRY(sfdd::prof_end(c));
+        if ((k + 1) % check_every == 0) {
+            SF_HIP(hipMemcpyAsync(hd, c->done_d, c->B * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+            SF_HIP(hipMemcpyAsync(hst, c->status_d, sizeof(sfdd::DevStatus), hipMemcpyDeviceToHost, c->stream));
+            SF_HIP(hipStreamSynchronize(c->stream));
+            SF_TRY(sfdd::prof_harvest(c));
+            if (hst->code != SF_OK) break;   // a device wait was abandoned
+            bool all = true;
+            for (int b = 0; b < c->B; ++b) all = all && hd[b];
+            if (all) break;
+        }
+    }
+    // results
+    double* hrel = (double*)stage_b(c);
+    int32_t* hsw = (int32_t*)stage_c(c);
+    SF_HIP(hipMemcpyAsync(hrel, c->relres_d, c->B * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    SF_HIP(hipMemcpyAsync(hsw, c->sweeps_d, c->B * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+    SF_HIP(hipStreamSynchronize(c->stream));
+    SF_TRY(sfdd::prof_harvest(c));
+    int rc = SF_OK;
+    for (int b = 0; b < c->B; ++b) {
+        if (relres) relres[b] = hrel[b];
+        if (sweeps) sweeps[b] = hsw[b];
+        if (!std::isfinite(hrel[b])) rc = SF_NONFINITE;
+        else if (hrel[b] > rtol && rc == SF_OK) rc = SF_NOT_CONVERGED;
+    }
+    const int code = pull_status(c);
+    if (code != SF_OK) return code;
+    return rc;
+}
+
+int sf_update_alpha(sf_context* c, const double* U, double* alpha, double kappa, double eta_thr, double alpha_th,
+                    double* eta_max) {
+    if (!c || !U || !alpha || !(kappa >= 0.0) || !std::isfinite(eta_thr) || !(alpha_th > 0.0)) return SF_ERR_INVALID;
+    if (c->state < ST_ASSEMBLED) return SF_ERR_STATE;
+    SF_TRY(sfdd::launch_indicator(c, U, c->eta, 1));
+    SF_TRY(sfdd::launch_alpha_update(c, c->eta, alpha, kappa, eta_thr, alpha_th));
+    c->state = ST_ASSEMBLED;   // factors are stale, F is unchanged
+    if (eta_max) {
+        uint64_t* hb = (uint64_t*)stage_a(c);
+        SF_HIP(hipMemcpyAsync(hb, c->etamax_bits, c->B * sizeof(uint64_t), hipMemcpyDeviceToHost, c->stream));
+        SF_HIP(hipStreamSynchronize(c->stream));
+        for (int b = 0; b < c->B; ++b) std::memcpy(&eta_max[b], &hb[b], sizeof(double));
+    }
+    return SF_OK;
+}
+
+int sf_error_detail(const sf_context* c, int32_t* pair, int32_t* subdomain, int64_t* row) {
+    if (!c) return SF_ERR_INVALID;
+    const int s = c->status_h.sub;
+    const int per = c->cfg.parts_x * c->cfg.parts_y;
+    if (pair) *pair = s >= 0 ? s / per : -1;
+    if (subdomain) *subdomain = s >= 0 ? s % per : -1;
+    if (row) *row = c->status_h.row;
+    return c->status_h.code;
+}
+
+int sf_rhs(sf_context* c, double* F) {
+    if (!c || !F) return SF_ERR_INVALID;
+    if (c->state < ST_ASSEMBLED) return SF_ERR_STATE;
+    SF_HIP(hipMemcpyAsync(F, c->F, 3 * sizeof(double) * c->W * c->H * c->B, hipMemcpyDeviceToDevice, c->stream));
+    return SF_OK;
+}
+
+int sf_residual(sf_context* c, const double* U, double* r, double* rnorm2) {
+    if (!c || !U || !r) return SF_ERR_INVALID;
+    if (c->state < ST_ASSEMBLED) return SF_ERR_STATE;
+    SF_TRY(sfdd::launch_residual(c, U, r, 0, 0.0, 0, 0));
+    if (rnorm2) {
+        double* h = (double*)stage_a(c);
+        SF_HIP(hipMemcpyAsync(h, c->relres_d, c->B * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        SF_HIP(hipStreamSynchronize(c->stream));
+        for (int b = 0; b < c->B; ++b) rnorm2[b] = h[b];
+    }
+    return SF_OK;
+}
+
+int sf_indicator(sf_context* c, const double* U, double* eta) {
+    if (!c || !U || !eta) return SF_ERR_INVALID;
+    if (c->state < ST_ASSEMBLED) return SF_ERR_STATE;
+    return sfdd::launch_indicator(c, U, eta, 1);
+}
+
+int sf_num_subdomains(const sf_context* c) { return c ? c->nsub : SF_ERR_INVALID; }
+
+int sf_profile(sf_context* c, int32_t enable, double* ms, int64_t* launches) {
+    if (!c) return SF_ERR_INVALID;
+    SF_TRY(sfdd::prof_harvest(c));
+    if (ms)
+        for (int i = 0; i < 4; ++i) ms[i] = c->prof_ms[i];
+    if (launches)
+        for (int i = 0; i < 4; ++i) launches[i] = c->prof_n[i];
+    if (enable >= 0) {
+        c->profiling = enable ? 1 : 0;
+        c->ev_used = 0;
+        for (int i = 0; i < 4; ++i) {
+            c->prof_ms[i] = 0.0;
+            c->prof_n[i] = 0;
+        }
+    }
+    return SF_OK;
+}
+
+int sf_plan(const sf_config* cfg, int32_t* geom) {
+    if (!cfg) return SF_ERR_INVALID;
+    SF_TRY(check_config(*cfg));
+    const std::vector<SubDesc> subs = plan_subdomains(*cfg);
+    if (geom) {
+        for (size_t i = 0; i < subs.size(); ++i) {
+            const SubDesc& d = subs[i];
+            int32_t* g = geom + 10 * i;
+            g[0] = d.pair;
+            g[1] = d.bx0;
+            g[2] = d.bx0 + d.bw;
+            g[3] = d.by0;
+            g[4] = d.by0 + d.bh;
+            g[5] = d.ox0;
+            g[6] = d.ox1;
+            g[7] = d.oy0;
+            g[8] = d.oy1;
+            g[9] = d.cols;
+        }
+    }
+    return (int)subs.size();
+}
+
+int sf_subdomain_geometry(const sf_context* c, int32_t sub, int32_t* g) {
+    if (!c || !g || sub < 0 || sub >= c->nsub) return SF_ERR_INVALID;
+    const SubDesc& d = c->subs[sub];
+    g[0] = d.pair;
+    g[1] = d.bx0;
+    g[2] = d.bx0 + d.bw;
+    g[3] = d.by0;
+    g[4] = d.by0 + d.bh;
+    g[5] = d.ox0;
+    g[6] = d.ox1;
+    g[7] = d.oy0;
+    g[8] = d.oy1;
+    g[9] = d.cols;
+    g[10] = d.P;
+    return SF_OK;
+}
+
+int sf_subdomain_solve(sf_context* c, int32_t sub, const double* b, double* x) {
+    if (!c || !b || !x || sub < 0 || sub >= c->nsub || b == x) return SF_ERR_INVALID;
+    if (c->state != ST_FACTORED) return SF_ERR_STATE;
+    hipLaunchKernelGGL(k_zero_status_api, dim3(1), dim3(1), 0, c->stream, c->status_d);
+    SF_HIP(hipGetLastError());
+    SF_TRY(sfdd::launch_sweep(c, nullptr, nullptr, sub, b, x));
+    const int code = pull_status(c);
+    return code;
+}
+
+}  // extern "C"

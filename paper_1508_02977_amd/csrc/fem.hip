@@ -1,0 +1,367 @@
+// Matrix-free P1 kernels: input validation, right-hand side, residual,
+// residual error indicator and the alpha update.  One thread per node (or
+// per element); every reduction is a fixed-order two-stage sum, so results
+// are bitwise reproducible run to run.
+#include <cmath>
+
+#include "element.h"
+#include "sfdd_internal.h"
+
+namespace sfdd {
+
+constexpr int NODE_THREADS = 256;
+
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+    // fixed-order reduction over the block (deterministic)
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) sh[wv] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += sh[i];
+    return s;
+}
+
+__global__ void k_validate(const double* __restrict__ I0, const double* __restrict__ I1,
+                           const double* __restrict__ al, int64_t nn, int64_t ne, int32_t* flags) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    int bad_img = 0, bad_al = 0;
+    for (int64_t k = i; k < nn; k += stride)
+        if (!isfinite(I0[k]) || !isfinite(I1[k])) bad_img = 1;
+    for (int64_t k = i; k < ne; k += stride)
+        if (!isfinite(al[k]) || !(al[k] > 0.0)) bad_al = 1;
+    if (bad_img) atomicOr(&flags[0], 1);
+    if (bad_al) atomicOr(&flags[1], 1);
+}
+
+// Copies f0 = I0, ft = I1 - I0, alpha; F = -int f_t a phi_i; ||F||^2 partials.
+__global__ void k_assemble(const double* __restrict__ I0, const double* __restrict__ I1,
+                           const double* __restrict__ al_in, double* __restrict__ f0,
+                           double* __restrict__ ft, double* __restrict__ al, double* __restrict__ F,
+                           double* __restrict__ partials, int npart, int W, int H) {
+    __shared__ double sh[NODE_THREADS / 64];
+    const int pair = blockIdx.y;
+    const int64_t nn = (int64_t)W * H, ne = (int64_t)(W - 1) * (H - 1) * 2;
+    const double* i0 = I0 + pair * nn;
+    const double* i1 = I1 + pair * nn;
+    const double* ali = al_in + pair * ne;
+    const int node = blockIdx.x * blockDim.x + threadIdx.x;
+    double acc = 0.0;
+    if (node < nn) {
+        f0[pair * nn + node] = i0[node];
+        ft[pair * nn + node] = i1[node] - i0[node];
+        for (int k = 0; k < 2; ++k) {
+            int64_t e = 2 * (int64_t)node + k;
+            if (e < ne) al[pair * ne + e] = ali[e];
+        }
+        const int x = node % W, y = node / W;
+        double out[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            const Around a = around(k);
+            const int cx = x + a.dcx, cy = y + a.dcy;
+            if (cx < 0 || cy < 0 || cx >= W - 1 || cy >= H - 1) continue;
+            Elem e = load_elem(i0, ali, W, H, cx, cy, a.t);
+            double ftv[3];
+#pragma unroll
+            for (int v = 0; v < 3; ++v) {
+                const int n = (cy + vdy(a.t, v)) * W + cx + vdx(a.t, v);
+                ftv[v] = i1[n] - i0[n];
+            }
+            double o[3];
+            elem_rhs_row(e, a.v, ftv, o);
+            out[0] += o[0];
+            out[1] += o[1];
+            out[2] += o[2];
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) F[(pair * 3 + c) * nn + node] = out[c];
+        acc = out[0] * out[0] + out[1] * out[1] + out[2] * out[2];
+    }
+    double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) partials[pair * npart + blockIdx.x] = s;
+}
+
+__global__ void k_finalize_norm(const double* __restrict__ partials, int npart, double* __restrict__ out) {
+    const int pair = blockIdx.x;
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int i = 0; i < npart; ++i) s += partials[pair * npart + i];
+        out[pair] = s;
+    }
+}
+
+// r = F - A U and ||r||^2 partials; pairs already converged are skipped.
+__global__ void k_residual(const double* __restrict__ f0, const double* __restrict__ al,
+                           const double* __restrict__ F, const double* __restrict__ U,
+                           double* __restrict__ r, double* __restrict__ partials, int npart,
+                           int W, int H, double lam, const int32_t* __restrict__ done) {
+    __shared__ double sh[NODE_THREADS / 64];
+    const int pair = blockIdx.y;
+    if (done != nullptr && done[pair]) {
+        if (threadIdx.x == 0) partials[pair * npart + blockIdx.x] = 0.0;
+        return;
+    }
+    const int64_t nn = (int64_t)W * H, ne = (int64_t)(W - 1) * (H - 1) * 2;
+    const double* fp = f0 + pair * nn;
+    const double* ap = al + pair * ne;
+    const double* Up = U + pair * 3 * nn;
+    const int node = blockIdx.x * blockDim.x + threadIdx.x;
+    double acc = 0.0;
+    if (node < nn) {
+        const int x = node % W, y = node / W;
+        double out[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) out[c] = F[(pair * 3 + c) * nn + node];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            const Around a = around(k);
+            const int cx = x + a.dcx, cy = y + a.dcy;
+            if (cx < 0 || cy < 0 || cx >= W - 1 || cy >= H - 1) continue;
+            Elem e = load_elem(fp, ap, W, H, cx, cy, a.t);
+            double u[3][3];
+#pragma unroll
+            for (int v = 0; v < 3; ++v) {
+                const int64_t n = (int64_t)(cy + vdy(a.t, v)) * W + cx + vdx(a.t, v);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) u[v][c] = Up[c * nn + n];
+            }
+            double o[3];
+            elem_apply_row(e, a.t, a.v, u, lam, o);
+            out[0] -= o[0];
+            out[1] -= o[1];
+            out[2] -= o[2];
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) r[(pair * 3 + c) * nn + node] = out[c];
+        acc = out[0] * out[0] + out[1] * out[1] + out[2] * out[2];
+    }
+    double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) partials[pair * npart + blockIdx.x] = s;
+}
+
+// Stop test of sweep `sweep` (checked before the sweep): per pair relres =
+// ||r||/||F||; a pair stops when relres <= rtol, on F = 0, on a non-finite
+// norm or when sweep == max_sweeps.  Also clears the sweep counters.
+__global__ void k_converge(const double* __restrict__ partials, int npart, const double* __restrict__ Fn2,
+                           double* __restrict__ relres, int32_t* __restrict__ sweeps,
+                           int32_t* __restrict__ done, int B, double rtol, int sweep, int max_sweeps,
+                           uint32_t* __restrict__ counters, int nsub) {
+    for (int i = threadIdx.x; i < nsub; i += blockDim.x) counters[i] = 0u;
+    for (int pair = threadIdx.x; pair < B; pair += blockDim.x) {
+        if (done[pair]) continue;
+        double s = 0.0;
+        for (int i = 0; i < npart; ++i) s += partials[pair * npart + i];
+        const double fn = Fn2[pair];
+        double rel;
+        int stop;
+        if (fn == 0.0) { rel = 0.0; stop = 1; }
+        else {
+            rel = sqrt(s) / sqrt(fn);
+            stop = !isfinite(rel) || rel <= rtol || sweep >= max_sweeps;
+        }
+        relres[pair] = rel;
+        sweeps[pair] = sweep;
+        if (stop) done[pair] = 1;
+    }
+}
+
+// --- residual error indicator (Section 3.3) -------------------------------
+//
+// eta_K = alpha_K^{-1/2} h_K |grad f| (int_K (s + f_t)^2)^{1/2}
+//       + 1/2 sum_e alpha_e^{-1/2} h_e |[alpha grad u . n_e]|,
+// s = f_x u1 + f_y u2 - f m, flow components only, alpha_e = max over the two
+// elements of e (own alpha on the image border, outside flux 0).
+// The degree-4 element integral uses the 6-point rule with points
+// (a, a, 1-2a) for a = a1, a2 and weights w1, w2 (sum of weights 1, exact to
+// degree 4, all weights positive), so the integral is a sum of squares.
+
+__device__ __forceinline__ void flux_grad(int t, const double u[3], double& dx, double& dy) {
+    if (t == 0) { dx = u[1] - u[0]; dy = u[2] - u[1]; }
+    else        { dx = u[1] - u[2]; dy = u[2] - u[0]; }
+}
+
+__device__ void elem_flux(const double* __restrict__ Up, int64_t nn, int W, int cx, int cy, int t,
+                          double al, double flux[2][2]) {
+    for (int c = 0; c < 2; ++c) {
+        double u[3];
+        for (int v = 0; v < 3; ++v) u[v] = Up[c * nn + (int64_t)(cy + vdy(t, v)) * W + cx + vdx(t, v)];
+        double gx, gy;
+        flux_grad(t, u, gx, gy);
+        flux[c][0] = al * gx;
+        flux[c][1] = al * gy;
+    }
+}
+
+__global__ void k_indicator(const double* __restrict__ f0, const double* __restrict__ ft,
+                            const double* __restrict__ al, const double* __restrict__ U,
+                            double* __restrict__ eta, uint64_t* __restrict__ etamax_bits, int W, int H) {
+    const int pair = blockIdx.y;
+    const int64_t nn = (int64_t)W * H, ne = (int64_t)(W - 1) * (H - 1) * 2;
+    const int64_t e_id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e_id >= ne) return;
+    const int t = (int)(e_id & 1);
+    const int cell = (int)(e_id >> 1);
+    const int cx = cell % (W - 1), cy = cell / (W - 1);
+    const double* fp = f0 + pair * nn;
+    const double* tp = ft + pair * nn;
+    const double* ap = al + pair * ne;
+    const double* Up = U + pair * 3 * nn;
+    Elem e = load_elem(fp, ap, W, H, cx, cy, t);
+    double ftv[3], uv[3][3];
+    for (int v = 0; v < 3; ++v) {
+        const int64_t n = (int64_t)(cy + vdy(t, v)) * W + cx + vdx(t, v);
+        ftv[v] = tp[n];
+        for (int c = 0; c < 3; ++c) uv[v][c] = Up[c * nn + n];
+    }
+    // element residual: int_K (s + f_t)^2, |K| = 1/2
+    const double qa[2] = {0.44594849091596489, 0.091576213509770743};
+    const double qw[2] = {0.22338158967801147, 0.10995174365532187};
+    double quad = 0.0;
+    for (int g = 0; g < 2; ++g) {
+        const double a = qa[g], b = 1.0 - 2.0 * a;
+        for (int p = 0; p < 3; ++p) {
+            double l[3] = {a, a, a};
+            l[p] = b;
+            double f = 0.0, ftq = 0.0, u1 = 0.0, u2 = 0.0, m = 0.0;
+            for (int v = 0; v < 3; ++v) {
+                f = fma(l[v], e.f[v], f);
+                ftq = fma(l[v], ftv[v], ftq);
+                u1 = fma(l[v], uv[v][0], u1);
+                u2 = fma(l[v], uv[v][1], u2);
+                m = fma(l[v], uv[v][2], m);
+            }
+            const double val = e.gx * u1 + e.gy * u2 - f * m + ftq;
+            quad = fma(qw[g] * val, val, quad);
+        }
+    }
+    quad *= 0.5;
+    const double sq2 = 1.4142135623730951;
+    double res = sq2 * sqrt((e.gx * e.gx + e.gy * e.gy) * quad) / sqrt(e.al);
+    // flux jumps over the three edges
+    double fin[2][2];
+    elem_flux(Up, nn, W, cx, cy, t, e.al, fin);
+    for (int k = 0; k < 3; ++k) {
+        // neighbour cell / type and unit normal of edge k
+        int ncx, ncy, nt;
+        double nx, ny, he;
+        if (t == 0) {
+            if (k == 0)      { ncx = cx;     ncy = cy - 1; nt = 1; nx = 0.0;  ny = -1.0; he = 1.0; }  // bottom
+            else if (k == 1) { ncx = cx + 1; ncy = cy;     nt = 1; nx = 1.0;  ny = 0.0;  he = 1.0; }  // right
+            else             { ncx = cx;     ncy = cy;     nt = 1; nx = -0.70710678118654752; ny = 0.70710678118654752; he = sq2; }
+        } else {
+            if (k == 0)      { ncx = cx;     ncy = cy + 1; nt = 0; nx = 0.0;  ny = 1.0;  he = 1.0; }  // top
+            else if (k == 1) { ncx = cx - 1; ncy = cy;     nt = 0; nx = -1.0; ny = 0.0;  he = 1.0; }  // left
+            else             { ncx = cx;     ncy = cy;     nt = 0; nx = 0.70710678118654752; ny = -0.70710678118654752; he = sq2; }
+        }
+        double fout[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+        double ae = e.al;
+        if (ncx >= 0 && ncy >= 0 && ncx < W - 1 && ncy < H - 1) {
+            const double an = ap[((int64_t)ncy * (W - 1) + ncx) * 2 + nt];
+            elem_flux(Up, nn, W, ncx, ncy, nt, an, fout);
+            ae = fmax(ae, an);
+        }
+        const double j0 = (fout[0][0] - fin[0][0]) * nx + (fout[0][1] - fin[0][1]) * ny;
+        const double j1 = (fout[1][0] - fin[1][0]) * nx + (fout[1][1] - fin[1][1]) * ny;
+        res += 0.5 * he * sqrt(j0 * j0 + j1 * j1) / sqrt(ae);
+    }
+    eta[pair * ne + e_id] = res;
+    // eta >= 0, so the IEEE bit pattern orders like an unsigned integer
+    atomicMax((unsigned long long*)&etamax_bits[pair], (unsigned long long)__double_as_longlong(res));
+}
+
+__global__ void k_alpha_update(const double* __restrict__ eta, const uint64_t* __restrict__ etamax_bits,
+                               double* __restrict__ al, double* __restrict__ al_out, int64_t ne,
+                               double kappa, double eta_thr, double alpha_th) {
+    const int pair = blockIdx.y;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ne) return;
+    const double mx = __longlong_as_double((long long)etamax_bits[pair]);
+    const double a = al[pair * ne + i];
+    double an = a;
+    if (mx > 0.0) {
+        const double rel = eta[pair * ne + i] / mx;
+        an = fmax(a / (1.0 + kappa * fmax(rel - eta_thr, 0.0)), alpha_th);
+    }
+    al[pair * ne + i] = an;
+    al_out[pair * ne + i] = an;
+}
+
+__global__ void k_zero_u64(uint64_t* p, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0ull;
+}
+
+// ---- launchers -----------------------------------------------------------
+
+#define SF_LAUNCH_CHECK()                                   \
+    do {                                                    \
+        if (hipGetLastError() != hipSuccess) return SF_ERR_HIP; \
+    } while (0)
+
+int launch_validate(sf_context* c, const double* I0, const double* I1, const double* alpha) {
+    const int64_t nn = (int64_t)c->W * c->H * c->B;
+    const int64_t ne = (int64_t)(c->W - 1) * (c->H - 1) * 2 * c->B;
+    int blocks = (int)std::min<int64_t>((std::max(nn, ne) + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_validate, dim3(blocks), dim3(256), 0, c->stream, I0, I1, alpha, nn, ne, c->flags_d);
+    SF_LAUNCH_CHECK();
+    return SF_OK;
+}
+
+int launch_assemble(sf_context* c, const double* I0, const double* I1, const double* alpha) {
+    const int64_t nn = (int64_t)c->W * c->H;
+    dim3 grid((unsigned)((nn + NODE_THREADS - 1) / NODE_THREADS), c->B);
+    hipLaunchKernelGGL(k_assemble, grid, dim3(NODE_THREADS), 0, c->stream, I0, I1, alpha, c->f0, c->ft,
+                       c->alpha, c->F, c->partials, c->npart, c->W, c->H);
+    SF_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_finalize_norm, dim3(c->B), dim3(64), 0, c->stream, c->partials, c->npart, c->Fn2);
+    SF_LAUNCH_CHECK();
+    return SF_OK;
+}
+
+int launch_residual(sf_context* c, const double* U, double* r, int fuse_converge, double rtol, int sweep,
+                    int max_sweeps) {
+    const int64_t nn = (int64_t)c->W * c->H;
+    dim3 grid((unsigned)((nn + NODE_THREADS - 1) / NODE_THREADS), c->B);
+    hipLaunchKernelGGL(k_residual, grid, dim3(NODE_THREADS), 0, c->stream, c->f0, c->alpha, c->F, U, r,
+                       c->partials, c->npart, c->W, c->H, c->cfg.lambda,
+                       fuse_converge ? (const int32_t*)c->done_d : (const int32_t*)nullptr);
+    SF_LAUNCH_CHECK();
+    if (fuse_converge) {
+        hipLaunchKernelGGL(k_converge, dim3(1), dim3(256), 0, c->stream, c->partials, c->npart, c->Fn2,
+                           c->relres_d, c->sweeps_d, c->done_d, c->B, rtol, sweep, max_sweeps,
+                           c->counters, c->nsub);
+    } else {
+        hipLaunchKernelGGL(k_finalize_norm, dim3(c->B), dim3(64), 0, c->stream, c->partials, c->npart,
+                           c->relres_d);
+    }
+    SF_LAUNCH_CHECK();
+    return SF_OK;
+}
+
+int launch_indicator(sf_context* c, const double* U, double* eta, int reset_max) {
+    const int64_t ne = (int64_t)(c->W - 1) * (c->H - 1) * 2;
+    if (reset_max) {
+        hipLaunchKernelGGL(k_zero_u64, dim3((c->B + 255) / 256), dim3(256), 0, c->stream, c->etamax_bits, c->B);
+        SF_LAUNCH_CHECK();
+    }
+    dim3 grid((unsigned)((ne + 255) / 256), c->B);
+    hipLaunchKernelGGL(k_indicator, grid, dim3(256), 0, c->stream, c->f0, c->ft, c->alpha, U, eta,
+                       c->etamax_bits, c->W, c->H);
+    SF_LAUNCH_CHECK();
+    return SF_OK;
+}
+
+int launch_alpha_update(sf_context* c, const double* eta, double* alpha_out, double kappa, double eta_thr,
+                        double alpha_th) {
+    const int64_t ne = (int64_t)(c->W - 1) * (c->H - 1) * 2;
+    dim3 grid((unsigned)((ne + 255) / 256), c->B);
+    hipLaunchKernelGGL(k_alpha_update, grid, dim3(256), 0, c->stream, eta, c->etamax_bits, c->alpha, alpha_out,
+                       ne, kappa, eta_thr, alpha_th);
+    SF_LAUNCH_CHECK();
+    return SF_OK;
+}
+
+}  // namespace sfdd

@@ -1,0 +1,114 @@
+// Internal types of the sfdd library (host and device).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+#include "sfdd.h"
+
+namespace sfdd {
+
+constexpr int TS = 32;          // factor tile edge (doubles)
+constexpr int TSZ = TS * TS;    // doubles per tile
+constexpr int SOLVE_THREADS = 256;
+constexpr int FACTOR_THREADS = 256;
+
+// One subdomain: a box of the pixel grid cut into lines along its shorter side.
+//   lines are columns (cols = 1): line t = x - bx0, position s = y - by0
+//   lines are rows    (cols = 0): line t = y - by0, position s = x - bx0
+// Local unknown 3*(t*ms + s) + c.  Line matrices are m x m (m = 3*ms),
+// padded to mp = NT*TS for the tiled factor storage.
+struct SubDesc {
+    int32_t pair;
+    int32_t bx0, by0, bw, bh;          // box origin and size (nodes)
+    int32_t ox0, ox1, oy0, oy1;        // owned nodes, half-open global ranges
+    int32_t cols;                      // 1: lines are columns
+    int32_t ms, nt;                    // nodes per line, number of lines
+    int32_t m, mp, NT, ntiles;         // line size, padded, tiles per side, tiles per line
+    int32_t P;                         // workgroups in a sweep
+    int32_t pad_;
+    int64_t foff;   // inverse Schur tiles: nt * ntiles * TSZ doubles
+    int64_t boff;   // line couplings B_t: nt * m * 6 doubles (t = 0 unused)
+    int64_t woff;   // sweep scratch: nt * mp doubles (forward results w_t)
+    int64_t soff;   // factor workspace: 3 * mp * mp doubles
+    int64_t poff;   // sweep partial vectors: 2 * P * mp doubles
+};
+
+// Global node coordinates of local node (t, s).
+__host__ __device__ inline void local_to_global(const SubDesc& d, int t, int s, int& x, int& y) {
+    if (d.cols) { x = d.bx0 + t; y = d.by0 + s; }
+    else        { x = d.bx0 + s; y = d.by0 + t; }
+}
+
+// Device-side status word (first error wins).
+struct DevStatus {
+    int32_t code;
+    int32_t sub;
+    int64_t row;
+};
+
+}  // namespace sfdd
+
+struct sf_context {
+    sf_config cfg;
+    hipStream_t stream;
+    int device;
+    int W, H, B;
+    int nsub;                       // over all pairs
+    int state;                      // 0 created, 1 assembled, 2 factored
+    std::vector<sfdd::SubDesc> subs;
+    sfdd::SubDesc* d_subs;
+    int32_t* d_wgmap;               // [2][nsub*maxP] workgroup -> (sub << 8 | rank):
+                                    // sweep launch order, then subdomain-major order
+    int sweep_grid;
+    int maxP;
+    // per-pair field data
+    double *f0, *ft, *alpha;        // [B][H][W], [B][H][W], [B][H-1][W-1][2]
+    double *F, *r;                  // [B][3][H][W]
+    double *eta;                    // [B][H-1][W-1][2] indicator scratch
+    double *Fn2;                    // [B] ||F||^2
+    double *partials;               // reduction scratch
+    int npart;                      // partial blocks per pair for node reductions
+    double *relres_d;               // [B]
+    int32_t *sweeps_d;              // [B]
+    int32_t *done_d;                // [B]
+    uint32_t *counters;             // [nsub] sweep synchronisation
+    uint64_t *etamax_bits;          // [B]
+    int32_t *flags_d;               // [4] input validation flags
+    // subdomain storage
+    double *factors;                // all subdomains' tiles and couplings
+    double *work;                   // factor workspaces + sweep scratch
+    int64_t factor_doubles, work_doubles;
+    sfdd::DevStatus *status_d;
+    sfdd::DevStatus status_h;       // last error detail
+    // host staging (pinned)
+    void *host_stage;
+    // optional per-kernel timing (sf_profile): event pairs around launches
+    int profiling;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<int> ev_kind;       // kernel class of each pending pair
+    int ev_used;
+    double prof_ms[4];
+    int64_t prof_n[4];
+};
+
+// kernel launchers (fem.hip, factor.hip, solve.hip)
+namespace sfdd {
+int launch_validate(sf_context* c, const double* I0, const double* I1, const double* alpha);
+int launch_assemble(sf_context* c, const double* I0, const double* I1, const double* alpha);
+int launch_residual(sf_context* c, const double* U, double* r, int fuse_converge, double rtol,
+                    int sweep, int max_sweeps);
+int launch_indicator(sf_context* c, const double* U, double* eta, int reset_max);
+int launch_alpha_update(sf_context* c, const double* eta, double* alpha_out, double kappa,
+                        double eta_thr, double alpha_th);
+int launch_factor(sf_context* c);
+int launch_sweep(sf_context* c, double* U, const double* r, int single_sub, const double* b_local,
+                 double* x_local);
+const void* sweep_kernel();
+// timing helpers (api.hip): bracket a launch of kernel class `kind`
+int prof_begin(sf_context* c, int kind);
+int prof_end(sf_context* c);
+int prof_harvest(sf_context* c);
+enum { PROF_SWEEP = 0, PROF_FACTOR = 1, PROF_RESIDUAL = 2, PROF_OTHER = 3 };
+}  // namespace sfdd

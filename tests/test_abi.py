@@ -1,0 +1,62 @@
+"""The C-ABI library: it loads, exports every declared entry point, and its
+host-side geometry matches the oracle's decomposition (no GPU needed)."""
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+from oracle import schwarz
+from paper_1508_02977_amd import api
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _ensure_built():
+    if not os.path.exists(api.LIB_PATH):
+        from paper_1508_02977_amd import build
+        build.build()
+
+
+def test_header_symbols_exported():
+    _ensure_built()
+    hdr = open(os.path.join(ROOT, "include", "sfdd.h")).read()
+    declared = set(re.findall(r"^\s*(?:int|void|const char\*)\s+(sf_\w+)\s*\(", hdr, re.M))
+    assert len(declared) >= 15
+    out = subprocess.run(["nm", "-D", "--defined-only", api.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r"\bT\s+(sf_\w+)", out))
+    assert declared <= exported, declared - exported
+    assert declared == set(api.exported_symbols())
+    L = api.lib()
+    for name in declared:
+        assert getattr(L, name) is not None
+
+
+def test_status_strings():
+    _ensure_built()
+    for code in (0, -1, -2, -3, -4, -5, 1, 2, 3):
+        assert api.sf_status_string(code) not in ("unknown status", "")
+
+
+@pytest.mark.parametrize("W,H,px,py,d", [(64, 64, 2, 2, 4), (640, 480, 4, 4, 8), (37, 29, 3, 2, 5),
+                                         (23, 41, 2, 3, 6), (50, 9, 5, 1, 3), (1920, 1080, 12, 7, 8)])
+def test_plan_matches_oracle_decomposition(W, H, px, py, d):
+    _ensure_built()
+    plan = api.sf_plan(W, H, 1, px, py, d)
+    subs = schwarz.decompose(W, H, px, py, d)
+    assert len(plan) == len(subs)
+    for g, s in zip(plan, subs):
+        assert g["box"] == (s.box[0], s.box[1], s.box[2], s.box[3])
+        assert g["own"] == s.own
+        assert g["cols"] == s.cols
+
+
+def test_plan_batch_and_invalid():
+    _ensure_built()
+    plan = api.sf_plan(20, 10, 3, 2, 1, 2)
+    assert [g["pair"] for g in plan] == [0, 0, 1, 1, 2, 2]
+    with pytest.raises(api.SfError):
+        api.sf_plan(1, 10, 1, 1, 1, 0)
+    with pytest.raises(api.SfError):
+        api.sf_plan(10, 10, 1, 11, 1, 0)
