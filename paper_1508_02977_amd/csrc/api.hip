@@ -200,10 +200,10 @@ int sf_create(const sf_config* cfg, void* stream, sf_context** out) {
 
     // ---- geometry (Section 4.1) --------------------------------------------
     c->subs = plan_subdomains(k);
-    int maxmp = 0, min_tiles = 1 << 30;
+    int maxmp = 0, min_nt = 1 << 30;
     for (const auto& d : c->subs) {
         maxmp = std::max(maxmp, d.mp);
-        min_tiles = std::min(min_tiles, d.ntiles);
+        min_nt = std::min(min_nt, d.NT);
     }
     if (maxmp > 512) { sf_destroy(c); return SF_ERR_INVALID; }   // line matrices up to 512 x 512
     c->nsub = (int)c->subs.size();
@@ -218,8 +218,9 @@ int sf_create(const sf_config* cfg, void* stream, sf_context** out) {
             hipSuccess || occ < 1)
         occ = 1;
     const int capacity = ncu * occ;
-    int P = k.band_tile > 0 ? k.band_tile : std::max(1, std::min(capacity / c->nsub, min_tiles / 2));
-    P = std::min(P, min_tiles);
+    // one rank per 32-row block row of the line matrices when the chip has room
+    int P = k.band_tile > 0 ? k.band_tile : std::max(1, std::min(capacity / c->nsub, min_nt));
+    P = std::min(P, min_nt);
     P = std::min(P, 255);
     if ((int64_t)P * c->nsub > capacity) P = std::max(1, capacity / c->nsub);
     c->maxP = P;
@@ -236,7 +237,7 @@ int sf_create(const sf_config* cfg, void* stream, sf_context** out) {
         d.woff = woff;
         woff += (int64_t)d.nt * d.mp;
         d.poff = woff;
-        woff += (int64_t)2 * P * d.mp;
+        woff += (int64_t)2 * d.mp;
         d.soff = woff;
         woff += (int64_t)3 * d.mp * d.mp;
     }

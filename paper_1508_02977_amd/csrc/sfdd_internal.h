@@ -11,7 +11,7 @@ namespace sfdd {
 
 constexpr int TS = 32;          // factor tile edge (doubles)
 constexpr int TSZ = TS * TS;    // doubles per tile
-constexpr int SOLVE_THREADS = 256;
+constexpr int SOLVE_THREADS = 512;
 constexpr int FACTOR_THREADS = 256;
 
 // One subdomain: a box of the pixel grid cut into lines along its shorter side.
@@ -32,7 +32,7 @@ struct SubDesc {
     int64_t boff;   // line couplings B_t: nt * m * 6 doubles (t = 0 unused)
     int64_t woff;   // sweep scratch: nt * mp doubles (forward results w_t)
     int64_t soff;   // factor workspace: 3 * mp * mp doubles
-    int64_t poff;   // sweep partial vectors: 2 * P * mp doubles
+    int64_t poff;   // sweep published rows: 2 * mp doubles
 };
 
 // Global node coordinates of local node (t, s).

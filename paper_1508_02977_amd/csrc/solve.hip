@@ -8,13 +8,15 @@
 //     backward: x_{nt-1} = w_{nt-1},  x_t = w_t - S_t^{-1} (B_{t+1}^T x_{t+1})
 // i.e. one dense symmetric matrix-vector product per line and direction.
 //
-// Parallel layout: P workgroups cooperate on one subdomain.  Each holds a
-// fixed share of the 32x32 lower tiles of every S_t^{-1} (tile k of a line
-// goes to rank k mod P) and streams them once per direction; an off-diagonal
-// tile contributes T z_J to rows I and T^T z_I to rows J.  Ranks publish
-// partial result vectors and bump a per-subdomain counter; at the next line
-// every rank sums the P partials in rank order (bitwise reproducible).  All
-// waits are bounded: a stalled wait raises SF_ERR_DEVICE and every rank exits.
+// Parallel layout: P workgroups (ranks) cooperate on one subdomain.  Rank p
+// computes the block rows I = p, p+P, ... of every product S_t^{-1} z: the
+// tiles of block row I are the lower tiles (I, J<=I) and, transposed, the
+// tiles (J>I, I) of block column I, so each off-diagonal tile is read by two
+// ranks (the second read is served by L2: all ranks of a subdomain sit on one
+// XCD).  Ranks publish their finished rows and bump a per-subdomain counter;
+// the next line starts when all P rows sets are out.  No reductions across
+// ranks, so results do not depend on P.  All waits are bounded: a stalled
+// wait raises SF_ERR_DEVICE and every rank exits.
 #include "sfdd_internal.h"
 
 namespace sfdd {
@@ -37,12 +39,15 @@ struct SweepArgs {
     long long spin_limit;
 };
 
+// Thread 0 polls the counter with relaxed device-scope loads (they bypass the
+// non-coherent caches); the other waves wait at the barrier.  Bounded: on a
+// stall the wait records SF_ERR_DEVICE and every rank of every subdomain exits.
 __device__ __forceinline__ bool wait_count(uint32_t* cnt, uint32_t target, const SweepArgs& A, int sub,
                                            int* sh_ok) {
     if (threadIdx.x == 0) {
         long long n = 0;
         int ok = 1;
-        while (__hip_atomic_load(cnt, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        while (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
             if (__hip_atomic_load(&A.status->code, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == SF_ERR_DEVICE ||
                 ++n > A.spin_limit) {
                 if (atomicCAS(&A.status->code, 0, SF_ERR_DEVICE) == 0) {
@@ -60,39 +65,51 @@ __device__ __forceinline__ bool wait_count(uint32_t* cnt, uint32_t target, const
     return *sh_ok != 0;
 }
 
+// Every value another rank reads is stored with a relaxed device-scope atomic
+// (written through to the coherence point); waiting for all of them to be
+// acknowledged before the counter increment orders data before flag without
+// a cache-wide writeback.
 __device__ __forceinline__ void signal_count(uint32_t* cnt) {
-    __threadfence();
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    if (threadIdx.x == 0) __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    if (threadIdx.x == 0) __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Contribution of this rank's tiles of one line matrix to y = S^{-1} z.
-// z and the per-wave accumulators yw[4][mp] live in LDS.
-__device__ __forceinline__ void apply_tiles(const double* __restrict__ Tl, int ntiles, int rank, int P,
-                                            const double* z, double (*yw)[MAXMP]) {
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+__device__ __forceinline__ void pub_store(double* p, double v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double pub_load(const double* p) {
+    return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Rows I*32 .. I*32+31 of y = S z for the symmetric line matrix S stored as
+// its lower 32x32 tiles (tile (I,J), I >= J, at index I(I+1)/2 + J):
+//   y_I = sum_{J <= I} T(I,J) z_J + sum_{J > I} T(J,I)^T z_J.
+// A wave takes tiles j0, j0+nwaves, ... of the NT tiles of the block row and
+// accumulates into its own LDS row buffer yw[32].
+__device__ __forceinline__ void block_row(const double* __restrict__ Tl, int NT, int I, const double* z,
+                                          double* yw, int wv, int nwaves) {
+    const int lane = threadIdx.x & 63;
     const int j = lane & 31, h = lane >> 5;
-    double* y = yw[wv];
-    int idx = 0;
-    for (int k = rank; k < ntiles; k += P, ++idx) {
-        if ((idx & 3) != wv) continue;
-        int I = 0;
-        while ((I + 1) * (I + 2) / 2 <= k) ++I;
-        const int J = k - I * (I + 1) / 2;
+    for (int J = wv; J < NT; J += nwaves) {
+        const bool lower = J <= I;
+        const int k = lower ? I * (I + 1) / 2 + J : J * (J + 1) / 2 + I;
         const double* T = Tl + (int64_t)k * TSZ + (16 * h) * TS + j;
         double tv[16];
 #pragma unroll
         for (int i = 0; i < 16; ++i) tv[i] = T[i * TS];
-        // y_J += T^T z_I  (for a diagonal tile this is the whole product)
-        const double* zI = z + I * TS + 16 * h;
-        double s = 0.0;
+        if (!lower || J == I) {
+            // y_I[j] += sum_r T[r][j] zJ[r]: T = T(J,I) (transposed use) or the
+            // symmetric diagonal tile; rows r of this lane are 16h..16h+15
+            const double* zr = z + J * TS + 16 * h;
+            double s = 0.0;
 #pragma unroll
-        for (int i = 0; i < 16; ++i) s = fma(tv[i], zI[i], s);
-        s += __shfl_xor(s, 32, 64);
-        if (h == 0) y[J * TS + j] += s;
-        if (I != J) {
-            // y_I += T z_J: per lane 16 row products, reduced over the 32 lanes of
-            // the half by a transpose-reduce butterfly (xor 16, 8, 4, 2, then 1).
+            for (int i = 0; i < 16; ++i) s = fma(tv[i], zr[i], s);
+            s += __shfl_xor(s, 32, 64);
+            if (h == 0) yw[j] += s;
+        } else {
+            // y_I[r] += sum_j T[r][j] zJ[j]: 16 row products per lane reduced over
+            // the 32 lanes of the half (transpose-reduce: xor 16, 8, 4, 2, then 1)
             const double zj = z[J * TS + j];
             double p[16];
 #pragma unroll
@@ -118,33 +135,30 @@ __device__ __forceinline__ void apply_tiles(const double* __restrict__ Tl, int n
                 p[0] = keep + __shfl_xor(send, 2, 64);
             }
             p[0] += __shfl_xor(p[0], 1, 64);
-            if ((j & 1) == 0) {
-                const int row = 8 * b4 + 4 * b3 + 2 * b2 + b1;
-                y[I * TS + 16 * h + row] += p[0];
-            }
+            if ((j & 1) == 0) yw[16 * h + 8 * b4 + 4 * b3 + 2 * b2 + b1] += p[0];
         }
     }
 }
 
 __global__ void __launch_bounds__(SOLVE_THREADS) k_sweep(SweepArgs A) {
+    constexpr int NW = SOLVE_THREADS / 64;
     __shared__ double z[MAXMP];
     __shared__ double full[MAXMP];
-    __shared__ double yw[4][MAXMP];
+    __shared__ double yw[NW][TS];
     __shared__ int sh_ok;
 
     const int code = A.wgmap[blockIdx.x];
     const int sub = code >> 8, rank = code & 255;
     const SubDesc d = A.subs[sub];
     if (A.mode == 0 && A.done[d.pair]) return;   // uniform over the subdomain's ranks
-    const int tid = threadIdx.x;
-    const int P = d.P, m = d.m, mp = d.mp, ms = d.ms, nt = d.nt, ntiles = d.ntiles;
+    const int tid = threadIdx.x, wv = tid >> 6;
+    const int P = d.P, m = d.m, mp = d.mp, ms = d.ms, nt = d.nt, ntiles = d.ntiles, NT = d.NT;
     const int64_t nn = (int64_t)A.W * A.H;
     const double* Tb = A.factors + d.foff;
     const double* Bb = A.factors + d.boff;
-    double* wst = A.work + d.woff;
-    double* part = A.work + d.poff;          // [2][P][mp]
+    double* wst = A.work + d.woff;           // forward results of this rank's rows
+    double* pub = A.work + d.poff;           // [2][mp] published rows (double-buffered)
     uint32_t* cnt = A.counters + sub;
-    const int sl0 = (rank * mp) / P, sl1 = ((rank + 1) * mp) / P;   // this rank's slice
 
     auto rhs = [&](int t, int a) -> double {
         if (A.mode == 1) return A.b_local[(int64_t)t * m + a];
@@ -159,33 +173,32 @@ __global__ void __launch_bounds__(SOLVE_THREADS) k_sweep(SweepArgs A) {
         if (x >= d.ox0 && x < d.ox1 && y >= d.oy0 && y < d.oy1)
             A.U[((int64_t)d.pair * 3 + a % 3) * nn + (int64_t)y * A.W + x] += v;
     };
-    // full <- base - sum_q part[buf][q]  (base may be null: +sum)
-    auto gather = [&](int buf, const double* base) {
-        const double* pb = part + (int64_t)buf * P * mp;
-        for (int a = tid; a < mp; a += SOLVE_THREADS) {
-            double s = 0.0;
-            for (int q = 0; q < P; ++q) s += pb[(int64_t)q * mp + a];
-            full[a] = base ? base[a] - s : s;
-        }
-    };
-    auto publish = [&](int buf) {
-        double* pb = part + ((int64_t)buf * P + rank) * mp;
-        for (int a = tid; a < mp; a += SOLVE_THREADS) pb[a] = yw[0][a] + yw[1][a] + yw[2][a] + yw[3][a];
-    };
-    auto clear_y = [&]() {
-        for (int a = tid; a < mp; a += SOLVE_THREADS) {
-            yw[0][a] = 0.0; yw[1][a] = 0.0; yw[2][a] = 0.0; yw[3][a] = 0.0;
+    // This rank's block rows I = rank, rank + P, ...: y = S_t z for those rows,
+    // then finish(I, row, y) for each row.
+    auto rows = [&](int t, auto&& finish) {
+        const double* Tl = Tb + (int64_t)t * ntiles * TSZ;
+        for (int I = rank; I < NT; I += P) {
+            for (int i = tid; i < NW * TS; i += SOLVE_THREADS) (&yw[0][0])[i] = 0.0;
+            __syncthreads();
+            block_row(Tl, NT, I, z, yw[wv], wv, NW);
+            __syncthreads();
+            if (tid < TS) {
+                double y = 0.0;
+                for (int w = 0; w < NW; ++w) y += yw[w][tid];
+                finish(I * TS + tid, y);
+            }
+            __syncthreads();
         }
     };
 
     uint32_t phase = 0;
-    // ---------------- forward ----------------
+    // ---------------- forward: w_t = S_t^{-1} (r_t - B_t w_{t-1}) ----------------
     for (int t = 0; t < nt; ++t, ++phase) {
         if (t > 0) {
             if (!wait_count(cnt, P * phase, A, sub, &sh_ok)) return;
-            gather((phase - 1) & 1, nullptr);          // full = w_{t-1}
+            const double* pb = pub + (int64_t)((phase - 1) & 1) * mp;
+            for (int a = tid; a < mp; a += SOLVE_THREADS) full[a] = pub_load(pb + a);
             __syncthreads();
-            for (int a = sl0 + tid; a < sl1; a += SOLVE_THREADS) wst[(int64_t)(t - 1) * mp + a] = full[a];
         }
         const double* Bt = Bb + (int64_t)t * m * 6;
         for (int a = tid; a < mp; a += SOLVE_THREADS) {
@@ -204,22 +217,21 @@ __global__ void __launch_bounds__(SOLVE_THREADS) k_sweep(SweepArgs A) {
             }
             z[a] = v;
         }
-        clear_y();
         __syncthreads();
-        apply_tiles(Tb + (int64_t)t * ntiles * TSZ, ntiles, rank, P, z, yw);
-        __syncthreads();
-        publish(phase & 1);
+        double* pw = pub + (int64_t)(phase & 1) * mp;
+        rows(t, [&](int a, double y) {
+            pub_store(pw + a, y);
+            wst[(int64_t)t * mp + a] = y;
+            if (t == nt - 1 && a < m) emit(t, a, y);      // x_{nt-1} = w_{nt-1}
+        });
         signal_count(cnt);
     }
-    // ---------------- backward ----------------
+    // ---------------- backward: x_t = w_t - S_t^{-1} B_{t+1}^T x_{t+1} ----------------
     for (int t = nt - 2; t >= 0; --t, ++phase) {
         if (!wait_count(cnt, P * phase, A, sub, &sh_ok)) return;
-        // full = x_{t+1}
-        gather((phase - 1) & 1, (t + 1 == nt - 1) ? nullptr : wst + (int64_t)(t + 1) * mp);
+        const double* pb = pub + (int64_t)((phase - 1) & 1) * mp;
+        for (int a = tid; a < mp; a += SOLVE_THREADS) full[a] = pub_load(pb + a);   // x_{t+1}
         __syncthreads();
-        for (int a = sl0 + tid; a < sl1; a += SOLVE_THREADS)
-            if (a < m) emit(t + 1, a, full[a]);
-        // z = B_{t+1}^T x_{t+1}
         const double* Bt = Bb + (int64_t)(t + 1) * m * 6;
         for (int b = tid; b < mp; b += SOLVE_THREADS) {
             double v = 0.0;
@@ -232,19 +244,15 @@ __global__ void __launch_bounds__(SOLVE_THREADS) k_sweep(SweepArgs A) {
             }
             z[b] = v;
         }
-        clear_y();
         __syncthreads();
-        apply_tiles(Tb + (int64_t)t * ntiles * TSZ, ntiles, rank, P, z, yw);
-        __syncthreads();
-        publish(phase & 1);
+        double* pw = pub + (int64_t)(phase & 1) * mp;
+        rows(t, [&](int a, double y) {
+            const double x = wst[(int64_t)t * mp + a] - y;
+            pub_store(pw + a, x);
+            if (a < m) emit(t, a, x);
+        });
         signal_count(cnt);
     }
-    // x_0
-    if (!wait_count(cnt, P * phase, A, sub, &sh_ok)) return;
-    gather((phase - 1) & 1, nt == 1 ? nullptr : wst);
-    __syncthreads();
-    for (int a = sl0 + tid; a < sl1; a += SOLVE_THREADS)
-        if (a < m) emit(0, a, full[a]);
 }
 
 __global__ void k_zero_u32(uint32_t* p, int n) {
