@@ -173,7 +173,7 @@ const char* sf_status_string(int s) {
 
 void sf_destroy(sf_context* c) {
     if (!c) return;
-    void* ptrs[] = {c->d_subs, c->d_wgmap, c->f0, c->ft, c->alpha, c->F, c->r, c->eta, c->Fn2,
+    void* ptrs[] = {c->d_subs, c->d_wgmap, c->d_fmap, c->f0, c->ft, c->alpha, c->F, c->r, c->eta, c->Fn2,
                     c->partials, c->relres_d, c->sweeps_d, c->done_d, c->counters, c->etamax_bits,
                     c->flags_d, c->factors, c->work, c->status_d};
     for (void* p : ptrs)
@@ -226,6 +226,21 @@ int sf_create(const sf_config* cfg, void* stream, sf_context** out) {
     c->maxP = P;
     c->sweep_grid = P * c->nsub;
 
+    // cooperative factor: ceil(NT/2) workgroups per subdomain, line matrices up to 384
+    int maxnt = 0;
+    for (const auto& d : c->subs) maxnt = std::max(maxnt, d.NT);
+    int occ2 = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ2, sfdd::factor2_kernel(), 512, 0) != hipSuccess)
+        occ2 = 0;
+    const int Pf = (maxnt + 1) / 2;
+    if (maxnt <= 12 && occ2 >= 1 && Pf <= ncu * occ2) {
+        c->factor_pf = Pf;
+        c->factor_chunk = std::max(1, std::min(c->nsub, (ncu * occ2) / Pf));
+    } else {
+        c->factor_pf = 0;
+        c->factor_chunk = 0;
+    }
+
     // ---- storage offsets -----------------------------------------------------
     int64_t foff = 0, woff = 0;
     for (auto& d : c->subs) {
@@ -234,12 +249,14 @@ int sf_create(const sf_config* cfg, void* stream, sf_context** out) {
         foff += (int64_t)d.nt * d.ntiles * sfdd::TSZ;
         d.boff = foff;
         foff += (int64_t)d.nt * d.m * 6;
+        d.aoff = foff;
+        foff += (int64_t)d.nt * d.ms * 18;
         d.woff = woff;
         woff += (int64_t)d.nt * d.mp;
         d.poff = woff;
         woff += (int64_t)2 * d.mp;
-        d.soff = woff;
-        woff += (int64_t)3 * d.mp * d.mp;
+        d.soff = woff;   // factor workspace (one-WG factor: 3 mp^2; cooperative: 2 mp^2 + exchange slots)
+        woff += std::max<int64_t>((int64_t)3 * d.mp * d.mp, (int64_t)2 * d.mp * d.mp + 2ll * d.NT * sfdd::TSZ);
     }
     c->factor_doubles = foff;
     c->work_doubles = woff;
@@ -247,6 +264,11 @@ int sf_create(const sf_config* cfg, void* stream, sf_context** out) {
     // workgroup map: XCD-aware when the subdomains split evenly over the
     // 8 XCDs (workgroup g runs on XCD g % 8): all ranks of a subdomain then
     // share one L2.  Second half: subdomain-major order.
+    std::vector<int32_t> fmap((size_t)c->nsub * std::max(1, c->factor_pf));
+    for (size_t g = 0; g < fmap.size(); ++g) {
+        const int pf = std::max(1, c->factor_pf);
+        fmap[g] = (int32_t)(((g / pf) << 8) | (g % pf));
+    }
     std::vector<int32_t> map(2 * (size_t)c->sweep_grid);
     const int G = c->sweep_grid;
     for (int g = 0; g < G; ++g) map[G + g] = ((g / P) << 8) | (g % P);
@@ -265,6 +287,7 @@ int sf_create(const sf_config* cfg, void* stream, sf_context** out) {
     int rc = SF_OK;
     rc |= dalloc(&c->d_subs, c->subs.size());
     rc |= dalloc(&c->d_wgmap, map.size());
+    rc |= dalloc(&c->d_fmap, fmap.size());
     rc |= dalloc(&c->f0, nn * c->B);
     rc |= dalloc(&c->ft, nn * c->B);
     rc |= dalloc(&c->alpha, ne * c->B);
@@ -291,7 +314,8 @@ int sf_create(const sf_config* cfg, void* stream, sf_context** out) {
     }
     if (hipMemcpy(c->d_subs, c->subs.data(), c->subs.size() * sizeof(SubDesc), hipMemcpyHostToDevice) !=
             hipSuccess ||
-        hipMemcpy(c->d_wgmap, map.data(), map.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess) {
+        hipMemcpy(c->d_wgmap, map.data(), map.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(c->d_fmap, fmap.data(), fmap.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess) {
         sf_destroy(c);
         return SF_ERR_HIP;
     }
@@ -324,7 +348,20 @@ int sf_factor_subdomains(sf_context* c) {
     if (!c) return SF_ERR_INVALID;
     if (c->state < ST_ASSEMBLED) return SF_ERR_STATE;
     SF_TRY(sfdd::prof_begin(c, sfdd::PROF_FACTOR));
-    SF_TRY(sfdd::launch_factor(c));
+    if (c->factor_pf > 0) {
+        SF_TRY(sfdd::launch_line_coeffs(c));
+        hipLaunchKernelGGL(k_zero_status_api, dim3(1), dim3(1), 0, c->stream, c->status_d);
+        SF_HIP(hipGetLastError());
+        for (int s0 = 0; s0 < c->nsub; s0 += c->factor_chunk) {
+            const int n = std::min(c->factor_chunk, c->nsub - s0);
+            hipLaunchKernelGGL(k_fill_i32, dim3((c->nsub + 255) / 256), dim3(256), 0, c->stream,
+                               (int32_t*)c->counters, c->nsub, 0);
+            SF_HIP(hipGetLastError());
+            SF_TRY(sfdd::launch_factor2(c, s0, n, c->factor_pf));
+        }
+    } else {
+        SF_TRY(sfdd::launch_factor(c));
+    }
     SF_TRY(sfdd::prof_end(c));
     const int code = pull_status(c);
     SF_TRY(sfdd::prof_harvest(c));

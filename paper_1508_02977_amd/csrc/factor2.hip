@@ -1,0 +1,480 @@
+// Subdomain factorisation, cooperative form: Pf workgroups per subdomain.
+//
+// Same factor as factor.hip (paper, Section 4.2, local direct solves): for
+// every line t of a subdomain, S_t = A_tt - B_t S_{t-1}^{-1} B_t^T and its
+// inverse, stored as 32x32 lower tiles.  Here the inverse is formed by the
+// blocked symmetric sweep (Gauss-Jordan without pivoting, valid because S_t
+// is SPD): for each 32-column pivot block k,
+//     Pi = S_kk^{-1}
+//     S_ij <- S_ij - S_ik Pi S_kj        (i, j != k)
+//     S_ik <- S_ik Pi,  S_kj <- Pi S_kj,  S_kk <- -Pi
+// and after all NT pivots the matrix holds -S^{-1}.  The pivot blocks are the
+// Schur complements a Cholesky factorisation would meet, so a non-positive
+// pivot inside Pi flags SF_NOT_SPD exactly as before.
+//
+// Work split: rank r owns block rows r and NT-1-r (balanced: NT+1 lower tiles
+// per rank) and keeps its tiles in MFMA accumulators (v_mfma_f64_16x16x4f64,
+// one 16x16 block per accumulator) for the whole line.  Lane layout of that
+// instruction (checked on gfx950): A[i][k] in lane i + 16k, B[k][j] in lane
+// j + 16k, accumulator element q of lane l is D[l/16 + 4q][l%16].  Each pivot step needs
+// block column k of the current matrix: its owners publish it to a global
+// exchange slot (relaxed device-scope stores), bump the subdomain counter,
+// and every rank reads it into LDS.  One exchange per pivot step, NT + 1 per
+// line.  The Schur update of the next line is built from the full symmetric
+// S_{t-1}^{-1} that the ranks leave in global memory at the end of a line.
+#include <algorithm>
+#include <cmath>
+
+#include "element.h"
+#include "sfdd_internal.h"
+
+namespace sfdd {
+
+constexpr int F2_THREADS = 512;
+constexpr int F2_NW = F2_THREADS / 64;
+constexpr int F2_MAXNT = 12;          // line matrices up to 384 x 384
+constexpr int LDP = 34;               // LDS row pitch (doubles): conflict-free 16x4 / 4x16 fragments
+constexpr int LTILE = TS * LDP;       // doubles per LDS tile
+constexpr int F2_MAXBLK = 7;          // accumulator blocks per wave: 4 * (NT + 1) / 8
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+struct FactorArgs {
+    const SubDesc* subs;
+    const int32_t* fmap;      // workgroup -> (sub << 8 | rank)
+    const double* f0;
+    const double* al;
+    double* factors;
+    double* work;
+    uint32_t* counters;
+    DevStatus* status;
+    int W, H;
+    double lam;
+    long long spin_limit;
+};
+
+__device__ void f2_stencil_block(const double* __restrict__ f0, const double* __restrict__ al, int W, int H,
+                                 int x, int y, int dx, int dy, double lam, double blk[9]) {
+    for (int i = 0; i < 9; ++i) blk[i] = 0.0;
+    double b[9];
+    auto add = [&](int cx, int cy, int t, int i, int j) {
+        if (cx < 0 || cy < 0 || cx >= W - 1 || cy >= H - 1) return;
+        Elem e = load_elem(f0, al, W, H, cx, cy, t);
+        elem_block(e, t, i, j, lam, b);
+        for (int k = 0; k < 9; ++k) blk[k] += b[k];
+    };
+    if (dx == 0 && dy == 0) {
+        for (int k = 0; k < 6; ++k) {
+            const Around a = around(k);
+            add(x + a.dcx, y + a.dcy, a.t, a.v, a.v);
+        }
+    } else if (dx == 1 && dy == 0) {
+        add(x, y, 0, 0, 1);
+        add(x, y - 1, 1, 2, 1);
+    } else if (dx == 0 && dy == 1) {
+        add(x, y, 1, 0, 2);
+        add(x - 1, y, 0, 1, 2);
+    } else {
+        add(x, y, 0, 0, 2);
+        add(x, y, 1, 0, 1);
+    }
+}
+
+// Line coefficients of every subdomain, computed once before the
+// factorisation: per line t and node s the 3x3 blocks A[(t,s),(t,s)] and
+// A[(t,s),(t,s+1)] (row-major, 18 doubles at aoff + (t*ms + s)*18) and the
+// coupling rows B_t[3s+c][.] (6 doubles per row, boff + (t*m + 3s+c)*6).
+__global__ void k_line_coeffs(const SubDesc* __restrict__ subs, const double* __restrict__ f0_all,
+                              const double* __restrict__ al_all, double* __restrict__ factors, int W, int H,
+                              double lam, int sub0) {
+    const SubDesc d = subs[sub0 + blockIdx.y];
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)d.nt * d.ms) return;
+    const int t = (int)(idx / d.ms), s = (int)(idx % d.ms);
+    const int64_t nn = (int64_t)W * H, ne = (int64_t)(W - 1) * (H - 1) * 2;
+    const double* f0 = f0_all + d.pair * nn;
+    const double* al = al_all + d.pair * ne;
+    double* Ab = factors + d.aoff + idx * 18;
+    int x, y;
+    local_to_global(d, t, s, x, y);
+    double blk[9];
+    f2_stencil_block(f0, al, W, H, x, y, 0, 0, lam, blk);
+    for (int k = 0; k < 9; ++k) Ab[k] = blk[k];
+    if (s + 1 < d.ms) {
+        if (d.cols) f2_stencil_block(f0, al, W, H, x, y, 0, 1, lam, blk);
+        else        f2_stencil_block(f0, al, W, H, x, y, 1, 0, lam, blk);
+    } else {
+        for (int k = 0; k < 9; ++k) blk[k] = 0.0;
+    }
+    for (int k = 0; k < 9; ++k) Ab[9 + k] = blk[k];
+    if (t > 0) {
+        int px, py;
+        local_to_global(d, t - 1, s, px, py);
+        double bs[9], bd[9];
+        if (d.cols) f2_stencil_block(f0, al, W, H, px, py, 1, 0, lam, bs);
+        else        f2_stencil_block(f0, al, W, H, px, py, 0, 1, lam, bs);
+        if (s > 0) {
+            int qx, qy;
+            local_to_global(d, t - 1, s - 1, qx, qy);
+            f2_stencil_block(f0, al, W, H, qx, qy, 1, 1, lam, bd);
+        } else {
+            for (int k = 0; k < 9; ++k) bd[k] = 0.0;
+        }
+        double* row = factors + d.boff + ((int64_t)t * d.m + 3 * s) * 6;
+        for (int c = 0; c < 3; ++c)
+            for (int e = 0; e < 3; ++e) {
+                row[c * 6 + e] = bd[3 * e + c];        // B[3s+c][3(s-1)+e]
+                row[c * 6 + 3 + e] = bs[3 * e + c];    // B[3s+c][3s+e]
+            }
+    }
+}
+
+__device__ __forceinline__ void xstore(double* p, double v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double xload(const double* p) {
+    return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ bool f2_wait(uint32_t* cnt, uint32_t target, const FactorArgs& A, int sub, int* sh_ok) {
+    if (threadIdx.x == 0) {
+        long long n = 0;
+        int ok = 1;
+        while (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            if (__hip_atomic_load(&A.status->code, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == SF_ERR_DEVICE ||
+                ++n > A.spin_limit) {
+                if (atomicCAS(&A.status->code, 0, SF_ERR_DEVICE) == 0) {
+                    A.status->sub = sub;
+                    A.status->row = (int64_t)target;
+                }
+                ok = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        *sh_ok = ok;
+    }
+    __syncthreads();
+    return *sh_ok != 0;
+}
+
+__device__ __forceinline__ void f2_signal(uint32_t* cnt) {
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x == 0) __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void f2_tile_of(int q, int rowA, int rowB, int& I, int& J) {
+    if (q <= rowA) { I = rowA; J = q; }
+    else           { I = rowB; J = q - rowA - 1; }
+}
+
+// Publish block column `col` of the current matrix (the own blocks in it)
+// into the exchange slots xb[J] = S_{J,col} (32x32 row-major).
+__device__ __forceinline__ void f2_publish(const d4 (&acc)[F2_MAXBLK], double* xb, int col, int nblk, int rowA,
+                                           int rowB, int wv, int cr, int cc) {
+#pragma unroll
+    for (int b = 0; b < F2_MAXBLK; ++b) {
+        const int blk = wv + F2_NW * b;
+        if (blk >= nblk) continue;
+        int I, J;
+        f2_tile_of(blk >> 2, rowA, rowB, I, J);
+        const int qi = (blk >> 1) & 1, qj = blk & 1;
+        if (J == col) {                                  // tile (I, col): slot I as is
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                xstore(xb + (int64_t)I * TSZ + (16 * qi + cr + 4 * q) * TS + 16 * qj + cc, acc[b][q]);
+        } else if (I == col) {                           // tile (col, J), J < col: slot J transposed
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                xstore(xb + (int64_t)J * TSZ + (16 * qj + cc) * TS + 16 * qi + cr + 4 * q, acc[b][q]);
+        }
+    }
+}
+
+__global__ void __launch_bounds__(F2_THREADS) k_factor2(FactorArgs A) {
+    // LDS: exchange column (NT tiles), pivot inverse, scaled rows X_I (2 tiles)
+    __shared__ double colk[F2_MAXNT * LTILE];
+    __shared__ double piv[LTILE];
+    __shared__ double xr[2 * LTILE];
+    __shared__ double adiag[F2_MAXNT * TS];
+    __shared__ int sh_ok;
+
+    const int code = A.fmap[blockIdx.x];
+    const int sub = code >> 8, rank = code & 255;
+    const SubDesc d = A.subs[sub];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int m = d.m, mp = d.mp, NT = d.NT, ms = d.ms;
+    const int Pf = (NT + 1) / 2;
+    const int64_t nn = (int64_t)A.W * A.H, ne = (int64_t)(A.W - 1) * (A.H - 1) * 2;
+    const double* f0 = A.f0 + d.pair * nn;
+    const double* al = A.al + d.pair * ne;
+    double* Tout = A.factors + d.foff;
+    double* Bst = A.factors + d.boff;
+    double* Sfull = A.work + d.soff;                    // mp x mp, full symmetric S_{t-1}^{-1}
+    double* T1 = Sfull + (int64_t)mp * mp;              // mp x mp, rows of B_t S_{t-1}^{-1}
+    double* xch = T1 + (int64_t)mp * mp;                // [2][NT][32x32] exchange slots
+    uint32_t* cnt = A.counters + sub;
+
+    // own block rows and tiles; tile list: row r first, then row NT-1-r
+    const int rowA = rank, rowB = NT - 1 - rank;
+    const int nrows = rowB > rowA ? 2 : 1;
+    const int ntl = (rowA + 1) + (nrows == 2 ? rowB + 1 : 0);
+    const int nblk = 4 * ntl;                 // 16x16 accumulator blocks
+    d4 acc[F2_MAXBLK];
+    // fragment coordinates of this lane inside a 16x16 block
+    const int fr = lane & 15, fk = lane >> 4;              // A/B operand: row fr, k-slice fk
+    const int cr = lane >> 4, cc = lane & 15;              // accumulator element q: row cr + 4q, col cc
+
+    uint32_t phase = 0;
+    for (int t = 0; t < d.nt; ++t) {
+        // ---------- phase 0 of the line: build own tiles of S_t -------------
+        // A_tt node blocks and B_t couplings of this line into LDS (colk area)
+        double* Aself = colk;                    // [ms][9]
+        double* Anext = colk + 9 * ms;           // [ms][9]: block (s, s+1)
+        double* Bl = colk + 18 * ms;             // [m][6]
+        {
+            const double* Ag = A.factors + d.aoff + (int64_t)t * ms * 18;
+            for (int i = tid; i < 18 * ms; i += F2_THREADS) {
+                const int s = i / 18, k = i % 18;
+                if (k < 9) Aself[9 * s + k] = Ag[i];
+                else       Anext[9 * s + k - 9] = Ag[i];
+            }
+            const double* Bg = Bst + (int64_t)t * m * 6;
+            if (t > 0)
+                for (int i = tid; i < 6 * m; i += F2_THREADS) Bl[i] = Bg[i];
+        }
+        __syncthreads();
+        for (int a = tid; a < mp; a += F2_THREADS) adiag[a] = a < m ? Aself[9 * (a / 3) + 4 * (a % 3)] : 1.0;
+        // A_tt entry (a, a2), both < m
+        auto a_entry = [&](int a, int a2) -> double {
+            const int s = a / 3, c = a % 3, s2 = a2 / 3, c2 = a2 % 3;
+            if (s == s2) return Aself[9 * s + 3 * c + c2];
+            if (s2 == s + 1) return Anext[9 * s + 3 * c + c2];
+            if (s == s2 + 1) return Anext[9 * s2 + 3 * c2 + c];
+            return 0.0;
+        };
+        if (t > 0) {
+            // stage 1: T1 rows of the own block rows, T1[a][c] = sum_{b in W(a)} B[a][b] Sfull[b][c]
+            if (!f2_wait(cnt, Pf * phase, A, sub, &sh_ok)) return;
+            for (int rr = 0; rr < nrows; ++rr) {
+                const int I = rr == 0 ? rowA : rowB;
+                for (int i = tid; i < TS * m; i += F2_THREADS) {
+                    const int a = I * TS + i / m, c = i % m;
+                    if (a >= m) continue;
+                    const int s = a / 3;
+                    const double* cf = Bl + a * 6;
+                    double v = 0.0;
+                    #pragma unroll
+                    for (int e = 0; e < 3; ++e) {
+                        if (s > 0) v = fma(cf[e], xload(Sfull + (int64_t)(3 * (s - 1) + e) * mp + c), v);
+                        v = fma(cf[3 + e], xload(Sfull + (int64_t)(3 * s + e) * mp + c), v);
+                    }
+                    T1[(int64_t)a * mp + c] = v;
+                }
+            }
+            __syncthreads();
+        }
+        // stage 2: own blocks S[a][a2] = A[a][a2] - sum_{b2 in W(a2)} T1[a][b2] B[a2][b2]
+#pragma unroll
+        for (int b = 0; b < F2_MAXBLK; ++b) {
+            const int blk = wv + F2_NW * b;
+            d4 v = {0.0, 0.0, 0.0, 0.0};
+            if (blk < nblk) {
+                int I, J;
+                f2_tile_of(blk >> 2, rowA, rowB, I, J);
+                const int qi = (blk >> 1) & 1, qj = blk & 1;
+                const int a2 = J * TS + 16 * qj + cc;
+                #pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int a = I * TS + 16 * qi + cr + 4 * q;
+                    double s = 0.0;
+                    if (a < m && a2 < m) {
+                        s = a_entry(a, a2);
+                        if (t > 0) {
+                            const int s2 = a2 / 3;
+                            const double* cf = Bl + a2 * 6;
+                            const double* tr = T1 + (int64_t)a * mp;
+                            double u = 0.0;
+                            #pragma unroll
+                            for (int e = 0; e < 3; ++e) {
+                                if (s2 > 0) u = fma(tr[3 * (s2 - 1) + e], cf[e], u);
+                                u = fma(tr[3 * s2 + e], cf[3 + e], u);
+                            }
+                            s -= u;
+                        }
+                    } else if (a == a2) {
+                        s = 1.0;              // identity on the padding
+                    }
+                    v[q] = s;
+                }
+            }
+            acc[b] = v;
+        }
+        __syncthreads();   // LDS (Aself/Anext/Bl) is reused for the exchange column below
+
+        f2_publish(acc, xch + (int64_t)(phase & 1) * NT * TSZ, 0, nblk, rowA, rowB, wv, cr, cc);
+        f2_signal(cnt);
+        ++phase;
+
+        // ---------- pivot steps -------------------------------------------------
+        for (int k = 0; k < NT; ++k, ++phase) {
+            if (!f2_wait(cnt, Pf * phase, A, sub, &sh_ok)) return;
+            const double* xb = xch + (int64_t)((phase - 1) & 1) * NT * TSZ;
+            for (int i = tid; i < NT * TSZ; i += F2_THREADS) {
+                const int J = i / TSZ, r = (i / TS) % TS, c = i % TS;
+                colk[J * LTILE + r * LDP + c] = xload(xb + i);
+            }
+            __syncthreads();
+            // Pi = S_kk^{-1}: unblocked symmetric sweep of the 32x32 pivot block
+            for (int i = tid; i < TSZ; i += F2_THREADS) piv[(i / TS) * LDP + i % TS] = colk[k * LTILE + (i / TS) * LDP + i % TS];
+            __syncthreads();
+            for (int p = 0; p < TS; ++p) {
+                const double pp = piv[p * LDP + p];
+                if (tid == 0 && !(pp > 1e-13 * adiag[k * TS + p] && isfinite(pp))) {
+                    if (atomicCAS(&A.status->code, 0, SF_NOT_SPD) == 0) {
+                        A.status->sub = sub;
+                        A.status->row = (int64_t)t * m + k * TS + p;
+                    }
+                }
+                const double ip = 1.0 / pp;
+                double nv[2];
+                int ir[2], ic[2];
+                #pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int e = tid + h * F2_THREADS;
+                    ir[h] = e / TS;
+                    ic[h] = e % TS;
+                    const int i = ir[h], j = ic[h];
+                    if (i != p && j != p) nv[h] = piv[i * LDP + j] - piv[i * LDP + p] * piv[p * LDP + j] * ip;
+                    else if (i == p && j == p) nv[h] = -ip;
+                    else if (i == p) nv[h] = piv[p * LDP + j] * ip;
+                    else nv[h] = piv[i * LDP + p] * ip;
+                }
+                __syncthreads();
+                #pragma unroll
+                for (int h = 0; h < 2; ++h) piv[ir[h] * LDP + ic[h]] = nv[h];
+                __syncthreads();
+            }
+            // the sweep left -S_kk^{-1}; make it Pi
+            for (int i = tid; i < TSZ; i += F2_THREADS) piv[(i / TS) * LDP + i % TS] = -piv[(i / TS) * LDP + i % TS];
+            __syncthreads();
+            // X_I = S_Ik Pi for the own rows I != k
+            for (int rr = 0; rr < nrows; ++rr) {
+                const int I = rr == 0 ? rowA : rowB;
+                if (I == k) continue;
+                // 4 blocks of 16x16, one per wave (waves 0..3 for row A, 4..7 for row B)
+                if ((wv >> 2) == rr) {
+                    const int qi = (wv >> 1) & 1, qj = wv & 1;
+                    d4 x = {0.0, 0.0, 0.0, 0.0};
+                    #pragma unroll
+                    for (int ks = 0; ks < TS / 4; ++ks) {
+                        const double a = colk[I * LTILE + (16 * qi + fr) * LDP + 4 * ks + fk];
+                        const double b = piv[(4 * ks + fk) * LDP + 16 * qj + fr];
+                        x = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, x, 0, 0, 0);
+                    }
+                    #pragma unroll
+                    for (int q = 0; q < 4; ++q) xr[rr * LTILE + (16 * qi + cr + 4 * q) * LDP + 16 * qj + cc] = x[q];
+                }
+            }
+            __syncthreads();
+            // update own blocks
+#pragma unroll
+            for (int b = 0; b < F2_MAXBLK; ++b) {
+                const int blk = wv + F2_NW * b;
+                if (blk >= nblk) continue;
+                int I, J;
+                f2_tile_of(blk >> 2, rowA, rowB, I, J);
+                const int qi = (blk >> 1) & 1, qj = blk & 1;
+                const int rr = (I == rowA) ? 0 : 1;
+                if (I != k && J != k) {
+                    d4 v = acc[b];
+                    #pragma unroll
+                    for (int ks = 0; ks < TS / 4; ++ks) {
+                        const double a = -xr[rr * LTILE + (16 * qi + fr) * LDP + 4 * ks + fk];
+                        const double bb = colk[J * LTILE + (16 * qj + fr) * LDP + 4 * ks + fk];
+                        v = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb, v, 0, 0, 0);
+                    }
+                    acc[b] = v;
+                } else if (I != k) {        // J == k: S_Ik <- X_I
+                    #pragma unroll
+                    for (int q = 0; q < 4; ++q) acc[b][q] = xr[rr * LTILE + (16 * qi + cr + 4 * q) * LDP + 16 * qj + cc];
+                } else if (J != k) {        // I == k: S_kJ <- Pi S_kJ = Pi colk[J]^T
+                    d4 v = {0.0, 0.0, 0.0, 0.0};
+                    #pragma unroll
+                    for (int ks = 0; ks < TS / 4; ++ks) {
+                        const double a = piv[(16 * qi + fr) * LDP + 4 * ks + fk];
+                        const double bb = colk[J * LTILE + (16 * qj + fr) * LDP + 4 * ks + fk];
+                        v = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb, v, 0, 0, 0);
+                    }
+                    acc[b] = v;
+                } else {                    // S_kk <- -Pi
+                    #pragma unroll
+                    for (int q = 0; q < 4; ++q) acc[b][q] = -piv[(16 * qi + cr + 4 * q) * LDP + 16 * qj + cc];
+                }
+            }
+            if (k + 1 < NT) {
+                f2_publish(acc, xch + (int64_t)(phase & 1) * NT * TSZ, k + 1, nblk, rowA, rowB, wv, cr, cc);
+            } else {
+                // ---------- line done: blocks hold -S_t^{-1} ----------------------
+#pragma unroll
+                for (int b = 0; b < F2_MAXBLK; ++b) {
+                    const int blk = wv + F2_NW * b;
+                    if (blk >= nblk) continue;
+                    int I, J;
+                    f2_tile_of(blk >> 2, rowA, rowB, I, J);
+                    const int qi = (blk >> 1) & 1, qj = blk & 1;
+                    const int q0 = I * (I + 1) / 2 + J;
+                    double* tl = Tout + ((int64_t)t * d.ntiles + q0) * TSZ;
+                    #pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int r = 16 * qi + cr + 4 * q, c = 16 * qj + cc;
+                        if (I == J && r < c) continue;           // diagonal tiles: mirror the lower half
+                        const double v = -acc[b][q];
+                        tl[r * TS + c] = v;
+                        if (I == J) tl[c * TS + r] = v;
+                        if (t + 1 < d.nt) {
+                            const int ga = I * TS + r, gc = J * TS + c;
+                            xstore(Sfull + (int64_t)ga * mp + gc, v);
+                            xstore(Sfull + (int64_t)gc * mp + ga, v);
+                        }
+                    }
+                }
+            }
+            f2_signal(cnt);
+        }
+    }
+}
+
+const void* factor2_kernel() { return (const void*)k_factor2; }
+
+int launch_line_coeffs(sf_context* c) {
+    int maxn = 0;
+    for (const auto& d : c->subs) maxn = std::max(maxn, d.nt * d.ms);
+    hipLaunchKernelGGL(k_line_coeffs, dim3((maxn + 255) / 256, c->nsub), dim3(256), 0, c->stream, c->d_subs, c->f0,
+                       c->alpha, c->factors, c->W, c->H, c->cfg.lambda, 0);
+    return hipGetLastError() == hipSuccess ? SF_OK : SF_ERR_HIP;
+}
+
+int launch_factor2(sf_context* c, int sub0, int nsub_chunk, int Pf) {
+    FactorArgs a;
+    a.subs = c->d_subs;
+    a.fmap = c->d_fmap + (int64_t)sub0 * Pf;
+    a.f0 = c->f0;
+    a.al = c->alpha;
+    a.factors = c->factors;
+    a.work = c->work;
+    a.counters = c->counters;
+    a.status = c->status_d;
+    a.W = c->W;
+    a.H = c->H;
+    a.lam = c->cfg.lambda;
+    a.spin_limit = 1ll << 20;
+    void* args[] = {&a};
+    if (hipLaunchCooperativeKernel((const void*)k_factor2, dim3(nsub_chunk * Pf), dim3(F2_THREADS), args, 0,
+                                   c->stream) != hipSuccess)
+        return SF_ERR_HIP;
+    return SF_OK;
+}
+
+}  // namespace sfdd

@@ -31,8 +31,9 @@ struct SubDesc {
     int64_t foff;   // inverse Schur tiles: nt * ntiles * TSZ doubles
     int64_t boff;   // line couplings B_t: nt * m * 6 doubles (t = 0 unused)
     int64_t woff;   // sweep scratch: nt * mp doubles (forward results w_t)
-    int64_t soff;   // factor workspace: 3 * mp * mp doubles
+    int64_t soff;   // factor workspace: max(3 mp^2, 2 mp^2 + 2 NT TS^2) doubles
     int64_t poff;   // sweep published rows: 2 * mp doubles
+    int64_t aoff;   // line node blocks A[(t,s),(t,s)], A[(t,s),(t,s+1)]: nt * ms * 18 doubles
 };
 
 // Global node coordinates of local node (t, s).
@@ -63,6 +64,9 @@ struct sf_context {
                                     // sweep launch order, then subdomain-major order
     int sweep_grid;
     int maxP;
+    int32_t* d_fmap;                // factor workgroup -> (sub << 8 | rank), subdomain-major
+    int factor_pf;                  // workgroups per subdomain in the cooperative factor (0: one-WG factor)
+    int factor_chunk;               // subdomains per cooperative factor launch
     // per-pair field data
     double *f0, *ft, *alpha;        // [B][H][W], [B][H][W], [B][H-1][W-1][2]
     double *F, *r;                  // [B][3][H][W]
@@ -103,6 +107,9 @@ int launch_indicator(sf_context* c, const double* U, double* eta, int reset_max)
 int launch_alpha_update(sf_context* c, const double* eta, double* alpha_out, double kappa,
                         double eta_thr, double alpha_th);
 int launch_factor(sf_context* c);
+int launch_factor2(sf_context* c, int sub0, int nsub_chunk, int Pf);
+int launch_line_coeffs(sf_context* c);
+const void* factor2_kernel();
 int launch_sweep(sf_context* c, double* U, const double* r, int single_sub, const double* b_local,
                  double* x_local);
 const void* sweep_kernel();

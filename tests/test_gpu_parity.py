@@ -20,7 +20,10 @@ CASES = {
     "ragged": dict(kind="plain64", seed=5, W=37, H=29, px=3, py=2, d=5),         # uneven tiles, odd overlap
     "tall": dict(kind="plain64", seed=6, W=23, H=41, px=2, py=3, d=6),           # line orientation mix
     "noisy": dict(kind="plain640", seed=3, W=72, H=56, px=3, py=3, d=8),         # 640x480 recipe, cropped
+    "single": dict(kind="plain64", seed=8, W=9, H=12, px=1, py=1, d=0),          # one line tile (m <= 32)
 }
+# line matrices above 384 x 384 take the one-workgroup factorisation
+WIDE = dict(kind="plain640", seed=4, W=300, H=136, px=2, py=1, d=8)
 
 
 def dev(a):
@@ -72,9 +75,9 @@ def test_rhs_and_residual_match_oracle(gpu, name):
     assert n2[0] == pytest.approx(float(np.sum(ro ** 2)), rel=1e-12)
 
 
-@pytest.mark.parametrize("name", ["plain64", "ragged", "tall"])
+@pytest.mark.parametrize("name", ["plain64", "ragged", "tall", "single", "wide"])
 def test_subdomain_solves_match_lapack(gpu, name):
-    case = CASES[name]
+    case = WIDE if name == "wide" else CASES[name]
     p, al, ctx, _ = setup(case)
     api.sf_factor_subdomains(ctx)
     A, F = fem.assemble(p.I0, p.I1, al, 1.0)
