@@ -254,7 +254,7 @@ int sf_create(const sf_config* cfg, void* stream, sf_context** out) {
         d.woff = woff;
         woff += (int64_t)d.nt * d.mp;
         d.poff = woff;
-        woff += (int64_t)2 * d.mp;
+        woff += (int64_t)4 * d.mp;
         d.soff = woff;   // factor workspace (one-WG factor: 3 mp^2; cooperative: 2 mp^2 + exchange slots)
         woff += std::max<int64_t>((int64_t)3 * d.mp * d.mp, (int64_t)2 * d.mp * d.mp + 2ll * d.NT * sfdd::TSZ);
     }
@@ -319,6 +319,12 @@ int sf_create(const sf_config* cfg, void* stream, sf_context** out) {
         sf_destroy(c);
         return SF_ERR_HIP;
     }
+    // sweep exchange buffers start with tag 0, which no launch ever waits for
+    if (hipMemset(c->work, 0, (size_t)c->work_doubles * sizeof(double)) != hipSuccess) {
+        sf_destroy(c);
+        return SF_ERR_HIP;
+    }
+    c->sweep_epoch = 1;
     hipLaunchKernelGGL(k_zero_status_api, dim3(1), dim3(1), 0, c->stream, c->status_d);
     if (hipGetLastError() != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess) {
         sf_destroy(c);

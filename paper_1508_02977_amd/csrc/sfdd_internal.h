@@ -32,7 +32,7 @@ struct SubDesc {
     int64_t boff;   // line couplings B_t: nt * m * 6 doubles (t = 0 unused)
     int64_t woff;   // sweep scratch: nt * mp doubles (forward results w_t)
     int64_t soff;   // factor workspace: max(3 mp^2, 2 mp^2 + 2 NT TS^2) doubles
-    int64_t poff;   // sweep published rows: 2 * mp doubles
+    int64_t poff;   // sweep published rows: [2][mp] pairs of tagged 64-bit words (4 mp doubles)
     int64_t aoff;   // line node blocks A[(t,s),(t,s)], A[(t,s),(t,s+1)]: nt * ms * 18 doubles
 };
 
@@ -67,6 +67,7 @@ struct sf_context {
     int32_t* d_fmap;                // factor workgroup -> (sub << 8 | rank), subdomain-major
     int factor_pf;                  // workgroups per subdomain in the cooperative factor (0: one-WG factor)
     int factor_chunk;               // subdomains per cooperative factor launch
+    uint32_t sweep_epoch;           // tag base for the sweep's published rows
     // per-pair field data
     double *f0, *ft, *alpha;        // [B][H][W], [B][H][W], [B][H-1][W-1][2]
     double *F, *r;                  // [B][3][H][W]

@@ -17,6 +17,8 @@
 // the next line starts when all P rows sets are out.  No reductions across
 // ranks, so results do not depend on P.  All waits are bounded: a stalled
 // wait raises SF_ERR_DEVICE and every rank exits.
+#include <algorithm>
+
 #include "sfdd_internal.h"
 
 namespace sfdd {
@@ -36,6 +38,7 @@ struct SweepArgs {
     uint32_t* counters;
     DevStatus* status;
     int W, H, mode;
+    uint32_t epoch;         // tag base of this launch (published words carry epoch + phase)
     long long spin_limit;
 };
 
@@ -44,7 +47,9 @@ struct SweepArgs {
 // stall the wait records SF_ERR_DEVICE and every rank of every subdomain exits.
 __device__ __forceinline__ bool wait_count(uint32_t* cnt, uint32_t target, const SweepArgs& A, int sub,
                                            int* sh_ok) {
-    if (threadIdx.x == 0) {
+    // the poller is the first lane of the last wave, which issues no other
+    // global loads in a phase, so its polls never queue behind prefetches
+    if (threadIdx.x == SOLVE_THREADS - 64) {
         long long n = 0;
         int ok = 1;
         while (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
@@ -72,7 +77,7 @@ __device__ __forceinline__ bool wait_count(uint32_t* cnt, uint32_t target, const
 __device__ __forceinline__ void signal_count(uint32_t* cnt) {
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    if (threadIdx.x == 0) __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (threadIdx.x == SOLVE_THREADS - 64) __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __device__ __forceinline__ void pub_store(double* p, double v) {
@@ -82,176 +87,326 @@ __device__ __forceinline__ double pub_load(const double* p) {
     return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Rows I*32 .. I*32+31 of y = S z for the symmetric line matrix S stored as
-// its lower 32x32 tiles (tile (I,J), I >= J, at index I(I+1)/2 + J):
-//   y_I = sum_{J <= I} T(I,J) z_J + sum_{J > I} T(J,I)^T z_J.
-// A wave takes tiles j0, j0+nwaves, ... of the NT tiles of the block row and
-// accumulates into its own LDS row buffer yw[32].
-__device__ __forceinline__ void block_row(const double* __restrict__ Tl, int NT, int I, const double* z,
-                                          double* yw, int wv, int nwaves) {
+constexpr int MAXR = 16;   // block rows per rank (NT <= 16)
+constexpr int PF = 2;      // tiles per wave held in registers across the wait
+
+// Tile (I, J) of the block row of symmetric S: lower tile (I,J) if J <= I,
+// else the lower tile (J,I) used transposed.  Lane (j, h) holds column j of
+// rows 16h..16h+15 of the stored tile.
+__device__ __forceinline__ void load_tile(const double* __restrict__ Tl, int I, int J, double tv[16]) {
     const int lane = threadIdx.x & 63;
     const int j = lane & 31, h = lane >> 5;
-    for (int J = wv; J < NT; J += nwaves) {
-        const bool lower = J <= I;
-        const int k = lower ? I * (I + 1) / 2 + J : J * (J + 1) / 2 + I;
-        const double* T = Tl + (int64_t)k * TSZ + (16 * h) * TS + j;
-        double tv[16];
+    const int k = J <= I ? I * (I + 1) / 2 + J : J * (J + 1) / 2 + I;
+    const double* T = Tl + (int64_t)k * TSZ + (16 * h) * TS + j;
 #pragma unroll
-        for (int i = 0; i < 16; ++i) tv[i] = T[i * TS];
-        if (!lower || J == I) {
-            // y_I[j] += sum_r T[r][j] zJ[r]: T = T(J,I) (transposed use) or the
-            // symmetric diagonal tile; rows r of this lane are 16h..16h+15
-            const double* zr = z + J * TS + 16 * h;
-            double s = 0.0;
+    for (int i = 0; i < 16; ++i) tv[i] = T[i * TS];
+}
+
+// y_I += (tile) z_J for one tile of the block row, into the wave's row buffer y[32].
+__device__ __forceinline__ void tile_apply(const double tv[16], int I, int J, const double* z, double* y) {
+    const int lane = threadIdx.x & 63;
+    const int j = lane & 31, h = lane >> 5;
+    if (J >= I) {
+        // stored (J, I) used transposed, or the symmetric diagonal tile:
+        // y_I[j] += sum_r T[r][j] zJ[r], rows r = 16h..16h+15 of this lane
+        const double* zr = z + J * TS + 16 * h;
+        double s = 0.0;
 #pragma unroll
-            for (int i = 0; i < 16; ++i) s = fma(tv[i], zr[i], s);
-            s += __shfl_xor(s, 32, 64);
-            if (h == 0) yw[j] += s;
-        } else {
-            // y_I[r] += sum_j T[r][j] zJ[j]: 16 row products per lane reduced over
-            // the 32 lanes of the half (transpose-reduce: xor 16, 8, 4, 2, then 1)
-            const double zj = z[J * TS + j];
-            double p[16];
+        for (int i = 0; i < 16; ++i) s = fma(tv[i], zr[i], s);
+        s += __shfl_xor(s, 32, 64);
+        if (h == 0) y[j] += s;
+    } else {
+        // stored (I, J): y_I[r] += sum_j T[r][j] zJ[j]; 16 row products per lane
+        // reduced over the 32 lanes of the half (transpose-reduce: xor 16, 8, 4, 2, then 1)
+        const double zj = z[J * TS + j];
+        double p[16];
 #pragma unroll
-            for (int i = 0; i < 16; ++i) p[i] = tv[i] * zj;
-            const int b4 = (j >> 4) & 1, b3 = (j >> 3) & 1, b2 = (j >> 2) & 1, b1 = (j >> 1) & 1;
+        for (int i = 0; i < 16; ++i) p[i] = tv[i] * zj;
+        const int b4 = (j >> 4) & 1, b3 = (j >> 3) & 1, b2 = (j >> 2) & 1, b1 = (j >> 1) & 1;
 #pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                const double keep = b4 ? p[q + 8] : p[q], send = b4 ? p[q] : p[q + 8];
-                p[q] = keep + __shfl_xor(send, 16, 64);
-            }
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const double keep = b3 ? p[q + 4] : p[q], send = b3 ? p[q] : p[q + 4];
-                p[q] = keep + __shfl_xor(send, 8, 64);
-            }
-#pragma unroll
-            for (int q = 0; q < 2; ++q) {
-                const double keep = b2 ? p[q + 2] : p[q], send = b2 ? p[q] : p[q + 2];
-                p[q] = keep + __shfl_xor(send, 4, 64);
-            }
-            {
-                const double keep = b1 ? p[1] : p[0], send = b1 ? p[0] : p[1];
-                p[0] = keep + __shfl_xor(send, 2, 64);
-            }
-            p[0] += __shfl_xor(p[0], 1, 64);
-            if ((j & 1) == 0) yw[16 * h + 8 * b4 + 4 * b3 + 2 * b2 + b1] += p[0];
+        for (int q = 0; q < 8; ++q) {
+            const double keep = b4 ? p[q + 8] : p[q], send = b4 ? p[q] : p[q + 8];
+            p[q] = keep + __shfl_xor(send, 16, 64);
         }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const double keep = b3 ? p[q + 4] : p[q], send = b3 ? p[q] : p[q + 4];
+            p[q] = keep + __shfl_xor(send, 8, 64);
+        }
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const double keep = b2 ? p[q + 2] : p[q], send = b2 ? p[q] : p[q + 2];
+            p[q] = keep + __shfl_xor(send, 4, 64);
+        }
+        {
+            const double keep = b1 ? p[1] : p[0], send = b1 ? p[0] : p[1];
+            p[0] = keep + __shfl_xor(send, 2, 64);
+        }
+        p[0] += __shfl_xor(p[0], 1, 64);
+        if ((j & 1) == 0) y[16 * h + 8 * b4 + 4 * b3 + 2 * b2 + b1] += p[0];
     }
 }
 
+// Phase q of a sweep: forward lines 0..nt-1, then backward lines nt-2..0.
+// Waves 0..NW-2 ("tile waves") hold this rank's tiles of the line matrix and
+// the right-hand side terms; the last wave ("control wave") does all the
+// latency-critical traffic: it polls the counter, gathers the published rows,
+// finishes and publishes this rank's rows and signals.  Global loads of a wave
+// complete in order, so keeping the large tile prefetch (issued by the tile
+// waves right after their compute, one phase ahead) off the control wave lets
+// the next phase's data stream in while the control wave synchronises.  All
+// addressing is set up once in registers; nothing inside the phase loop loads
+// an address from memory (such a load would drain the prefetch queue).
 __global__ void __launch_bounds__(SOLVE_THREADS) k_sweep(SweepArgs A) {
     constexpr int NW = SOLVE_THREADS / 64;
+    constexpr int NWT = NW - 1;                    // tile waves
+    constexpr int CW0 = NWT * 64;                  // first thread of the control wave
+    constexpr int NRC = MAXR * TS / 64;            // own rows per control lane
     __shared__ double z[MAXMP];
     __shared__ double full[MAXMP];
-    __shared__ double yw[NW][TS];
+    __shared__ double yw[NWT][MAXR * TS];
     __shared__ int sh_ok;
 
     const int code = A.wgmap[blockIdx.x];
     const int sub = code >> 8, rank = code & 255;
     const SubDesc d = A.subs[sub];
-    if (A.mode == 0 && A.done[d.pair]) return;   // uniform over the subdomain's ranks
-    const int tid = threadIdx.x, wv = tid >> 6;
-    const int P = d.P, m = d.m, mp = d.mp, ms = d.ms, nt = d.nt, ntiles = d.ntiles, NT = d.NT;
+    const int mode = A.mode;
+    if (mode == 0 && A.done[d.pair]) return;   // uniform over the subdomain's ranks
+    const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+    const bool ctl = wv == NWT;
+    const int P = d.P, m = d.m, mp = d.mp, ms = d.ms, nt = d.nt, NT = d.NT;
+    const int R = (NT - rank + P - 1) / P;         // block rows of this rank: rank + P*i, i < R
+    const int ntw = R * NT;                        // tiles per phase for this rank
+    const int nrow = R * TS;                       // rows finished by this rank
     const int64_t nn = (int64_t)A.W * A.H;
-    const double* Tb = A.factors + d.foff;
-    const double* Bb = A.factors + d.boff;
-    double* wst = A.work + d.woff;           // forward results of this rank's rows
-    double* pub = A.work + d.poff;           // [2][mp] published rows (double-buffered)
-    uint32_t* cnt = A.counters + sub;
+    const int64_t tstride = (int64_t)d.ntiles * TSZ;       // tiles of one line
+    const double* __restrict__ Tb = A.factors + d.foff;
+    const double* __restrict__ Bb = A.factors + d.boff;
+    double* __restrict__ wst = A.work + d.woff;            // w_t, then x_t, of this rank's rows
+    // published rows: [2][mp] pairs of 64-bit words (tag << 32 | half of the double)
+    uint64_t* __restrict__ pub = reinterpret_cast<uint64_t*>(A.work + d.poff);
+    DevStatus* st = A.status;
+    const long long spin = A.spin_limit;
+    const int nphase = 2 * nt - 1;
+    const uint32_t epoch = A.epoch;
 
-    auto rhs = [&](int t, int a) -> double {
-        if (A.mode == 1) return A.b_local[(int64_t)t * m + a];
-        int x, y;
-        local_to_global(d, t, a / 3, x, y);
-        return A.r[((int64_t)d.pair * 3 + a % 3) * nn + (int64_t)y * A.W + x];
+    // local unknown a of line t sits at global index gbase(a) + t * gstep
+    const int64_t gstep = d.cols ? 1 : (int64_t)A.W;
+    auto gbase = [&](int a) -> int64_t {
+        const int s = a / 3, c = a % 3;
+        const int x = d.cols ? d.bx0 : d.bx0 + s, y = d.cols ? d.by0 + s : d.by0;
+        return ((int64_t)d.pair * 3 + c) * nn + (int64_t)y * A.W + x;
     };
-    auto emit = [&](int t, int a, double v) {
-        if (A.mode == 1) { A.x_local[(int64_t)t * m + a] = v; return; }
+    // right-hand side of row a = tid
+    const double* __restrict__ rsrc = mode == 1 ? A.b_local + tid : A.r + (tid < m ? gbase(tid) : 0);
+    const int64_t rstep = mode == 1 ? m : gstep;
+    // B coefficient rows of this thread (forward: row a; backward: rows 3s.., 3s+3..)
+    const int zs = tid / 3, ze = tid % 3;
+    // this thread's tiles (fixed for all lines): offsets inside a line
+    const int tj = lane & 31, th = lane >> 5;
+    int64_t toff[PF];
+#pragma unroll
+    for (int p = 0; p < PF; ++p) {
+        const int qt = wv + NWT * p;
+        const int I = rank + P * (qt / NT), J = qt % NT;
+        const int k = J <= I ? I * (I + 1) / 2 + J : J * (J + 1) / 2 + I;
+        toff[p] = (int64_t)k * TSZ + (16 * th) * TS + tj;
+    }
+    // own rows of the control lanes
+    int crow[NRC];
+#pragma unroll
+    for (int i = 0; i < NRC; ++i) {
+        const int k = tid - CW0 + 64 * i;
+        crow[i] = k < nrow ? (rank + P * (k / TS)) * TS + k % TS : -1;
+    }
+
+    double pre[PF][16];
+    double pr = 0.0, pb[6] = {0, 0, 0, 0, 0, 0};
+    auto prefetch = [&](int q) {                    // tile waves
+        const int t = q < nt ? q : 2 * nt - 2 - q;
+        if (tid < m) {                              // z terms first: needed earlier
+            if (q < nt) {
+                pr = rsrc[t * rstep];
+                if (t > 0) {
+                    const double* cf = Bb + ((int64_t)t * m + tid) * 6;
+#pragma unroll
+                    for (int e = 0; e < 6; ++e) pb[e] = cf[e];
+                }
+            } else {
+                const double* Bt = Bb + (int64_t)(t + 1) * m * 6;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) pb[c] = Bt[(int64_t)(3 * zs + c) * 6 + 3 + ze];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) pb[3 + c] = zs + 1 < ms ? Bt[(int64_t)(3 * (zs + 1) + c) * 6 + ze] : 0.0;
+            }
+        }
+        const double* Tl = Tb + (int64_t)t * tstride;
+#pragma unroll
+        for (int p = 0; p < PF; ++p)
+            if (wv + NWT * p < ntw) {
+#pragma unroll
+                for (int i = 0; i < 16; ++i) pre[p][i] = Tl[toff[p] + i * TS];
+            }
+    };
+    double pw[NRC];
+#pragma unroll
+    for (int i = 0; i < NRC; ++i) pw[i] = 0.0;
+
+    for (int i = tid; i < NWT * MAXR * TS; i += SOLVE_THREADS) (&yw[0][0])[i] = 0.0;
+    if (!ctl) prefetch(0);
+    // Phase structure (B = workgroup barrier):
+    //   control wave: [gather(q)] B z B  .  B [finish, publish(q)]
+    //   tile waves:              B z B [compute(q)] B [prefetch(q+1)]
+    // Rows are exchanged as tagged 64-bit words (32-bit tag, 32-bit half of a
+    // double): a reader polls the words it needs until both halves carry the
+    // tag of the wanted phase, so one memory round trip both synchronises and
+    // transfers the data; no separate flag, counter or store acknowledgement.
+    __syncthreads();
+    for (int q = 0; q < nphase; ++q) {
+        const int t = q < nt ? q : 2 * nt - 2 - q;
+        const bool fwd = q < nt;
+        if (q > 0) {
+            if (ctl) {
+                // each lane needs mp/64 entries: issue all loads, then re-poll
+                // only the entries whose tags are not there yet
+                const uint32_t tag = epoch + (uint32_t)(q - 1);
+                const uint64_t* pbuf = pub + (int64_t)((q - 1) & 1) * mp * 2;
+                constexpr int NG = MAXMP / 64;
+                uint64_t lo[NG], hi[NG];
+                unsigned pending = 0;
+#pragma unroll
+                for (int g = 0; g < NG; ++g)
+                    if (lane + 64 * g < mp) pending |= 1u << g;
+                long long n = 0;
+                int ok = 1;
+                while (pending) {
+#pragma unroll
+                    for (int g = 0; g < NG; ++g)
+                        if (pending & (1u << g)) {
+                            const int a = lane + 64 * g;
+                            lo[g] = __hip_atomic_load(const_cast<uint64_t*>(pbuf + 2 * a), __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT);
+                            hi[g] = __hip_atomic_load(const_cast<uint64_t*>(pbuf + 2 * a + 1), __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT);
+                        }
+#pragma unroll
+                    for (int g = 0; g < NG; ++g)
+                        if ((pending & (1u << g)) && (uint32_t)(lo[g] >> 32) == tag && (uint32_t)(hi[g] >> 32) == tag) {
+                            full[lane + 64 * g] = __longlong_as_double((long long)((hi[g] << 32) | (lo[g] & 0xffffffffull)));
+                            pending &= ~(1u << g);
+                        }
+                    if (!pending) break;
+                    if (++n > spin ||
+                        __hip_atomic_load(&st->code, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == SF_ERR_DEVICE) {
+                        ok = 0;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                }
+                // wave-wide outcome
+                const int all_ok = __all(ok);
+                if (lane == 0) {
+                    if (!all_ok && atomicCAS(&st->code, 0, SF_ERR_DEVICE) == 0) {
+                        st->sub = sub;
+                        st->row = (int64_t)q;
+                    }
+                    sh_ok = all_ok;
+                }
+            }
+            __syncthreads();
+            if (!sh_ok) return;
+        }
+        // z: forward r_t - B_t w_{t-1}; backward B_{t+1}^T x_{t+1}
+        if (!ctl && tid < mp) {
+            double v = 0.0;
+            if (tid < m) {
+                if (fwd) {
+                    v = pr;
+                    if (t > 0) {
+                        double bw = 0.0;
+                        if (zs > 0)
+#pragma unroll
+                            for (int e = 0; e < 3; ++e) bw = fma(pb[e], full[3 * (zs - 1) + e], bw);
+#pragma unroll
+                        for (int e = 0; e < 3; ++e) bw = fma(pb[3 + e], full[3 * zs + e], bw);
+                        v -= bw;
+                    }
+                } else {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) v = fma(pb[c], full[3 * zs + c], v);
+                    if (zs + 1 < ms)
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) v = fma(pb[3 + c], full[3 * (zs + 1) + c], v);
+                }
+            }
+            z[tid] = v;
+        }
+        __syncthreads();
+        if (!ctl) {
+            // this rank's block rows
+#pragma unroll
+            for (int p = 0; p < PF; ++p) {
+                const int qt = wv + NWT * p;
+                if (qt < ntw) {
+                    const int i = qt / NT;
+                    tile_apply(pre[p], rank + P * i, qt % NT, z, &yw[wv][i * TS]);
+                }
+            }
+            for (int qt = wv + NWT * PF; qt < ntw; qt += NWT) {
+                const int i = qt / NT;
+                double tv[16];
+                load_tile(Tb + (int64_t)t * tstride, rank + P * i, qt % NT, tv);
+                tile_apply(tv, rank + P * i, qt % NT, z, &yw[wv][i * TS]);
+            }
+        }
+        __syncthreads();
+        if (!ctl) {
+            if (q + 1 < nphase) prefetch(q + 1);
+        } else {
+            // finish and publish this rank's rows; keep them; prefetch w
+            const uint64_t tag = (uint64_t)(epoch + (uint32_t)q) << 32;
+            uint64_t* pout = pub + (int64_t)(q & 1) * mp * 2;
+            double* wt = wst + (int64_t)t * mp;
+#pragma unroll
+            for (int i = 0; i < NRC; ++i) {
+                const int k = tid - CW0 + 64 * i;
+                if (crow[i] >= 0) {
+                    double y = 0.0;
+                    for (int w = 0; w < NWT; ++w) {
+                        y += yw[w][k];
+                        yw[w][k] = 0.0;
+                    }
+                    if (!fwd) y = pw[i] - y;               // x_t = w_t - S_t^{-1} v
+                    const uint64_t bits = (uint64_t)__double_as_longlong(y);
+                    __hip_atomic_store(pout + 2 * crow[i], tag | (bits & 0xffffffffull), __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                    __hip_atomic_store(pout + 2 * crow[i] + 1, tag | (bits >> 32), __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                    wt[crow[i]] = y;                               // w_t or x_t
+                }
+            }
+            if (q + 1 < nphase && q + 1 >= nt) {
+                const double* wn = wst + (int64_t)(2 * nt - 3 - q) * mp;   // line of phase q + 1
+#pragma unroll
+                for (int i = 0; i < NRC; ++i) pw[i] = crow[i] >= 0 ? wn[crow[i]] : 0.0;
+            }
+        }
+    }
+    // U[O_i] += x on the owned nodes of this rank's rows (x_{nt-1} = w_{nt-1})
+    __syncthreads();
+    for (int i = tid; i < nt * nrow; i += SOLVE_THREADS) {
+        const int t = i / nrow, k = i % nrow;
+        const int a = (rank + P * (k / TS)) * TS + k % TS;
+        if (a >= m) continue;
+        const double v = wst[(int64_t)t * mp + a];
+        if (mode == 1) {
+            A.x_local[(int64_t)t * m + a] = v;
+            continue;
+        }
         int x, y;
         local_to_global(d, t, a / 3, x, y);
         if (x >= d.ox0 && x < d.ox1 && y >= d.oy0 && y < d.oy1)
             A.U[((int64_t)d.pair * 3 + a % 3) * nn + (int64_t)y * A.W + x] += v;
-    };
-    // This rank's block rows I = rank, rank + P, ...: y = S_t z for those rows,
-    // then finish(I, row, y) for each row.
-    auto rows = [&](int t, auto&& finish) {
-        const double* Tl = Tb + (int64_t)t * ntiles * TSZ;
-        for (int I = rank; I < NT; I += P) {
-            for (int i = tid; i < NW * TS; i += SOLVE_THREADS) (&yw[0][0])[i] = 0.0;
-            __syncthreads();
-            block_row(Tl, NT, I, z, yw[wv], wv, NW);
-            __syncthreads();
-            if (tid < TS) {
-                double y = 0.0;
-                for (int w = 0; w < NW; ++w) y += yw[w][tid];
-                finish(I * TS + tid, y);
-            }
-            __syncthreads();
-        }
-    };
-
-    uint32_t phase = 0;
-    // ---------------- forward: w_t = S_t^{-1} (r_t - B_t w_{t-1}) ----------------
-    for (int t = 0; t < nt; ++t, ++phase) {
-        if (t > 0) {
-            if (!wait_count(cnt, P * phase, A, sub, &sh_ok)) return;
-            const double* pb = pub + (int64_t)((phase - 1) & 1) * mp;
-            for (int a = tid; a < mp; a += SOLVE_THREADS) full[a] = pub_load(pb + a);
-            __syncthreads();
-        }
-        const double* Bt = Bb + (int64_t)t * m * 6;
-        for (int a = tid; a < mp; a += SOLVE_THREADS) {
-            double v = 0.0;
-            if (a < m) {
-                v = rhs(t, a);
-                if (t > 0) {
-                    const int s = a / 3;
-                    const double* cf = Bt + (int64_t)a * 6;
-                    double bw = 0.0;
-                    if (s > 0)
-                        for (int e = 0; e < 3; ++e) bw = fma(cf[e], full[3 * (s - 1) + e], bw);
-                    for (int e = 0; e < 3; ++e) bw = fma(cf[3 + e], full[3 * s + e], bw);
-                    v -= bw;
-                }
-            }
-            z[a] = v;
-        }
-        __syncthreads();
-        double* pw = pub + (int64_t)(phase & 1) * mp;
-        rows(t, [&](int a, double y) {
-            pub_store(pw + a, y);
-            wst[(int64_t)t * mp + a] = y;
-            if (t == nt - 1 && a < m) emit(t, a, y);      // x_{nt-1} = w_{nt-1}
-        });
-        signal_count(cnt);
-    }
-    // ---------------- backward: x_t = w_t - S_t^{-1} B_{t+1}^T x_{t+1} ----------------
-    for (int t = nt - 2; t >= 0; --t, ++phase) {
-        if (!wait_count(cnt, P * phase, A, sub, &sh_ok)) return;
-        const double* pb = pub + (int64_t)((phase - 1) & 1) * mp;
-        for (int a = tid; a < mp; a += SOLVE_THREADS) full[a] = pub_load(pb + a);   // x_{t+1}
-        __syncthreads();
-        const double* Bt = Bb + (int64_t)(t + 1) * m * 6;
-        for (int b = tid; b < mp; b += SOLVE_THREADS) {
-            double v = 0.0;
-            if (b < m) {
-                const int s = b / 3, e = b % 3;
-                for (int c = 0; c < 3; ++c) v = fma(Bt[(int64_t)(3 * s + c) * 6 + 3 + e], full[3 * s + c], v);
-                if (s + 1 < ms)
-                    for (int c = 0; c < 3; ++c)
-                        v = fma(Bt[(int64_t)(3 * (s + 1) + c) * 6 + e], full[3 * (s + 1) + c], v);
-            }
-            z[b] = v;
-        }
-        __syncthreads();
-        double* pw = pub + (int64_t)(phase & 1) * mp;
-        rows(t, [&](int a, double y) {
-            const double x = wst[(int64_t)t * mp + a] - y;
-            pub_store(pw + a, x);
-            if (a < m) emit(t, a, x);
-        });
-        signal_count(cnt);
     }
 }
 
@@ -279,6 +434,12 @@ int launch_sweep(sf_context* c, double* U, const double* r, int single_sub, cons
     a.H = c->H;
     a.mode = single_sub >= 0 ? 1 : 0;
     a.spin_limit = 1ll << 20;
+    // tags must differ from every tag left in the exchange buffers by earlier
+    // launches: advance by more than the phases of one launch
+    a.epoch = c->sweep_epoch;
+    int maxph = 0;
+    for (const auto& d : c->subs) maxph = std::max(maxph, 2 * d.nt);
+    c->sweep_epoch += (uint32_t)maxph + 2;
     int grid = c->sweep_grid;
     if (single_sub >= 0) {
         hipLaunchKernelGGL(k_zero_u32, dim3((c->nsub + 255) / 256), dim3(256), 0, c->stream, c->counters, c->nsub);
