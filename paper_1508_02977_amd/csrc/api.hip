@@ -173,7 +173,7 @@ const char* sf_status_string(int s) {
 
 void sf_destroy(sf_context* c) {
     if (!c) return;
-    void* ptrs[] = {c->d_subs, c->d_wgmap, c->d_fmap, c->f0, c->ft, c->alpha, c->F, c->r, c->eta, c->Fn2,
+    void* ptrs[] = {c->d_subs, c->f0, c->ft, c->alpha, c->F, c->r, c->eta, c->Fn2,
                     c->partials, c->relres_d, c->sweeps_d, c->done_d, c->counters, c->etamax_bits,
                     c->flags_d, c->factors, c->work, c->status_d};
     for (void* p : ptrs)
@@ -219,12 +219,14 @@ int sf_create(const sf_config* cfg, void* stream, sf_context** out) {
         occ = 1;
     const int capacity = ncu * occ;
     // one rank per 32-row block row of the line matrices when the chip has room
-    int P = k.band_tile > 0 ? k.band_tile : std::max(1, std::min(capacity / c->nsub, min_nt));
+    // workgroup slots: 8 XCD lanes x ceil(nsub / 8) subdomains per lane x P ranks
+    const int nsx = (c->nsub + 7) / 8;
+    int P = k.band_tile > 0 ? k.band_tile : std::max(1, std::min(capacity / (8 * nsx), min_nt));
     P = std::min(P, min_nt);
     P = std::min(P, 255);
-    if ((int64_t)P * c->nsub > capacity) P = std::max(1, capacity / c->nsub);
+    if ((int64_t)P * 8 * nsx > capacity) P = std::max(1, capacity / (8 * nsx));
     c->maxP = P;
-    c->sweep_grid = P * c->nsub;
+    c->sweep_grid = 8 * nsx * P;
 
     // cooperative factor: ceil(NT/2) workgroups per subdomain, line matrices up to 384
     int maxnt = 0;
@@ -233,9 +235,10 @@ int sf_create(const sf_config* cfg, void* stream, sf_context** out) {
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ2, sfdd::factor2_kernel(), 512, 0) != hipSuccess)
         occ2 = 0;
     const int Pf = (maxnt + 1) / 2;
-    if (maxnt <= 12 && occ2 >= 1 && Pf <= ncu * occ2) {
+    if (maxnt <= 12 && occ2 >= 1 && 8 * Pf <= ncu * occ2) {
         c->factor_pf = Pf;
-        c->factor_chunk = std::max(1, std::min(c->nsub, (ncu * occ2) / Pf));
+        // subdomains per launch: a multiple of 8 whose slots fit co-resident
+        c->factor_chunk = std::max(8, 8 * ((ncu * occ2) / (8 * Pf)));
     } else {
         c->factor_pf = 0;
         c->factor_chunk = 0;
@@ -261,33 +264,10 @@ int sf_create(const sf_config* cfg, void* stream, sf_context** out) {
     c->factor_doubles = foff;
     c->work_doubles = woff;
 
-    // workgroup map: XCD-aware when the subdomains split evenly over the
-    // 8 XCDs (workgroup g runs on XCD g % 8): all ranks of a subdomain then
-    // share one L2.  Second half: subdomain-major order.
-    std::vector<int32_t> fmap((size_t)c->nsub * std::max(1, c->factor_pf));
-    for (size_t g = 0; g < fmap.size(); ++g) {
-        const int pf = std::max(1, c->factor_pf);
-        fmap[g] = (int32_t)(((g / pf) << 8) | (g % pf));
-    }
-    std::vector<int32_t> map(2 * (size_t)c->sweep_grid);
-    const int G = c->sweep_grid;
-    for (int g = 0; g < G; ++g) map[G + g] = ((g / P) << 8) | (g % P);
-    if (c->nsub % 8 == 0 && ncu % 8 == 0) {
-        for (int g = 0; g < G; ++g) {
-            const int x = g % 8, slot = g / 8;
-            const int sub = x + 8 * (slot / P), rank = slot % P;
-            map[g] = (sub << 8) | rank;
-        }
-    } else {
-        for (int g = 0; g < G; ++g) map[g] = map[G + g];
-    }
-
     const int64_t nn = (int64_t)c->W * c->H, ne = (int64_t)(c->W - 1) * (c->H - 1) * 2;
     c->npart = (int)((nn + 255) / 256);
     int rc = SF_OK;
     rc |= dalloc(&c->d_subs, c->subs.size());
-    rc |= dalloc(&c->d_wgmap, map.size());
-    rc |= dalloc(&c->d_fmap, fmap.size());
     rc |= dalloc(&c->f0, nn * c->B);
     rc |= dalloc(&c->ft, nn * c->B);
     rc |= dalloc(&c->alpha, ne * c->B);
@@ -313,9 +293,7 @@ int sf_create(const sf_config* cfg, void* stream, sf_context** out) {
         return SF_ERR_OOM;
     }
     if (hipMemcpy(c->d_subs, c->subs.data(), c->subs.size() * sizeof(SubDesc), hipMemcpyHostToDevice) !=
-            hipSuccess ||
-        hipMemcpy(c->d_wgmap, map.data(), map.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(c->d_fmap, fmap.data(), fmap.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess) {
+        hipSuccess) {
         sf_destroy(c);
         return SF_ERR_HIP;
     }
@@ -325,6 +303,7 @@ int sf_create(const sf_config* cfg, void* stream, sf_context** out) {
         return SF_ERR_HIP;
     }
     c->sweep_epoch = 1;
+
     hipLaunchKernelGGL(k_zero_status_api, dim3(1), dim3(1), 0, c->stream, c->status_d);
     if (hipGetLastError() != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess) {
         sf_destroy(c);

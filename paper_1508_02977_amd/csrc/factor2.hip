@@ -41,7 +41,8 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 
 struct FactorArgs {
     const SubDesc* subs;
-    const int32_t* fmap;      // workgroup -> (sub << 8 | rank)
+    int sub0, nsub;           // subdomains [sub0, nsub) of this launch; sub0 % 8 == 0
+    int pf;                   // rank slots per subdomain (the largest ceil(NT / 2))
     const double* f0;
     const double* al;
     double* factors;
@@ -200,12 +201,16 @@ __global__ void __launch_bounds__(F2_THREADS) k_factor2(FactorArgs A) {
     __shared__ double adiag[F2_MAXNT * TS];
     __shared__ int sh_ok;
 
-    const int code = A.fmap[blockIdx.x];
-    const int sub = code >> 8, rank = code & 255;
+    // workgroup g runs on XCD g % 8: the ranks of subdomain i are the slots
+    // with g % 8 == i % 8, so its exchange stays inside one L2
+    const int slot = blockIdx.x / 8;
+    const int sub = A.sub0 + (int)(blockIdx.x % 8) + 8 * (slot / A.pf), rank = slot % A.pf;
+    if (sub >= A.nsub) return;                           // idle slot
     const SubDesc d = A.subs[sub];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int m = d.m, mp = d.mp, NT = d.NT, ms = d.ms;
     const int Pf = (NT + 1) / 2;
+    if (rank >= Pf) return;                              // surplus slot of a short subdomain
     const int64_t nn = (int64_t)A.W * A.H, ne = (int64_t)(A.W - 1) * (A.H - 1) * 2;
     const double* f0 = A.f0 + d.pair * nn;
     const double* al = A.al + d.pair * ne;
@@ -254,62 +259,91 @@ __global__ void __launch_bounds__(F2_THREADS) k_factor2(FactorArgs A) {
             if (s == s2 + 1) return Anext[9 * s2 + 3 * c2 + c];
             return 0.0;
         };
-        if (t > 0) {
-            // stage 1: T1 rows of the own block rows, T1[a][c] = sum_{b in W(a)} B[a][b] Sfull[b][c]
-            if (!f2_wait(cnt, Pf * phase, A, sub, &sh_ok)) return;
-            for (int rr = 0; rr < nrows; ++rr) {
-                const int I = rr == 0 ? rowA : rowB;
-                for (int i = tid; i < TS * m; i += F2_THREADS) {
-                    const int a = I * TS + i / m, c = i % m;
-                    if (a >= m) continue;
-                    const int s = a / 3;
-                    const double* cf = Bl + a * 6;
-                    double v = 0.0;
-                    #pragma unroll
-                    for (int e = 0; e < 3; ++e) {
-                        if (s > 0) v = fma(cf[e], xload(Sfull + (int64_t)(3 * (s - 1) + e) * mp + c), v);
-                        v = fma(cf[3 + e], xload(Sfull + (int64_t)(3 * s + e) * mp + c), v);
-                    }
-                    T1[(int64_t)a * mp + c] = v;
-                }
-            }
-            __syncthreads();
-        }
-        // stage 2: own blocks S[a][a2] = A[a][a2] - sum_{b2 in W(a2)} T1[a][b2] B[a2][b2]
+        // Own blocks of S_t = A_tt - B_t S_{t-1}^{-1} B_t^T.  A 16x16 block with
+        // rows R and columns C needs S_{t-1}^{-1} only on the node windows of R
+        // and C (<= 21 x 21 entries): each wave stages that window of the full
+        // symmetric inverse left by the previous line in its own LDS scratch,
+        // forms Z = S^{-1}[W(R), .] B_C^T, then the block Q = B_R Z.
+        if (t > 0 && !f2_wait(cnt, Pf * phase, A, sub, &sh_ok)) return;
+        {
+            constexpr int WN = 21;
+            double* win = colk + 4608 + wv * (WN * WN + WN * 16);   // [WN][WN]
+            double* zb = win + WN * WN;                             // [WN][16]
 #pragma unroll
-        for (int b = 0; b < F2_MAXBLK; ++b) {
-            const int blk = wv + F2_NW * b;
-            d4 v = {0.0, 0.0, 0.0, 0.0};
-            if (blk < nblk) {
-                int I, J;
-                f2_tile_of(blk >> 2, rowA, rowB, I, J);
-                const int qi = (blk >> 1) & 1, qj = blk & 1;
-                const int a2 = J * TS + 16 * qj + cc;
-                #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int a = I * TS + 16 * qi + cr + 4 * q;
-                    double s = 0.0;
-                    if (a < m && a2 < m) {
-                        s = a_entry(a, a2);
-                        if (t > 0) {
-                            const int s2 = a2 / 3;
-                            const double* cf = Bl + a2 * 6;
-                            const double* tr = T1 + (int64_t)a * mp;
-                            double u = 0.0;
-                            #pragma unroll
-                            for (int e = 0; e < 3; ++e) {
-                                if (s2 > 0) u = fma(tr[3 * (s2 - 1) + e], cf[e], u);
-                                u = fma(tr[3 * s2 + e], cf[3 + e], u);
-                            }
-                            s -= u;
+            for (int b = 0; b < F2_MAXBLK; ++b) {
+                const int blk = wv + F2_NW * b;
+                d4 v = {0.0, 0.0, 0.0, 0.0};
+                if (blk < nblk) {
+                    int I, J;
+                    f2_tile_of(blk >> 2, rowA, rowB, I, J);
+                    const int qi = (blk >> 1) & 1, qj = blk & 1;
+                    const int r0 = I * TS + 16 * qi, c0 = J * TS + 16 * qj;
+                    if (t > 0) {
+                        const int wr0 = max(0, 3 * (r0 / 3) - 3), wr1 = min(m, 3 * ((r0 + 15) / 3) + 3);
+                        const int wc0 = max(0, 3 * (c0 / 3) - 3), wc1 = min(m, 3 * ((c0 + 15) / 3) + 3);
+                        const int nr = max(0, wr1 - wr0), nc = max(0, wc1 - wc0);
+                        // (i) window of S_{t-1}^{-1}
+                        double wv_[(WN * WN + 63) / 64];
+#pragma unroll
+                        for (int u = 0; u < (WN * WN + 63) / 64; ++u) {
+                            const int e = lane + 64 * u, i = e / WN, j = e % WN;
+                            wv_[u] = (i < nr && j < nc) ? xload(Sfull + (int64_t)(wr0 + i) * mp + wc0 + j) : 0.0;
                         }
-                    } else if (a == a2) {
-                        s = 1.0;              // identity on the padding
+#pragma unroll
+                        for (int u = 0; u < (WN * WN + 63) / 64; ++u) {
+                            const int e = lane + 64 * u;
+                            if (e < WN * WN) win[e] = wv_[u];
+                        }
+                        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                        // (ii) Z[i][jc] = sum_{b2 in W(c0+jc)} win[i][b2 - wc0] B[c0+jc][b2]
+                        for (int e = lane; e < WN * 16; e += 64) {
+                            const int i = e / 16, jc = e % 16, a2 = c0 + jc;
+                            double zv = 0.0;
+                            if (i < nr && a2 < m) {
+                                const int s2 = a2 / 3;
+                                const double* cf = Bl + a2 * 6;
+#pragma unroll
+                                for (int g = 0; g < 3; ++g) {
+                                    if (s2 > 0) zv = fma(win[i * WN + 3 * (s2 - 1) + g - wc0], cf[g], zv);
+                                    zv = fma(win[i * WN + 3 * s2 + g - wc0], cf[3 + g], zv);
+                                }
+                            }
+                            zb[e] = zv;
+                        }
+                        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
                     }
-                    v[q] = s;
+                    // (iii) this lane's 4 entries: S = A - B_R Z
+                    const int a2 = c0 + cc;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int a = r0 + cr + 4 * q;
+                        double sv = 0.0;
+                        if (a < m && a2 < m) {
+                            sv = a_entry(a, a2);
+                            if (t > 0) {
+                                const int s = a / 3;
+                                const int wr0 = max(0, 3 * (r0 / 3) - 3);
+                                const double* cf = Bl + a * 6;
+                                double u = 0.0;
+#pragma unroll
+                                for (int g = 0; g < 3; ++g) {
+                                    if (s > 0) u = fma(cf[g], zb[(3 * (s - 1) + g - wr0) * 16 + cc], u);
+                                    u = fma(cf[3 + g], zb[(3 * s + g - wr0) * 16 + cc], u);
+                                }
+                                sv -= u;
+                            }
+                        } else if (a == a2) {
+                            sv = 1.0;              // identity on the padding
+                        }
+                        v[q] = sv;
+                    }
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
                 }
+                acc[b] = v;
             }
-            acc[b] = v;
         }
         __syncthreads();   // LDS (Aself/Anext/Bl) is reused for the exchange column below
 
@@ -321,43 +355,58 @@ __global__ void __launch_bounds__(F2_THREADS) k_factor2(FactorArgs A) {
         for (int k = 0; k < NT; ++k, ++phase) {
             if (!f2_wait(cnt, Pf * phase, A, sub, &sh_ok)) return;
             const double* xb = xch + (int64_t)((phase - 1) & 1) * NT * TSZ;
-            for (int i = tid; i < NT * TSZ; i += F2_THREADS) {
-                const int J = i / TSZ, r = (i / TS) % TS, c = i % TS;
-                colk[J * LTILE + r * LDP + c] = xload(xb + i);
+            {
+                constexpr int NL = F2_MAXNT * TSZ / F2_THREADS;
+                double tmp[NL];
+#pragma unroll
+                for (int u = 0; u < NL; ++u) {
+                    const int i = tid + F2_THREADS * u;
+                    tmp[u] = i < NT * TSZ ? xload(xb + i) : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < NL; ++u) {
+                    const int i = tid + F2_THREADS * u;
+                    const int J = i / TSZ, r = (i / TS) % TS, c = i % TS;
+                    if (i < NT * TSZ) colk[J * LTILE + r * LDP + c] = tmp[u];
+                }
             }
             __syncthreads();
-            // Pi = S_kk^{-1}: unblocked symmetric sweep of the 32x32 pivot block
-            for (int i = tid; i < TSZ; i += F2_THREADS) piv[(i / TS) * LDP + i % TS] = colk[k * LTILE + (i / TS) * LDP + i % TS];
-            __syncthreads();
-            for (int p = 0; p < TS; ++p) {
-                const double pp = piv[p * LDP + p];
-                if (tid == 0 && !(pp > 1e-13 * adiag[k * TS + p] && isfinite(pp))) {
-                    if (atomicCAS(&A.status->code, 0, SF_NOT_SPD) == 0) {
-                        A.status->sub = sub;
-                        A.status->row = (int64_t)t * m + k * TS + p;
+            // Pi = S_kk^{-1}: unblocked symmetric sweep of the 32x32 pivot block,
+            // in the registers of wave 0 (lane (j, h) holds rows 16h..16h+15 of
+            // column j); the other waves wait at the barrier.
+            if (wv == 0) {
+                const int j = lane & 31, h = lane >> 5;
+                double v[16];
+#pragma unroll
+                for (int r = 0; r < 16; ++r) v[r] = colk[k * LTILE + (16 * h + r) * LDP + j];
+#pragma unroll
+                for (int p = 0; p < TS; ++p) {
+                    const int hp = p >> 4, rp = p & 15;
+                    const double pp = __shfl(v[rp], p + 32 * hp, 64);
+                    if (lane == 0 && !(pp > 1e-13 * adiag[k * TS + p] && isfinite(pp))) {
+                        if (atomicCAS(&A.status->code, 0, SF_NOT_SPD) == 0) {
+                            A.status->sub = sub;
+                            A.status->row = (int64_t)t * m + k * TS + p;
+                        }
+                    }
+                    const double ip = 1.0 / pp;
+                    const double rowp = __shfl(v[rp], j + 32 * hp, 64);     // S[p][j]
+                    double colp[16];
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) colp[r] = __shfl(v[r], p + 32 * h, 64);   // S[16h+r][p]
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) {
+                        const int i = 16 * h + r;
+                        if (i != p && j != p) v[r] = v[r] - colp[r] * rowp * ip;
+                        else if (i == p && j == p) v[r] = -ip;
+                        else if (i == p) v[r] = rowp * ip;
+                        else v[r] = colp[r] * ip;
                     }
                 }
-                const double ip = 1.0 / pp;
-                double nv[2];
-                int ir[2], ic[2];
-                #pragma unroll
-                for (int h = 0; h < 2; ++h) {
-                    const int e = tid + h * F2_THREADS;
-                    ir[h] = e / TS;
-                    ic[h] = e % TS;
-                    const int i = ir[h], j = ic[h];
-                    if (i != p && j != p) nv[h] = piv[i * LDP + j] - piv[i * LDP + p] * piv[p * LDP + j] * ip;
-                    else if (i == p && j == p) nv[h] = -ip;
-                    else if (i == p) nv[h] = piv[p * LDP + j] * ip;
-                    else nv[h] = piv[i * LDP + p] * ip;
-                }
-                __syncthreads();
-                #pragma unroll
-                for (int h = 0; h < 2; ++h) piv[ir[h] * LDP + ic[h]] = nv[h];
-                __syncthreads();
+                // the sweep left -S_kk^{-1}
+#pragma unroll
+                for (int r = 0; r < 16; ++r) piv[(16 * h + r) * LDP + j] = -v[r];
             }
-            // the sweep left -S_kk^{-1}; make it Pi
-            for (int i = tid; i < TSZ; i += F2_THREADS) piv[(i / TS) * LDP + i % TS] = -piv[(i / TS) * LDP + i % TS];
             __syncthreads();
             // X_I = S_Ik Pi for the own rows I != k
             for (int rr = 0; rr < nrows; ++rr) {
@@ -459,7 +508,9 @@ int launch_line_coeffs(sf_context* c) {
 int launch_factor2(sf_context* c, int sub0, int nsub_chunk, int Pf) {
     FactorArgs a;
     a.subs = c->d_subs;
-    a.fmap = c->d_fmap + (int64_t)sub0 * Pf;
+    a.sub0 = sub0;
+    a.nsub = sub0 + nsub_chunk;
+    a.pf = Pf;
     a.f0 = c->f0;
     a.al = c->alpha;
     a.factors = c->factors;
@@ -471,7 +522,7 @@ int launch_factor2(sf_context* c, int sub0, int nsub_chunk, int Pf) {
     a.lam = c->cfg.lambda;
     a.spin_limit = 1ll << 20;
     void* args[] = {&a};
-    if (hipLaunchCooperativeKernel((const void*)k_factor2, dim3(nsub_chunk * Pf), dim3(F2_THREADS), args, 0,
+    if (hipLaunchCooperativeKernel((const void*)k_factor2, dim3(8 * ((nsub_chunk + 7) / 8) * Pf), dim3(F2_THREADS), args, 0,
                                    c->stream) != hipSuccess)
         return SF_ERR_HIP;
     return SF_OK;

@@ -60,11 +60,8 @@ struct sf_context {
     int state;                      // 0 created, 1 assembled, 2 factored
     std::vector<sfdd::SubDesc> subs;
     sfdd::SubDesc* d_subs;
-    int32_t* d_wgmap;               // [2][nsub*maxP] workgroup -> (sub << 8 | rank):
-                                    // sweep launch order, then subdomain-major order
-    int sweep_grid;
+    int sweep_grid;                 // 8 * ceil(nsub / 8) * maxP workgroups (idle slots exit)
     int maxP;
-    int32_t* d_fmap;                // factor workgroup -> (sub << 8 | rank), subdomain-major
     int factor_pf;                  // workgroups per subdomain in the cooperative factor (0: one-WG factor)
     int factor_chunk;               // subdomains per cooperative factor launch
     uint32_t sweep_epoch;           // tag base for the sweep's published rows

@@ -27,7 +27,7 @@ constexpr int MAXMP = 512;
 
 struct SweepArgs {
     const SubDesc* subs;
-    const int32_t* wgmap;
+    int nsub;               // subdomains (mode 0) ; the single subdomain index (mode 1)
     const double* factors;
     double* work;
     const double* r;        // global residual [B][3][H][W] (mode 0)
@@ -41,51 +41,6 @@ struct SweepArgs {
     uint32_t epoch;         // tag base of this launch (published words carry epoch + phase)
     long long spin_limit;
 };
-
-// Thread 0 polls the counter with relaxed device-scope loads (they bypass the
-// non-coherent caches); the other waves wait at the barrier.  Bounded: on a
-// stall the wait records SF_ERR_DEVICE and every rank of every subdomain exits.
-__device__ __forceinline__ bool wait_count(uint32_t* cnt, uint32_t target, const SweepArgs& A, int sub,
-                                           int* sh_ok) {
-    // the poller is the first lane of the last wave, which issues no other
-    // global loads in a phase, so its polls never queue behind prefetches
-    if (threadIdx.x == SOLVE_THREADS - 64) {
-        long long n = 0;
-        int ok = 1;
-        while (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-            if (__hip_atomic_load(&A.status->code, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == SF_ERR_DEVICE ||
-                ++n > A.spin_limit) {
-                if (atomicCAS(&A.status->code, 0, SF_ERR_DEVICE) == 0) {
-                    A.status->sub = sub;
-                    A.status->row = (int64_t)target;
-                }
-                ok = 0;
-                break;
-            }
-            __builtin_amdgcn_s_sleep(1);
-        }
-        *sh_ok = ok;
-    }
-    __syncthreads();
-    return *sh_ok != 0;
-}
-
-// Every value another rank reads is stored with a relaxed device-scope atomic
-// (written through to the coherence point); waiting for all of them to be
-// acknowledged before the counter increment orders data before flag without
-// a cache-wide writeback.
-__device__ __forceinline__ void signal_count(uint32_t* cnt) {
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
-    if (threadIdx.x == SOLVE_THREADS - 64) __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ __forceinline__ void pub_store(double* p, double v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ double pub_load(const double* p) {
-    return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
 
 constexpr int MAXR = 16;   // block rows per rank (NT <= 16)
 constexpr int PF = 2;      // tiles per wave held in registers across the wait
@@ -157,6 +112,10 @@ __device__ __forceinline__ void tile_apply(const double tv[16], int I, int J, co
 // the next phase's data stream in while the control wave synchronises.  All
 // addressing is set up once in registers; nothing inside the phase loop loads
 // an address from memory (such a load would drain the prefetch queue).
+// Workgroup g is dispatched to XCD g % 8; the ranks of subdomain i are the
+// workgroups g with g % 8 == i % 8, so the tiles that two ranks of one
+// subdomain both read are shared through one L2.  Correctness does not depend
+// on the placement: the exchange uses device-scope accesses.
 __global__ void __launch_bounds__(SOLVE_THREADS) k_sweep(SweepArgs A) {
     constexpr int NW = SOLVE_THREADS / 64;
     constexpr int NWT = NW - 1;                    // tile waves
@@ -167,10 +126,22 @@ __global__ void __launch_bounds__(SOLVE_THREADS) k_sweep(SweepArgs A) {
     __shared__ double yw[NWT][MAXR * TS];
     __shared__ int sh_ok;
 
-    const int code = A.wgmap[blockIdx.x];
-    const int sub = code >> 8, rank = code & 255;
-    const SubDesc d = A.subs[sub];
     const int mode = A.mode;
+    int sub, rank;
+    {
+        const int x = blockIdx.x % 8, slot = blockIdx.x / 8;
+        if (mode == 1) {
+            if (x != 0) return;                        // idle slot
+            sub = A.nsub;
+            rank = slot;
+        } else {
+            const int P0 = A.subs[0].P;
+            sub = x + 8 * (slot / P0);
+            rank = slot % P0;
+            if (sub >= A.nsub) return;                 // idle slot
+        }
+    }
+    const SubDesc d = A.subs[sub];
     if (mode == 0 && A.done[d.pair]) return;   // uniform over the subdomain's ranks
     const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
     const bool ctl = wv == NWT;
@@ -420,7 +391,7 @@ const void* sweep_kernel() { return (const void*)k_sweep; }
 int launch_sweep(sf_context* c, double* U, const double* r, int single_sub, const double* b_local, double* x_local) {
     SweepArgs a;
     a.subs = c->d_subs;
-    a.wgmap = c->d_wgmap;
+    a.nsub = single_sub >= 0 ? single_sub : c->nsub;
     a.factors = c->factors;
     a.work = c->work;
     a.r = r;
@@ -440,22 +411,15 @@ int launch_sweep(sf_context* c, double* U, const double* r, int single_sub, cons
     int maxph = 0;
     for (const auto& d : c->subs) maxph = std::max(maxph, 2 * d.nt);
     c->sweep_epoch += (uint32_t)maxph + 2;
-    int grid = c->sweep_grid;
-    if (single_sub >= 0) {
-        hipLaunchKernelGGL(k_zero_u32, dim3((c->nsub + 255) / 256), dim3(256), 0, c->stream, c->counters, c->nsub);
-        if (hipGetLastError() != hipSuccess) return SF_ERR_HIP;
-        // second half of the map: subdomain-major order
-        a.wgmap = c->d_wgmap + (int64_t)c->nsub * c->maxP + (int64_t)single_sub * c->maxP;
-        grid = c->maxP;
-    }
+    const int grid = single_sub >= 0 ? 8 * c->maxP : c->sweep_grid;
+    const void* kern = (const void*)k_sweep;
+    void* args[] = {&a};
     if (c->maxP > 1) {
-        void* args[] = {&a};
-        if (hipLaunchCooperativeKernel((const void*)k_sweep, dim3(grid), dim3(SOLVE_THREADS), args, 0, c->stream) !=
-            hipSuccess)
+        if (hipLaunchCooperativeKernel(kern, dim3(grid), dim3(SOLVE_THREADS), args, 0, c->stream) != hipSuccess)
             return SF_ERR_HIP;
     } else {
-        hipLaunchKernelGGL(k_sweep, dim3(grid), dim3(SOLVE_THREADS), 0, c->stream, a);
-        if (hipGetLastError() != hipSuccess) return SF_ERR_HIP;
+        if (hipLaunchKernel(kern, dim3(grid), dim3(SOLVE_THREADS), args, 0, c->stream) != hipSuccess)
+            return SF_ERR_HIP;
     }
     return SF_OK;
 }
