@@ -4,13 +4,13 @@
  * Method: Gilliocq-Hirtz & Belhachmi, "A massively parallel multi-level
  * approach to a domain decomposition method for the optical flow estimation
  * with varying illumination".  The library solves the P1 finite-element
- * discretisation (Section 3.2) of the Euler-Lagrange system of functional
- * (BW2) (Section 2), Horn-Schunck regularisation with a per-element alpha and
+ * discretisation (Section 2.2) of the Euler-Lagrange system of functional
+ * (BW2) (Section 1), Horn-Schunck regularisation with a per-element alpha and
  * the Gennert-Negahdaripour illumination unknown m, by additive Schwarz with
- * overlapping rectangular subdomains and Dirichlet transmission (Section 4.2,
- * equation (schwarz)), each subdomain solved directly by a Cholesky
- * factorisation of its banded matrix; alpha is adapted with the residual
- * indicator of Section 3.3.
+ * overlapping rectangular subdomains and Dirichlet transmission (Section 3.2,
+ * equation (schwarz)), each subdomain solved directly by a block
+ * factorisation of its banded matrix over the grid lines; alpha is adapted
+ * with the residual indicator of Section 2.3.
  *
  * Conventions shared by every call:
  *   - W x H nodes, one per pixel centre; node (x, y), x = column, y = row.
@@ -59,7 +59,7 @@ typedef struct sf_config {
     int32_t parts_x;          /* tiles across, 1 <= parts_x <= W                  */
     int32_t parts_y;          /* tiles down,   1 <= parts_y <= H                  */
     int32_t overlap;          /* delta >= 0: nodes shared by neighbouring boxes   */
-    double  lambda;           /* regularisation of m (> 0), constant (Section 3.3) */
+    double  lambda;           /* regularisation of m (> 0), constant (Section 2.3) */
     double  sigma;            /* Gaussian presmoothing of the frames; must be 0   */
     int32_t factor_precision; /* SF_FP64                                          */
     int32_t band_tile;        /* workgroups per subdomain in a sweep; 0 = auto    */
@@ -67,7 +67,7 @@ typedef struct sf_config {
 
 typedef struct sf_context sf_context;
 
-/* Create a context for one geometry (Section 4.1: tile (p,q) owns nodes
+/* Create a context for one geometry (Section 3.1: tile (p,q) owns nodes
  * [floor(pW/Px), floor((p+1)W/Px)) x [floor(qH/Py), floor((q+1)H/Py));
  * its box extends every side interior to the image by floor(delta/2)
  * (left/top) or ceil(delta/2) (right/bottom) nodes).  `stream` is a
@@ -79,21 +79,22 @@ int sf_create(const sf_config* cfg, void* stream, sf_context** out);
 /* Release everything the context owns (NULL is accepted). */
 void sf_destroy(sf_context* ctx);
 
-/* Section 2 and 3.2: copy I0, I1 and alpha into the context and build the
+/* Section 1 and 2.2: copy I0, I1 and alpha into the context and build the
  * right-hand side F_i = -int f_t a phi_i, a = (f_x, f_y, -f), f = I0 (P1),
  * f_t = I1 - I0 (P1), integrated exactly.  Returns SF_NONFINITE if a frame
  * value is not finite and SF_ERR_INVALID if an alpha is not finite or <= 0.
  * Makes previous factors stale.                                             */
 int sf_assemble(sf_context* ctx, const double* I0, const double* I1, const double* alpha);
 
-/* Section 4.2, local problems: factor every subdomain matrix A_i = A[S_i,S_i]
+/* Section 3.2, local problems: factor every subdomain matrix A_i = A[S_i,S_i]
  * (ordering: lines along the shorter box side, 3 unknowns per node, band
- * half-width 3*ms+5).  Block Cholesky over the lines: S_t = A_tt -
- * B_t S_{t-1}^{-1} B_t^T, each S_t factored by Cholesky and stored inverted.
- * Returns SF_NOT_SPD (with sf_error_detail) if a pivot is not positive.    */
+ * half-width 3*ms+5).  Block LDL^T over the lines: S_t = A_tt -
+ * B_t S_{t-1}^{-1} B_t^T with S_0 = A_00; every S_t is inverted (SPD
+ * pivots checked) and stored as S_t^{-1}.  Returns SF_NOT_SPD (with
+ * sf_error_detail) if a pivot is not positive.                              */
 int sf_factor_subdomains(sf_context* ctx);
 
-/* Section 4.2, equation (schwarz), restricted additive form: from the
+/* Section 3.2, equation (schwarz), restricted additive form: from the
  * initial guess in U, repeat r = F - A U, relres = ||r||/||F|| (per pair);
  * stop a pair when relres <= rtol or after max_sweeps sweeps; otherwise
  * U[O_i] += (A_i^{-1} r[S_i])[O_i] for every subdomain i (O_i its owned
@@ -104,7 +105,7 @@ int sf_factor_subdomains(sf_context* ctx);
 int sf_schwarz_solve(sf_context* ctx, double* U, double rtol, int32_t max_sweeps,
                      int32_t* sweeps, double* relres);
 
-/* Section 3.3: residual indicator eta_K (flow components, alpha weights,
+/* Section 2.3: residual indicator eta_K (flow components, alpha weights,
  * element residual + half the flux jumps) and the decrease rule
  * alpha <- max(alpha / (1 + kappa max(eta/||eta||_inf - eta_thr, 0)), alpha_th)
  * with ||eta||_inf per pair.  alpha [B][H-1][W-1][2] is overwritten with

@@ -12,16 +12,16 @@ illumination"):
 
 * ``fem``      - P1 finite elements on the two-triangles-per-pixel mesh, global
                  assembly of the Euler-Lagrange system of functional (BW2)
-                 with rho = 0 (Section 3.1-3.2, equations (weakform) and
+                 with rho = 0 (Section 2.1-2.2, equations (weakform) and
                  (discret-form)); exact integration from the moment formula.
 * ``schwarz``  - image decomposition with overlap and the additive Schwarz
-                 iteration with Dirichlet transmission (Section 4.1-4.2,
+                 iteration with Dirichlet transmission (Section 3.1-3.2,
                  equation (schwarz)), in its restricted-additive form and in the
                  paper's Dirichlet form; subdomain solves by LAPACK banded
                  Cholesky; dense global solve for tiny grids.
 * ``adapt``    - residual error indicator eta_K (equation (errind)) and the
-                 alpha decrease rule (Section 3.3).
-* ``metrics``  - AAE and EE (Section 5).
+                 alpha decrease rule (Section 2.3).
+* ``metrics``  - AAE and EE (Section 4).
 
 Functions whose result the paper does not fix by any printed value or closed
 form are marked "parity unpinned" in their docstrings.

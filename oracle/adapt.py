@@ -2,7 +2,7 @@
 
 TEST INFRASTRUCTURE ONLY (see ``oracle/__init__``).
 
-Paper, Section 3.3, equation (errind) and the decrease rule that follows it:
+Paper, Section 2.3, equation (errind) and the decrease rule that follows it:
 
     eta_K = Lambda_K^{-1/2} h_K || R_K ||_{L2(K)^2}
             + 1/2 sum_{e in edges(K)} Lambda_e^{-1/2} h_e^{1/2} || [Lambda grad U . n_e]_e ||_{L2(e)^2}
@@ -144,7 +144,7 @@ def indicator(I0, I1, alpha, lam, U) -> np.ndarray:
 
 
 def update_alpha(alpha, eta, kappa: float, eta_thr: float, alpha_th: float):
-    """Decrease rule of Section 3.3; returns (new alpha, ||eta||_inf)."""
+    """Decrease rule of Section 2.3; returns (new alpha, ||eta||_inf)."""
     alpha = np.asarray(alpha, dtype=np.float64)
     eta = np.asarray(eta, dtype=np.float64)
     m = float(np.max(eta))

@@ -2,13 +2,13 @@
 
 TEST INFRASTRUCTURE ONLY (see ``oracle/__init__``).
 
-Model (paper, Section 2, functional (BW2) with rho = 0, and its Euler-Lagrange
+Model (paper, Section 1, functional (BW2) with rho = 0, and its Euler-Lagrange
 system): minimise over U = (u1, u2, m)
 
     E(U) = int (f_x u1 + f_y u2 + f_t - m f)^2
                + alpha (|grad u1|^2 + |grad u2|^2) + lambda |grad m|^2
 
-Discretisation (Section 3.2): the pixel grid, each pixel square cut into two
+Discretisation (Section 2.2): the pixel grid, each pixel square cut into two
 triangles by the diagonal drawn in figure "sch-mesh", continuous P1 elements
 for all three unknowns.  Readings taken where the text is silent:
 

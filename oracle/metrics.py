@@ -1,4 +1,4 @@
-"""Flow accuracy measures of Section 5 (oracle, FP64).
+"""Flow accuracy measures of Section 4 (oracle, FP64).
 
 TEST INFRASTRUCTURE ONLY (see ``oracle/__init__``).
 

@@ -2,7 +2,7 @@
 
 TEST INFRASTRUCTURE ONLY (see ``oracle/__init__``).
 
-The adaptive loop of Section 3.3 on the fixed pixel mesh (no remeshing):
+The adaptive loop of Section 2.3 on the fixed pixel mesh (no remeshing):
 solve, compute eta, decrease alpha, reassemble with the new alpha, refactor,
 solve again warm-started from the previous iterate; ``passes`` alpha updates
 give ``passes + 1`` solves.

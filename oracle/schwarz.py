@@ -2,8 +2,8 @@
 
 TEST INFRASTRUCTURE ONLY (see ``oracle/__init__``).
 
-Paper, Section 4.1 (one rectangular part of the image per processor, an
-overlap between neighbouring parts) and Section 4.2, equation (schwarz): in
+Paper, Section 3.1 (one rectangular part of the image per processor, an
+overlap between neighbouring parts) and Section 3.2, equation (schwarz): in
 sweep k every subdomain solves the full system restricted to its box with the
 natural (Neumann) condition on the image border and the Dirichlet condition
 U_i^k = U_j^{k-1} on the interface, all subdomains in parallel from the

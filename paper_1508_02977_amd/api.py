@@ -286,7 +286,7 @@ def sf_subdomain_solve(ctx: Context, sub: int, b, x) -> None:
            "sf_subdomain_solve", ctx)
 
 
-# ---- the adaptive pipeline (Section 3.3 loop on the fixed pixel mesh) ------
+# ---- the adaptive pipeline (Section 2.3 loop on the fixed pixel mesh) ------
 
 @dataclasses.dataclass
 class PipelineResult:

@@ -77,7 +77,7 @@ int check_config(const sf_config& k) {
     return SF_OK;
 }
 
-// Subdomains of all pairs, row-major tile order within a pair (Section 4.1):
+// Subdomains of all pairs, row-major tile order within a pair (Section 3.1):
 // tile (p, q) owns [cx_p, cx_{p+1}) x [cy_q, cy_{q+1}); its box grows by
 // floor(delta/2) on interior left/top sides and ceil(delta/2) on interior
 // right/bottom sides; lines run along the shorter box side.
@@ -198,7 +198,7 @@ int sf_create(const sf_config* cfg, void* stream, sf_context** out) {
     c->B = k.batch;
     if (hipGetDevice(&c->device) != hipSuccess) { sf_destroy(c); return SF_ERR_HIP; }
 
-    // ---- geometry (Section 4.1) --------------------------------------------
+    // ---- geometry (Section 3.1) --------------------------------------------
     c->subs = plan_subdomains(k);
     int maxmp = 0, min_nt = 1 << 30;
     for (const auto& d : c->subs) {

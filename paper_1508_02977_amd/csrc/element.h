@@ -1,6 +1,6 @@
 // P1 element algebra on the pixel mesh, device side.
 //
-// Paper, Section 3.2 (weak form, two triangles per pixel) and Section 2
+// Paper, Section 2.2 (weak form, two triangles per pixel) and Section 1
 // (functional (BW2), rho = 0): per element K the local operator is
 //   Lambda_c |K| grad phi_i . grad phi_j               (regulariser)
 // + int_K a_c a_d phi_i phi_j,  a = (f_x, f_y, -f)      (data term)

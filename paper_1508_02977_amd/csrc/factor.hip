@@ -1,6 +1,6 @@
 // Subdomain factorisation: block Cholesky of the banded subdomain matrix.
 //
-// Paper, Section 4.2: every subdomain problem is solved directly (the paper
+// Paper, Section 3.2: every subdomain problem is solved directly (the paper
 // uses sparse LU from UMFPACK/MUMPS).  Ordered line by line along the shorter
 // box side, A_i is block tridiagonal with m x m diagonal blocks A_tt and
 // sparse couplings B_t = A[line t, line t-1] (each unknown couples to the

@@ -1,6 +1,6 @@
 // Subdomain factorisation, cooperative form: Pf workgroups per subdomain.
 //
-// Same factor as factor.hip (paper, Section 4.2, local direct solves): for
+// Same factor as factor.hip (paper, Section 3.2, local direct solves): for
 // every line t of a subdomain, S_t = A_tt - B_t S_{t-1}^{-1} B_t^T and its
 // inverse, stored as 32x32 lower tiles.  Here the inverse is formed by the
 // blocked symmetric sweep (Gauss-Jordan without pivoting, valid because S_t

@@ -168,7 +168,7 @@ __global__ void k_converge(const double* __restrict__ partials, int npart, const
     }
 }
 
-// --- residual error indicator (Section 3.3) -------------------------------
+// --- residual error indicator (Section 2.3) -------------------------------
 //
 // eta_K = alpha_K^{-1/2} h_K |grad f| (int_K (s + f_t)^2)^{1/2}
 //       + 1/2 sum_e alpha_e^{-1/2} h_e |[alpha grad u . n_e]|,

@@ -1,4 +1,4 @@
-// Restricted additive Schwarz sweep (paper, Section 4.2, equation (schwarz)).
+// Restricted additive Schwarz sweep (paper, Section 3.2, equation (schwarz)).
 //
 // For every subdomain i (all pairs at once): e_i = A_i^{-1} r[S_i] and
 // U[O_i] += e_i[O_i], where r = F - A U of the current iterate.  With the

@@ -5,7 +5,7 @@ method's arithmetic (no gradients, no finite elements, no solver).  Both the
 GPU path's tests/benchmarks and the FP64 CPU oracle's tests take their inputs
 from here, so both sides see bit-identical frames.
 
-Conventions (paper, Section 2, brightness constancy with the Gennert-
+Conventions (paper, Section 1, brightness constancy with the Gennert-
 Negahdaripour illumination law, M = 1 + dm and a negligible translator T):
   * node (x, y) is the centre of pixel (x, y); x is the column, y the row;
     arrays are indexed ``[y, x]`` and stored row-major in float64;

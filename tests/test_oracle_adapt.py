@@ -1,4 +1,4 @@
-"""Pins of the oracle's error indicator and alpha rule (Section 3.3) and metrics."""
+"""Pins of the oracle's error indicator and alpha rule (Section 2.3) and metrics."""
 import numpy as np
 import pytest
 

@@ -27,7 +27,7 @@ def _duffy_rule(order=8):
 
 @pytest.mark.parametrize("order", [2, 3, 4])
 def test_moment_tables_match_quadrature(order):
-    # Section 3.2: exact P1 integrals; checked against numerical integration of
+    # Section 2.2: exact P1 integrals; checked against numerical integration of
     # products of barycentric functions on a triangle of area 1/2.
     P = fem.product_table(order, 0.5)
     rule = _duffy_rule()
@@ -67,7 +67,7 @@ def test_energy_identity_pins_A_and_F(lam):
 
 
 def test_symmetric_bitwise_and_spd_on_texture():
-    # Section 2 theorem (Lax-Milgram): the form is coercive on textured images,
+    # Section 1 theorem (Lax-Milgram): the form is coercive on textured images,
     # so the assembled matrix is symmetric positive definite.
     p = synth.make_pair("plain64", 2, W=14, H=12)
     al = synth.random_alpha(14, 12, 1)

@@ -1,4 +1,4 @@
-"""Pins of the oracle's decomposition and Schwarz iteration (Section 4)."""
+"""Pins of the oracle's decomposition and Schwarz iteration (Section 3)."""
 import numpy as np
 import pytest
 import scipy.sparse as sp
@@ -92,7 +92,7 @@ def test_single_subdomain_is_exact_in_one_sweep():
 
 
 def test_larger_overlap_converges_faster():
-    # Section 4.2 / Section 5: the rate improves with the size of the overlap.
+    # Section 3.2 / Section 4: the rate improves with the size of the overlap.
     p, A, F = _system(48, 40, noise=0.01)
     counts = []
     for d in (2, 4, 8):
