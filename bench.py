@@ -32,12 +32,17 @@ SWEEP_SOURCES = ("paper_1508_02977_amd/csrc/solve.hip", "paper_1508_02977_amd/cs
 
 
 def sweep_source_digest():
-    """SHA-256 over the sources the sweep kernel is built from."""
+    """SHA-256 over the code (comments and blank space removed) of the
+    sources the sweep kernel is built from."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for rel in SWEEP_SOURCES:
-        with open(os.path.join(ROOT, rel), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, rel)) as f:
+            code = f.read()
+        code = re.sub(r"/\*.*?\*/", " ", code, flags=re.S)
+        code = re.sub(r"//[^\n]*", " ", code)
+        h.update(" ".join(code.split()).encode())
     return h.hexdigest()
 
 
