@@ -62,7 +62,7 @@ typedef struct sf_config {
     double  lambda;           /* regularisation of m (> 0), constant (Section 2.3) */
     double  sigma;            /* Gaussian presmoothing of the frames; must be 0   */
     int32_t factor_precision; /* SF_FP64                                          */
-    int32_t band_tile;        /* workgroups per subdomain in a sweep; 0 = auto    */
+    int32_t band_tile;        /* sweep workgroups per chain of a subdomain; 0 = auto */
 } sf_config;
 
 typedef struct sf_context sf_context;
@@ -152,8 +152,10 @@ int sf_profile(sf_context* ctx, int32_t enable, double* ms, int64_t* launches);
 /* Number of subdomains over all pairs (B * parts_x * parts_y).             */
 int sf_num_subdomains(const sf_context* ctx);
 
-/* geom[11] (HOST): pair, box x0, x1, y0, y1 (half-open), owned x0, x1, y0,
- * y1, lines-are-columns flag, workgroups per subdomain used by a sweep.    */
+/* geom[13] (HOST): pair, box x0, x1, y0, y1 (half-open), owned x0, x1, y0,
+ * y1, lines-are-columns flag, sweep workgroups per chain, chains (1: lines
+ * eliminated top to bottom; 2: from both ends towards the middle line) and
+ * the middle line k (nt - 1 with one chain).                               */
 int sf_subdomain_geometry(const sf_context* ctx, int32_t sub, int32_t* geom);
 
 /* x = A_i^{-1} b for subdomain `sub` from its factors; b and x hold

@@ -252,8 +252,10 @@ def sf_plan(width, height, batch=1, parts_x=1, parts_y=1, overlap=0, lam=1.0):
 
 
 def _geom(g):
-    return dict(pair=g[0], box=(g[1], g[2], g[3], g[4]), own=(g[5], g[6], g[7], g[8]), cols=bool(g[9]),
-                P=g[10] if len(g) > 10 else None)
+    out = dict(pair=g[0], box=(g[1], g[2], g[3], g[4]), own=(g[5], g[6], g[7], g[8]), cols=bool(g[9]))
+    if len(g) > 10:
+        out.update(P=g[10], chains=g[11], kmid=g[12])
+    return out
 
 
 PROFILE_CLASSES = ("sweep", "factor", "residual", "other")
@@ -273,7 +275,7 @@ def sf_num_subdomains(ctx: Context) -> int:
 
 
 def sf_subdomain_geometry(ctx: Context, sub: int):
-    g = (c_int32 * 11)()
+    g = (c_int32 * 13)()
     _check(lib().sf_subdomain_geometry(ctx.handle, int(sub), ctypes.cast(g, c_void_p)), "sf_subdomain_geometry")
     return _geom(list(g))
 

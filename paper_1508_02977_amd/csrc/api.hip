@@ -5,6 +5,7 @@
 #include <new>
 
 #include "sfdd_internal.h"
+#include "factor2_layout.h"
 
 using sfdd::SubDesc;
 
@@ -208,8 +209,8 @@ int sf_create(const sf_config* cfg, void* stream, sf_context** out) {
     if (maxmp > 512) { sf_destroy(c); return SF_ERR_INVALID; }   // line matrices up to 512 x 512
     c->nsub = (int)c->subs.size();
 
-    // ---- workgroups per subdomain in a sweep --------------------------------
-    int ncu = 0, occ = 0;
+    // ---- launch shapes ---------------------------------------------------------
+    int ncu = 0, occ = 0, occ_b = 0;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess) {
         sf_destroy(c);
         return SF_ERR_HIP;
@@ -217,37 +218,62 @@ int sf_create(const sf_config* cfg, void* stream, sf_context** out) {
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, sfdd::sweep_kernel(), sfdd::SOLVE_THREADS, 0) !=
             hipSuccess || occ < 1)
         occ = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ_b, sfdd::sweep_kernel_small(), sfdd::SOLVE_THREADS, 0) ==
+            hipSuccess && occ_b >= 1)
+        occ = std::min(occ, occ_b);
     const int capacity = ncu * occ;
-    // one rank per 32-row block row of the line matrices when the chip has room
-    // workgroup slots: 8 XCD lanes x ceil(nsub / 8) subdomains per lane x P ranks
+    // workgroup slots: 8 XCD lanes x ceil(nsub / 8) subdomains per lane x groups x P ranks
     const int nsx = (c->nsub + 7) / 8;
-    int P = k.band_tile > 0 ? k.band_tile : std::max(1, std::min(capacity / (8 * nsx), min_nt));
-    P = std::min(P, min_nt);
-    P = std::min(P, 255);
-    if ((int64_t)P * 8 * nsx > capacity) P = std::max(1, capacity / (8 * nsx));
-    c->maxP = P;
-    c->sweep_grid = 8 * nsx * P;
 
-    // cooperative factor: ceil(NT/2) workgroups per subdomain, line matrices up to 384
+    // cooperative factor: ceil(NT/2) workgroups per chain, line matrices up to
+    // 384; two chains (twisted factorisation) when both chains of every
+    // subdomain fit co-resident in the sweep and 8 subdomains in the factor
     int maxnt = 0;
     for (const auto& d : c->subs) maxnt = std::max(maxnt, d.NT);
     int occ2 = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ2, sfdd::factor2_kernel(), 512, 0) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ2, sfdd::factor2_kernel(), sfdd::F2_WAVES * 64, 0) !=
+        hipSuccess)
         occ2 = 0;
     const int Pf = (maxnt + 1) / 2;
+    c->groups = 1;
     if (maxnt <= 12 && occ2 >= 1 && 8 * Pf <= ncu * occ2) {
         c->factor_pf = Pf;
+        if (16 * Pf <= ncu * occ2 && 16 * nsx <= capacity) c->groups = 2;
         // subdomains per launch: a multiple of 8 whose slots fit co-resident
-        c->factor_chunk = std::max(8, 8 * ((ncu * occ2) / (8 * Pf)));
+        c->factor_chunk = 8 * ((ncu * occ2) / (8 * c->groups * Pf));
     } else {
         c->factor_pf = 0;
         c->factor_chunk = 0;
+    }
+    const int G = c->groups;
+
+    // sweep workgroups per chain: at most one per 32-row block row of the line
+    // matrices, and the fewest that give the largest per-rank share
+    int P;
+    if (k.band_tile > 0) {
+        P = k.band_tile;
+    } else {
+        P = std::max(1, std::min(capacity / (8 * nsx * G), min_nt));
+        const int rows = (min_nt + P - 1) / P;
+        P = (min_nt + rows - 1) / rows;
+    }
+    P = std::min(P, min_nt);
+    P = std::min(P, 255);
+    if ((int64_t)P * 8 * nsx * G > capacity) P = std::max(1, capacity / (8 * nsx * G));
+    c->maxP = P;
+    c->sweep_grid = 8 * nsx * G * P;
+    c->sweep_rows = 0;
+    for (int r = 0; r < P; ++r) {
+        int R = 0;
+        while (2 * P * (R / 2) + ((R & 1) ? 2 * P - 1 - r : r) < maxnt) ++R;
+        c->sweep_rows = std::max(c->sweep_rows, R);
     }
 
     // ---- storage offsets -----------------------------------------------------
     int64_t foff = 0, woff = 0;
     for (auto& d : c->subs) {
         d.P = P;
+        d.kmid = G == 2 ? (d.nt - 1) / 2 : d.nt - 1;
         d.foff = foff;
         foff += (int64_t)d.nt * d.ntiles * sfdd::TSZ;
         d.boff = foff;
@@ -257,9 +283,9 @@ int sf_create(const sf_config* cfg, void* stream, sf_context** out) {
         d.woff = woff;
         woff += (int64_t)d.nt * d.mp;
         d.poff = woff;
-        woff += (int64_t)4 * d.mp;
-        d.soff = woff;   // factor workspace (one-WG factor: 3 mp^2; cooperative: 2 mp^2 + exchange slots)
-        woff += std::max<int64_t>((int64_t)3 * d.mp * d.mp, (int64_t)2 * d.mp * d.mp + 2ll * d.NT * sfdd::TSZ);
+        woff += (int64_t)12 * d.mp;
+        d.soff = woff;   // factor workspace (one-WG factor: 3 mp^2; cooperative: two chains)
+        woff += std::max<int64_t>((int64_t)3 * d.mp * d.mp, 2 * sfdd::f2_chain_doubles(d.mp, d.NT));
     }
     c->factor_doubles = foff;
     c->work_doubles = woff;
@@ -279,7 +305,7 @@ int sf_create(const sf_config* cfg, void* stream, sf_context** out) {
     rc |= dalloc(&c->relres_d, c->B);
     rc |= dalloc(&c->sweeps_d, c->B);
     rc |= dalloc(&c->done_d, c->B);
-    rc |= dalloc(&c->counters, c->nsub);
+    rc |= dalloc(&c->counters, 2 * (size_t)c->nsub);
     rc |= dalloc(&c->etamax_bits, c->B);
     rc |= dalloc(&c->flags_d, 4);
     rc |= dalloc(&c->factors, (size_t)c->factor_doubles);
@@ -339,8 +365,8 @@ int sf_factor_subdomains(sf_context* c) {
         SF_HIP(hipGetLastError());
         for (int s0 = 0; s0 < c->nsub; s0 += c->factor_chunk) {
             const int n = std::min(c->factor_chunk, c->nsub - s0);
-            hipLaunchKernelGGL(k_fill_i32, dim3((c->nsub + 255) / 256), dim3(256), 0, c->stream,
-                               (int32_t*)c->counters, c->nsub, 0);
+            hipLaunchKernelGGL(k_fill_i32, dim3((2 * c->nsub + 255) / 256), dim3(256), 0, c->stream,
+                               (int32_t*)c->counters, 2 * c->nsub, 0);
             SF_HIP(hipGetLastError());
             SF_TRY(sfdd::launch_factor2(c, s0, n, c->factor_pf));
         }
@@ -514,6 +540,8 @@ int sf_subdomain_geometry(const sf_context* c, int32_t sub, int32_t* g) {
     g[8] = d.oy1;
     g[9] = d.cols;
     g[10] = d.P;
+    g[11] = c->groups;
+    g[12] = d.kmid;
     return SF_OK;
 }
 

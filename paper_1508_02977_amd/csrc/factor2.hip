@@ -26,23 +26,26 @@
 #include <cmath>
 
 #include "element.h"
+#include "factor2_layout.h"
 #include "sfdd_internal.h"
 
 namespace sfdd {
 
-constexpr int F2_THREADS = 512;
+constexpr int F2_THREADS = 256;      // one wave per SIMD: 512 registers per wave
 constexpr int F2_NW = F2_THREADS / 64;
 constexpr int F2_MAXNT = 12;          // line matrices up to 384 x 384
 constexpr int LDP = 34;               // LDS row pitch (doubles): conflict-free 16x4 / 4x16 fragments
 constexpr int LTILE = TS * LDP;       // doubles per LDS tile
-constexpr int F2_MAXBLK = 7;          // accumulator blocks per wave: 4 * (NT + 1) / 8
+constexpr int F2_MAXBLK = 13;         // accumulator blocks per wave: 4 * (NT + 1) / 4
+static_assert(F2_NW == F2_WAVES && F2_MAXBLK == F2_BLOCKS, "factor workspace layout");
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
 struct FactorArgs {
     const SubDesc* subs;
     int sub0, nsub;           // subdomains [sub0, nsub) of this launch; sub0 % 8 == 0
-    int pf;                   // rank slots per subdomain (the largest ceil(NT / 2))
+    int pf;                   // rank slots per chain (the largest ceil(NT / 2))
+    int groups;               // chains per subdomain: 1 (top to bottom) or 2 (twisted)
     const double* f0;
     const double* al;
     double* factors;
@@ -190,6 +193,7 @@ __device__ __forceinline__ void f2_publish(const d4 (&acc)[F2_MAXBLK], double* x
             for (int q = 0; q < 4; ++q)
                 xstore(xb + (int64_t)J * TSZ + (16 * qj + cc) * TS + 16 * qi + cr + 4 * q, acc[b][q]);
         }
+        __builtin_amdgcn_sched_barrier(0);
     }
 }
 
@@ -199,27 +203,32 @@ __global__ void __launch_bounds__(F2_THREADS) k_factor2(FactorArgs A) {
     __shared__ double piv[LTILE];
     __shared__ double xr[2 * LTILE];
     __shared__ double adiag[F2_MAXNT * TS];
+    __shared__ double Cl[F2_MAXNT * TS * 6];             // couplings to the next line, [m][6]
     __shared__ int sh_ok;
 
     // workgroup g runs on XCD g % 8: the ranks of subdomain i are the slots
     // with g % 8 == i % 8, so its exchange stays inside one L2
-    const int slot = blockIdx.x / 8;
-    const int sub = A.sub0 + (int)(blockIdx.x % 8) + 8 * (slot / A.pf), rank = slot % A.pf;
+    const int slot = blockIdx.x / 8, per = A.groups * A.pf;
+    const int sub = A.sub0 + (int)(blockIdx.x % 8) + 8 * (slot / per);
+    const int chain = (slot % per) / A.pf, rank = slot % A.pf;
     if (sub >= A.nsub) return;                           // idle slot
     const SubDesc d = A.subs[sub];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int m = d.m, mp = d.mp, NT = d.NT, ms = d.ms;
     const int Pf = (NT + 1) / 2;
     if (rank >= Pf) return;                              // surplus slot of a short subdomain
-    const int64_t nn = (int64_t)A.W * A.H, ne = (int64_t)(A.W - 1) * (A.H - 1) * 2;
-    const double* f0 = A.f0 + d.pair * nn;
-    const double* al = A.al + d.pair * ne;
     double* Tout = A.factors + d.foff;
     double* Bst = A.factors + d.boff;
-    double* Sfull = A.work + d.soff;                    // mp x mp, full symmetric S_{t-1}^{-1}
-    double* T1 = Sfull + (int64_t)mp * mp;              // mp x mp, rows of B_t S_{t-1}^{-1}
-    double* xch = T1 + (int64_t)mp * mp;                // [2][NT][32x32] exchange slots
-    uint32_t* cnt = A.counters + sub;
+    // per chain: the full symmetric inverse of its latest line (mp x mp),
+    // [2][NT][32x32] exchange slots, then per rank and wave F2_MAXBLK 16x16
+    // blocks of build scratch
+    const int64_t cstride = f2_chain_doubles(mp, NT);
+    double* Sup = A.work + d.soff;                      // top chain: S_{t-1}^{-1}
+    double* Sdn = Sup + cstride;                        // bottom chain: S_{t+1}^{-1}
+    double* Sown = chain == 0 ? Sup : Sdn;
+    double* xch = Sown + (int64_t)mp * mp;
+    double* bscr = xch + 2ll * NT * TSZ + (int64_t)(rank * F2_NW + wv) * F2_MAXBLK * 256;
+    uint32_t* cnt = A.counters + 2 * sub + chain;
 
     // own block rows and tiles; tile list: row r first, then row NT-1-r
     const int rowA = rank, rowB = NT - 1 - rank;
@@ -228,16 +237,31 @@ __global__ void __launch_bounds__(F2_THREADS) k_factor2(FactorArgs A) {
     const int nblk = 4 * ntl;                 // 16x16 accumulator blocks
     d4 acc[F2_MAXBLK];
     // fragment coordinates of this lane inside a 16x16 block
-    const int fr = lane & 15, fk = lane >> 4;              // A/B operand: row fr, k-slice fk
-    const int cr = lane >> 4, cc = lane & 15;              // accumulator element q: row cr + 4q, col cc
+    // (recomputed from an opaque copy of the lane id in every pivot step, so
+    // that the compiler does not keep the dozens of loop-invariant LDS
+    // addresses of the unrolled block loops live across the whole line)
+    int fr = lane & 15, fk = lane >> 4;                    // A/B operand: row fr, k-slice fk
+    int cr = lane >> 4, cc = lane & 15;                    // accumulator element q: row cr + 4q, col cc
 
+    // Lines of the chains: the top chain (0) takes lines 0..k-1 and then the
+    // middle line k, the bottom chain (1) lines nt-1..k+1 (k = d.kmid; with one
+    // chain k = nt - 1).  Top line t: S_t = A_tt - B_t S_{t-1}^{-1} B_t^T.
+    // Bottom line t: S_t = A_tt - B_{t+1}^T S_{t+1}^{-1} B_{t+1}.  Middle: both
+    // terms, after the bottom chain has finished.
+    const int nt = d.nt, km = d.kmid;
+    const int nl1 = nt - 1 - km;                       // lines of the bottom chain
+    const int nlines = chain == 0 ? km + 1 : nl1;
     uint32_t phase = 0;
-    for (int t = 0; t < d.nt; ++t) {
+    for (int li = 0; li < nlines; ++li) {
+        const int t = chain == 0 ? li : nt - 1 - li;
+        const bool mid = chain == 0 && li == km;
+        const bool hup = chain == 0 && t > 0;                    // term of line t-1
+        const bool hdn = (chain == 1 || mid) && t < nt - 1;      // term of line t+1
         // ---------- phase 0 of the line: build own tiles of S_t -------------
-        // A_tt node blocks and B_t couplings of this line into LDS (colk area)
+        // A_tt node blocks and the couplings of this line into LDS
         double* Aself = colk;                    // [ms][9]
         double* Anext = colk + 9 * ms;           // [ms][9]: block (s, s+1)
-        double* Bl = colk + 18 * ms;             // [m][6]
+        double* Bl = colk + 18 * ms;             // [m][6]: B_t, nodes s-1, s of line t-1
         {
             const double* Ag = A.factors + d.aoff + (int64_t)t * ms * 18;
             for (int i = tid; i < 18 * ms; i += F2_THREADS) {
@@ -245,9 +269,21 @@ __global__ void __launch_bounds__(F2_THREADS) k_factor2(FactorArgs A) {
                 if (k < 9) Aself[9 * s + k] = Ag[i];
                 else       Anext[9 * s + k - 9] = Ag[i];
             }
-            const double* Bg = Bst + (int64_t)t * m * 6;
-            if (t > 0)
+            if (hup) {
+                const double* Bg = Bst + (int64_t)t * m * 6;
                 for (int i = tid; i < 6 * m; i += F2_THREADS) Bl[i] = Bg[i];
+            }
+            if (hdn) {
+                // B_{t+1}^T as rows of line t: node s couples to nodes s, s+1 of line t+1
+                const double* Bg = Bst + (int64_t)(t + 1) * m * 6;
+                for (int i = tid; i < 6 * m; i += F2_THREADS) {
+                    const int a = i / 6, k = i % 6, s = a / 3, c = a % 3, g = k % 3;
+                    double v = 0.0;
+                    if (k < 3) v = Bg[(3 * s + g) * 6 + 3 + c];
+                    else if (s + 1 < ms) v = Bg[(3 * (s + 1) + g) * 6 + c];
+                    Cl[i] = v;
+                }
+            }
         }
         __syncthreads();
         for (int a = tid; a < mp; a += F2_THREADS) adiag[a] = a < m ? Aself[9 * (a / 3) + 4 * (a % 3)] : 1.0;
@@ -259,17 +295,78 @@ __global__ void __launch_bounds__(F2_THREADS) k_factor2(FactorArgs A) {
             if (s == s2 + 1) return Anext[9 * s2 + 3 * c2 + c];
             return 0.0;
         };
-        // Own blocks of S_t = A_tt - B_t S_{t-1}^{-1} B_t^T.  A 16x16 block with
-        // rows R and columns C needs S_{t-1}^{-1} only on the node windows of R
-        // and C (<= 21 x 21 entries): each wave stages that window of the full
-        // symmetric inverse left by the previous line in its own LDS scratch,
-        // forms Z = S^{-1}[W(R), .] B_C^T, then the block Q = B_R Z.
-        if (t > 0 && !f2_wait(cnt, Pf * phase, A, sub, &sh_ok)) return;
+        // Own blocks of S_t = A_tt - (coupling terms).  A term C S^{-1} C^T with
+        // couplings C to the two nodes s-1+dn, s+dn of the neighbouring line
+        // (dn = 0: line t-1, dn = 1: line t+1) needs, for a 16x16 block with
+        // rows R and columns C, S^{-1} only on the node windows of R and C
+        // (<= 21 x 21 entries): each wave stages that window of the full
+        // symmetric inverse left by the neighbouring line in its own LDS
+        // scratch, forms Z = S^{-1}[W(R), .] C_C^T, then subtracts C_R Z.
+        if (li > 0 && !f2_wait(cnt, Pf * phase, A, sub, &sh_ok)) return;
+        if (mid && nl1 > 0 && !f2_wait(A.counters + 2 * sub + 1, (uint32_t)(Pf * (NT + 1) * nl1), A, sub, &sh_ok))
+            return;
         {
             constexpr int WN = 21;
             double* win = colk + 4608 + wv * (WN * WN + WN * 16);   // [WN][WN]
             double* zb = win + WN * WN;                             // [WN][16]
+            auto term = [&](const double* S, const double* cf, int dn, int r0, int c0, d4& v) {
+                const int wr0 = max(0, 3 * (r0 / 3 - 1 + dn)), wr1 = min(m, 3 * ((r0 + 15) / 3 + dn) + 3);
+                const int wc0 = max(0, 3 * (c0 / 3 - 1 + dn)), wc1 = min(m, 3 * ((c0 + 15) / 3 + dn) + 3);
+                const int nr = max(0, wr1 - wr0), nc = max(0, wc1 - wc0);
+                // (i) window of the neighbour's inverse
+                double wv_[(WN * WN + 63) / 64];
 #pragma unroll
+                for (int u = 0; u < (WN * WN + 63) / 64; ++u) {
+                    const int e = lane + 64 * u, i = e / WN, j = e % WN;
+                    wv_[u] = (i < nr && j < nc) ? xload(S + (int64_t)(wr0 + i) * mp + wc0 + j) : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < (WN * WN + 63) / 64; ++u) {
+                    const int e = lane + 64 * u;
+                    if (e < WN * WN) win[e] = wv_[u];
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                // (ii) Z[i][jc] = sum over the coupled nodes of column c0 + jc
+                for (int e = lane; e < WN * 16; e += 64) {
+                    const int i = e / 16, jc = e % 16, a2 = c0 + jc;
+                    double zv = 0.0;
+                    if (i < nr && a2 < m) {
+                        const int nlo = a2 / 3 - 1 + dn, nhi = a2 / 3 + dn;
+                        const double* c2 = cf + a2 * 6;
+#pragma unroll
+                        for (int g = 0; g < 3; ++g) {
+                            if (nlo >= 0) zv = fma(win[i * WN + 3 * nlo + g - wc0], c2[g], zv);
+                            if (nhi < ms) zv = fma(win[i * WN + 3 * nhi + g - wc0], c2[3 + g], zv);
+                        }
+                    }
+                    zb[e] = zv;
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                // (iii) this lane's 4 entries: v -= C_R Z
+                const int a2 = c0 + cc;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int a = r0 + cr + 4 * q;
+                    if (a < m && a2 < m) {
+                        const int nlo = a / 3 - 1 + dn, nhi = a / 3 + dn;
+                        const double* c1 = cf + a * 6;
+                        double u = 0.0;
+#pragma unroll
+                        for (int g = 0; g < 3; ++g) {
+                            if (nlo >= 0) u = fma(c1[g], zb[(3 * nlo + g - wr0) * 16 + cc], u);
+                            if (nhi < ms) u = fma(c1[3 + g], zb[(3 * nhi + g - wr0) * 16 + cc], u);
+                        }
+                        v[q] -= u;
+                    }
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            };
+            // one copy of the block code (not unrolled: the accumulators stay out
+            // of its register budget); blocks go through this wave's scratch
+#pragma unroll 1
             for (int b = 0; b < F2_MAXBLK; ++b) {
                 const int blk = wv + F2_NW * b;
                 d4 v = {0.0, 0.0, 0.0, 0.0};
@@ -278,72 +375,22 @@ __global__ void __launch_bounds__(F2_THREADS) k_factor2(FactorArgs A) {
                     f2_tile_of(blk >> 2, rowA, rowB, I, J);
                     const int qi = (blk >> 1) & 1, qj = blk & 1;
                     const int r0 = I * TS + 16 * qi, c0 = J * TS + 16 * qj;
-                    if (t > 0) {
-                        const int wr0 = max(0, 3 * (r0 / 3) - 3), wr1 = min(m, 3 * ((r0 + 15) / 3) + 3);
-                        const int wc0 = max(0, 3 * (c0 / 3) - 3), wc1 = min(m, 3 * ((c0 + 15) / 3) + 3);
-                        const int nr = max(0, wr1 - wr0), nc = max(0, wc1 - wc0);
-                        // (i) window of S_{t-1}^{-1}
-                        double wv_[(WN * WN + 63) / 64];
-#pragma unroll
-                        for (int u = 0; u < (WN * WN + 63) / 64; ++u) {
-                            const int e = lane + 64 * u, i = e / WN, j = e % WN;
-                            wv_[u] = (i < nr && j < nc) ? xload(Sfull + (int64_t)(wr0 + i) * mp + wc0 + j) : 0.0;
-                        }
-#pragma unroll
-                        for (int u = 0; u < (WN * WN + 63) / 64; ++u) {
-                            const int e = lane + 64 * u;
-                            if (e < WN * WN) win[e] = wv_[u];
-                        }
-                        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                        // (ii) Z[i][jc] = sum_{b2 in W(c0+jc)} win[i][b2 - wc0] B[c0+jc][b2]
-                        for (int e = lane; e < WN * 16; e += 64) {
-                            const int i = e / 16, jc = e % 16, a2 = c0 + jc;
-                            double zv = 0.0;
-                            if (i < nr && a2 < m) {
-                                const int s2 = a2 / 3;
-                                const double* cf = Bl + a2 * 6;
-#pragma unroll
-                                for (int g = 0; g < 3; ++g) {
-                                    if (s2 > 0) zv = fma(win[i * WN + 3 * (s2 - 1) + g - wc0], cf[g], zv);
-                                    zv = fma(win[i * WN + 3 * s2 + g - wc0], cf[3 + g], zv);
-                                }
-                            }
-                            zb[e] = zv;
-                        }
-                        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                    }
-                    // (iii) this lane's 4 entries: S = A - B_R Z
                     const int a2 = c0 + cc;
 #pragma unroll
                     for (int q = 0; q < 4; ++q) {
                         const int a = r0 + cr + 4 * q;
-                        double sv = 0.0;
-                        if (a < m && a2 < m) {
-                            sv = a_entry(a, a2);
-                            if (t > 0) {
-                                const int s = a / 3;
-                                const int wr0 = max(0, 3 * (r0 / 3) - 3);
-                                const double* cf = Bl + a * 6;
-                                double u = 0.0;
-#pragma unroll
-                                for (int g = 0; g < 3; ++g) {
-                                    if (s > 0) u = fma(cf[g], zb[(3 * (s - 1) + g - wr0) * 16 + cc], u);
-                                    u = fma(cf[3 + g], zb[(3 * s + g - wr0) * 16 + cc], u);
-                                }
-                                sv -= u;
-                            }
-                        } else if (a == a2) {
-                            sv = 1.0;              // identity on the padding
-                        }
-                        v[q] = sv;
+                        v[q] = (a < m && a2 < m) ? a_entry(a, a2) : (a == a2 ? 1.0 : 0.0);   // identity on the padding
                     }
-                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                    if (hup) term(Sup, Bl, 0, r0, c0, v);
+                    if (hdn) term(Sdn, Cl, 1, r0, c0, v);
                 }
-                acc[b] = v;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) bscr[(b * 4 + q) * 64 + lane] = v[q];
             }
+#pragma unroll
+            for (int b = 0; b < F2_MAXBLK; ++b)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) acc[b][q] = bscr[(b * 4 + q) * 64 + lane];
         }
         __syncthreads();   // LDS (Aself/Anext/Bl) is reused for the exchange column below
 
@@ -353,19 +400,27 @@ __global__ void __launch_bounds__(F2_THREADS) k_factor2(FactorArgs A) {
 
         // ---------- pivot steps -------------------------------------------------
         for (int k = 0; k < NT; ++k, ++phase) {
+            int tido = tid;
+            asm volatile("" : "+v"(tido));
+            fr = tido & 15;
+            fk = (tido >> 4) & 3;
+            cr = fk;
+            cc = fr;
             if (!f2_wait(cnt, Pf * phase, A, sub, &sh_ok)) return;
             const double* xb = xch + (int64_t)((phase - 1) & 1) * NT * TSZ;
-            {
-                constexpr int NL = F2_MAXNT * TSZ / F2_THREADS;
+            // the column in two batches of loads (register budget)
+#pragma unroll
+            for (int half = 0; half < 2; ++half) {
+                constexpr int NL = F2_MAXNT * TSZ / F2_THREADS / 2;
                 double tmp[NL];
 #pragma unroll
                 for (int u = 0; u < NL; ++u) {
-                    const int i = tid + F2_THREADS * u;
+                    const int i = tido + F2_THREADS * (u + NL * half);
                     tmp[u] = i < NT * TSZ ? xload(xb + i) : 0.0;
                 }
 #pragma unroll
                 for (int u = 0; u < NL; ++u) {
-                    const int i = tid + F2_THREADS * u;
+                    const int i = tido + F2_THREADS * (u + NL * half);
                     const int J = i / TSZ, r = (i / TS) % TS, c = i % TS;
                     if (i < NT * TSZ) colk[J * LTILE + r * LDP + c] = tmp[u];
                 }
@@ -374,6 +429,7 @@ __global__ void __launch_bounds__(F2_THREADS) k_factor2(FactorArgs A) {
             // Pi = S_kk^{-1}: unblocked symmetric sweep of the 32x32 pivot block,
             // in the registers of wave 0 (lane (j, h) holds rows 16h..16h+15 of
             // column j); the other waves wait at the barrier.
+            __builtin_amdgcn_sched_barrier(0);
             if (wv == 0) {
                 const int j = lane & 31, h = lane >> 5;
                 double v[16];
@@ -391,29 +447,28 @@ __global__ void __launch_bounds__(F2_THREADS) k_factor2(FactorArgs A) {
                     }
                     const double ip = 1.0 / pp;
                     const double rowp = __shfl(v[rp], j + 32 * hp, 64);     // S[p][j]
-                    double colp[16];
-#pragma unroll
-                    for (int r = 0; r < 16; ++r) colp[r] = __shfl(v[r], p + 32 * h, 64);   // S[16h+r][p]
 #pragma unroll
                     for (int r = 0; r < 16; ++r) {
                         const int i = 16 * h + r;
-                        if (i != p && j != p) v[r] = v[r] - colp[r] * rowp * ip;
+                        const double colp = __shfl(v[r], p + 32 * h, 64);   // S[16h+r][p]
+                        if (i != p && j != p) v[r] = v[r] - colp * rowp * ip;
                         else if (i == p && j == p) v[r] = -ip;
                         else if (i == p) v[r] = rowp * ip;
-                        else v[r] = colp[r] * ip;
+                        else v[r] = colp * ip;
                     }
                 }
                 // the sweep left -S_kk^{-1}
 #pragma unroll
                 for (int r = 0; r < 16; ++r) piv[(16 * h + r) * LDP + j] = -v[r];
             }
+            __builtin_amdgcn_sched_barrier(0);
             __syncthreads();
             // X_I = S_Ik Pi for the own rows I != k
             for (int rr = 0; rr < nrows; ++rr) {
                 const int I = rr == 0 ? rowA : rowB;
                 if (I == k) continue;
-                // 4 blocks of 16x16, one per wave (waves 0..3 for row A, 4..7 for row B)
-                if ((wv >> 2) == rr) {
+                // 4 blocks of 16x16 per row, one per wave
+                {
                     const int qi = (wv >> 1) & 1, qj = wv & 1;
                     d4 x = {0.0, 0.0, 0.0, 0.0};
                     #pragma unroll
@@ -461,15 +516,24 @@ __global__ void __launch_bounds__(F2_THREADS) k_factor2(FactorArgs A) {
                     #pragma unroll
                     for (int q = 0; q < 4; ++q) acc[b][q] = -piv[(16 * qi + cr + 4 * q) * LDP + 16 * qj + cc];
                 }
+                // keep the scheduler from hoisting the operand loads of all
+                // blocks at once (register budget)
+                __builtin_amdgcn_sched_barrier(0);
             }
             if (k + 1 < NT) {
                 f2_publish(acc, xch + (int64_t)(phase & 1) * NT * TSZ, k + 1, nblk, rowA, rowB, wv, cr, cc);
             } else {
                 // ---------- line done: blocks hold -S_t^{-1} ----------------------
+                // (through this wave's scratch, so that the store code is not
+                // unrolled over the accumulators)
 #pragma unroll
+                for (int b = 0; b < F2_MAXBLK; ++b)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) bscr[(b * 4 + q) * 64 + lane] = acc[b][q];
+#pragma unroll 1
                 for (int b = 0; b < F2_MAXBLK; ++b) {
                     const int blk = wv + F2_NW * b;
-                    if (blk >= nblk) continue;
+                    if (blk >= nblk) break;
                     int I, J;
                     f2_tile_of(blk >> 2, rowA, rowB, I, J);
                     const int qi = (blk >> 1) & 1, qj = blk & 1;
@@ -479,13 +543,13 @@ __global__ void __launch_bounds__(F2_THREADS) k_factor2(FactorArgs A) {
                     for (int q = 0; q < 4; ++q) {
                         const int r = 16 * qi + cr + 4 * q, c = 16 * qj + cc;
                         if (I == J && r < c) continue;           // diagonal tiles: mirror the lower half
-                        const double v = -acc[b][q];
+                        const double v = -bscr[(b * 4 + q) * 64 + lane];
                         tl[r * TS + c] = v;
                         if (I == J) tl[c * TS + r] = v;
-                        if (t + 1 < d.nt) {
+                        if (!mid) {                              // the next line of this chain needs it
                             const int ga = I * TS + r, gc = J * TS + c;
-                            xstore(Sfull + (int64_t)ga * mp + gc, v);
-                            xstore(Sfull + (int64_t)gc * mp + ga, v);
+                            xstore(Sown + (int64_t)ga * mp + gc, v);
+                            xstore(Sown + (int64_t)gc * mp + ga, v);
                         }
                     }
                 }
@@ -511,6 +575,7 @@ int launch_factor2(sf_context* c, int sub0, int nsub_chunk, int Pf) {
     a.sub0 = sub0;
     a.nsub = sub0 + nsub_chunk;
     a.pf = Pf;
+    a.groups = c->groups;
     a.f0 = c->f0;
     a.al = c->alpha;
     a.factors = c->factors;
@@ -522,7 +587,7 @@ int launch_factor2(sf_context* c, int sub0, int nsub_chunk, int Pf) {
     a.lam = c->cfg.lambda;
     a.spin_limit = 1ll << 20;
     void* args[] = {&a};
-    if (hipLaunchCooperativeKernel((const void*)k_factor2, dim3(8 * ((nsub_chunk + 7) / 8) * Pf), dim3(F2_THREADS), args, 0,
+    if (hipLaunchCooperativeKernel((const void*)k_factor2, dim3(8 * ((nsub_chunk + 7) / 8) * c->groups * Pf), dim3(F2_THREADS), args, 0,
                                    c->stream) != hipSuccess)
         return SF_ERR_HIP;
     return SF_OK;

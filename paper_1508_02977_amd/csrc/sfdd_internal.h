@@ -11,7 +11,7 @@ namespace sfdd {
 
 constexpr int TS = 32;          // factor tile edge (doubles)
 constexpr int TSZ = TS * TS;    // doubles per tile
-constexpr int SOLVE_THREADS = 512;
+constexpr int SOLVE_THREADS = 256;    // sweep: 3 tile waves + 1 control wave, one wave per SIMD
 constexpr int FACTOR_THREADS = 256;
 
 // One subdomain: a box of the pixel grid cut into lines along its shorter side.
@@ -26,13 +26,13 @@ struct SubDesc {
     int32_t cols;                      // 1: lines are columns
     int32_t ms, nt;                    // nodes per line, number of lines
     int32_t m, mp, NT, ntiles;         // line size, padded, tiles per side, tiles per line
-    int32_t P;                         // workgroups in a sweep
-    int32_t pad_;
+    int32_t P;                         // workgroups per chain in a sweep
+    int32_t kmid;                      // middle line of the twisted factorisation (nt - 1: one chain)
     int64_t foff;   // inverse Schur tiles: nt * ntiles * TSZ doubles
     int64_t boff;   // line couplings B_t: nt * m * 6 doubles (t = 0 unused)
     int64_t woff;   // sweep scratch: nt * mp doubles (forward results w_t)
-    int64_t soff;   // factor workspace: max(3 mp^2, 2 mp^2 + 2 NT TS^2) doubles
-    int64_t poff;   // sweep published rows: [2][mp] pairs of tagged 64-bit words (4 mp doubles)
+    int64_t soff;   // factor workspace: max(3 mp^2, 2 (mp^2 + 2 NT TS^2)) doubles
+    int64_t poff;   // sweep published rows: [2 chains][3 slots][mp] pairs of tagged 64-bit words
     int64_t aoff;   // line node blocks A[(t,s),(t,s)], A[(t,s),(t,s+1)]: nt * ms * 18 doubles
 };
 
@@ -60,8 +60,10 @@ struct sf_context {
     int state;                      // 0 created, 1 assembled, 2 factored
     std::vector<sfdd::SubDesc> subs;
     sfdd::SubDesc* d_subs;
-    int sweep_grid;                 // 8 * ceil(nsub / 8) * maxP workgroups (idle slots exit)
-    int maxP;
+    int sweep_grid;                 // 8 * ceil(nsub / 8) * groups * maxP workgroups (idle slots exit)
+    int maxP;                       // sweep workgroups per chain
+    int groups;                     // chains per subdomain: 2 = twisted factorisation, 1 = top to bottom
+    int sweep_rows;                 // largest number of block rows a sweep workgroup owns
     int factor_pf;                  // workgroups per subdomain in the cooperative factor (0: one-WG factor)
     int factor_chunk;               // subdomains per cooperative factor launch
     uint32_t sweep_epoch;           // tag base for the sweep's published rows
@@ -75,7 +77,7 @@ struct sf_context {
     double *relres_d;               // [B]
     int32_t *sweeps_d;              // [B]
     int32_t *done_d;                // [B]
-    uint32_t *counters;             // [nsub] sweep synchronisation
+    uint32_t *counters;             // [2 nsub] factor synchronisation, one per chain
     uint64_t *etamax_bits;          // [B]
     int32_t *flags_d;               // [4] input validation flags
     // subdomain storage
@@ -111,6 +113,7 @@ const void* factor2_kernel();
 int launch_sweep(sf_context* c, double* U, const double* r, int single_sub, const double* b_local,
                  double* x_local);
 const void* sweep_kernel();
+const void* sweep_kernel_small();
 // timing helpers (api.hip): bracket a launch of kernel class `kind`
 int prof_begin(sf_context* c, int kind);
 int prof_end(sf_context* c);

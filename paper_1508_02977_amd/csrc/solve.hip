@@ -35,54 +35,66 @@ struct SweepArgs {
     const int32_t* done;    // [B] converged pairs (mode 0)
     const double* b_local;  // local right-hand side (mode 1)
     double* x_local;        // local solution (mode 1)
-    uint32_t* counters;
     DevStatus* status;
     int W, H, mode;
+    int groups;             // 1: plain substitution; 2: twisted (both ends towards line kmid)
     uint32_t epoch;         // tag base of this launch (published words carry epoch + phase)
     long long spin_limit;
 };
 
 constexpr int MAXR = 16;   // block rows per rank (NT <= 16)
-constexpr int PF = 2;      // tiles per wave held in registers across the wait
 
 // Tile (I, J) of the block row of symmetric S: lower tile (I,J) if J <= I,
-// else the lower tile (J,I) used transposed.  Lane (j, h) holds column j of
-// rows 16h..16h+15 of the stored tile.
-__device__ __forceinline__ void load_tile(const double* __restrict__ Tl, int I, int J, double tv[16]) {
+// else the lower tile (J,I) used transposed.  Lane (c, h), c = lane % 16,
+// h = lane / 16, holds columns 2c, 2c+1 of rows 8h..8h+7 of the stored tile:
+// tv[2i] = T[8h+i][2c], tv[2i+1] = T[8h+i][2c+1] (16-byte loads, a wave
+// instruction reads 4 rows of 256 bytes).
+__device__ __forceinline__ int64_t tile_lane_offset(int I, int J) {
     const int lane = threadIdx.x & 63;
-    const int j = lane & 31, h = lane >> 5;
     const int k = J <= I ? I * (I + 1) / 2 + J : J * (J + 1) / 2 + I;
-    const double* T = Tl + (int64_t)k * TSZ + (16 * h) * TS + j;
+    return (int64_t)k * TSZ + (8 * (lane >> 4)) * TS + 2 * (lane & 15);
+}
+
+__device__ __forceinline__ void load_tile(const double* __restrict__ T, double tv[16]) {
 #pragma unroll
-    for (int i = 0; i < 16; ++i) tv[i] = T[i * TS];
+    for (int i = 0; i < 8; ++i) {
+        const double2 v = *reinterpret_cast<const double2*>(T + i * TS);
+        tv[2 * i] = v.x;
+        tv[2 * i + 1] = v.y;
+    }
 }
 
 // y_I += (tile) z_J for one tile of the block row, into the wave's row buffer y[32].
 __device__ __forceinline__ void tile_apply(const double tv[16], int I, int J, const double* z, double* y) {
     const int lane = threadIdx.x & 63;
-    const int j = lane & 31, h = lane >> 5;
+    const int c = lane & 15, h = lane >> 4;
     if (J >= I) {
         // stored (J, I) used transposed, or the symmetric diagonal tile:
-        // y_I[j] += sum_r T[r][j] zJ[r], rows r = 16h..16h+15 of this lane
-        const double* zr = z + J * TS + 16 * h;
-        double s = 0.0;
+        // y_I[col] += sum_r T[r][col] zJ[r] over this lane's rows, then over the 4 row groups
+        const double* zr = z + J * TS + 8 * h;
+        double s0 = 0.0, s1 = 0.0;
 #pragma unroll
-        for (int i = 0; i < 16; ++i) s = fma(tv[i], zr[i], s);
-        s += __shfl_xor(s, 32, 64);
-        if (h == 0) y[j] += s;
-    } else {
-        // stored (I, J): y_I[r] += sum_j T[r][j] zJ[j]; 16 row products per lane
-        // reduced over the 32 lanes of the half (transpose-reduce: xor 16, 8, 4, 2, then 1)
-        const double zj = z[J * TS + j];
-        double p[16];
-#pragma unroll
-        for (int i = 0; i < 16; ++i) p[i] = tv[i] * zj;
-        const int b4 = (j >> 4) & 1, b3 = (j >> 3) & 1, b2 = (j >> 2) & 1, b1 = (j >> 1) & 1;
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const double keep = b4 ? p[q + 8] : p[q], send = b4 ? p[q] : p[q + 8];
-            p[q] = keep + __shfl_xor(send, 16, 64);
+        for (int i = 0; i < 8; ++i) {
+            s0 = fma(tv[2 * i], zr[i], s0);
+            s1 = fma(tv[2 * i + 1], zr[i], s1);
         }
+        s0 += __shfl_xor(s0, 16, 64);
+        s1 += __shfl_xor(s1, 16, 64);
+        s0 += __shfl_xor(s0, 32, 64);
+        s1 += __shfl_xor(s1, 32, 64);
+        if (h == 0) {
+            y[2 * c] += s0;
+            y[2 * c + 1] += s1;
+        }
+    } else {
+        // stored (I, J): y_I[r] += sum_col T[r][col] zJ[col]; 8 row partials per
+        // lane reduced over the 16 lanes of the row group (transpose-reduce:
+        // xor 8, 4, 2, then 1)
+        const double z0 = z[J * TS + 2 * c], z1 = z[J * TS + 2 * c + 1];
+        double p[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) p[i] = fma(tv[2 * i], z0, tv[2 * i + 1] * z1);
+        const int b3 = (c >> 3) & 1, b2 = (c >> 2) & 1, b1 = (c >> 1) & 1;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const double keep = b3 ? p[q + 4] : p[q], send = b3 ? p[q] : p[q + 4];
@@ -98,45 +110,70 @@ __device__ __forceinline__ void tile_apply(const double tv[16], int I, int J, co
             p[0] = keep + __shfl_xor(send, 2, 64);
         }
         p[0] += __shfl_xor(p[0], 1, 64);
-        if ((j & 1) == 0) y[16 * h + 8 * b4 + 4 * b3 + 2 * b2 + b1] += p[0];
+        if ((c & 1) == 0) y[8 * h + 4 * b3 + 2 * b2 + b1] += p[0];
     }
 }
 
-// Phase q of a sweep: forward lines 0..nt-1, then backward lines nt-2..0.
-// Waves 0..NW-2 ("tile waves") hold this rank's tiles of the line matrix and
-// the right-hand side terms; the last wave ("control wave") does all the
-// latency-critical traffic: it polls the counter, gathers the published rows,
-// finishes and publishes this rank's rows and signals.  Global loads of a wave
-// complete in order, so keeping the large tile prefetch (issued by the tile
-// waves right after their compute, one phase ahead) off the control wave lets
-// the next phase's data stream in while the control wave synchronises.  All
-// addressing is set up once in registers; nothing inside the phase loop loads
-// an address from memory (such a load would drain the prefetch queue).
+// i-th own block row of rank `rank` among P ranks: rows are dealt in
+// boustrophedon order (0..P-1, then P-1..0, ...), so with NT <= 2P a rank owns
+// the pair (r, 2P-1-r) and every rank meets about the same number of tiles
+// that it applies directly and transposed.  Row numbers increase with i.
+__device__ __forceinline__ int own_row(int i, int rank, int P) {
+    return 2 * P * (i >> 1) + ((i & 1) ? 2 * P - 1 - rank : rank);
+}
+
+// Twisted sweep.  The lines of a subdomain are eliminated from both ends
+// towards the middle line k (the factor stores S_t^{-1} of the top chain for
+// t < k, of the bottom chain for t > k and of the middle line for t = k):
+//   top    (group 0):  w_t = S_t^{-1} (r_t - B_t w_{t-1}),          t = 0..k-1
+//   bottom (group 1):  w_t = S_t^{-1} (r_t - B_{t+1}^T w_{t+1}),    t = nt-1..k+1
+//   middle (both):     x_k = S_k^{-1} (r_k - B_k w_{k-1} - B_{k+1}^T w_{k+1})
+//   top back:          x_t = w_t - S_t^{-1} B_{t+1}^T x_{t+1},      t = k-1..0
+//   bottom back:       x_t = w_t - S_t^{-1} B_t x_{t-1},            t = k+1..nt-1
+// so a sweep takes 2 max(k, nt-1-k) + 1 dependent phases instead of 2 nt - 1.
+// With one group (k = nt - 1) this is the plain forward/backward substitution.
+// Each group has P ranks (workgroups); both groups compute the middle line
+// (group 0 stores it).
+//
+// Within a rank, waves 0..NW-2 ("tile waves") hold its tiles of the line
+// matrix and the right-hand side terms; the last wave ("control wave") does
+// the latency-critical traffic: it gathers the rows the phase needs, finishes
+// and publishes this rank's rows.  Global loads of a wave complete in order,
+// so keeping the tile prefetch (issued by the tile waves right after their
+// compute, one phase ahead) off the control wave lets the next phase's data
+// stream in while the control wave synchronises.  All addressing is set up in
+// registers; nothing inside the phase loop loads an address from memory (such
+// a load would drain the prefetch queue).
 // Workgroup g is dispatched to XCD g % 8; the ranks of subdomain i are the
 // workgroups g with g % 8 == i % 8, so the tiles that two ranks of one
 // subdomain both read are shared through one L2.  Correctness does not depend
 // on the placement: the exchange uses device-scope accesses.
+template <int RMAX, int PF, int LMAX>
 __global__ void __launch_bounds__(SOLVE_THREADS) k_sweep(SweepArgs A) {
     constexpr int NW = SOLVE_THREADS / 64;
     constexpr int NWT = NW - 1;                    // tile waves
     constexpr int CW0 = NWT * 64;                  // first thread of the control wave
-    constexpr int NRC = MAXR * TS / 64;            // own rows per control lane
-    __shared__ double z[MAXMP];
-    __shared__ double full[MAXMP];
-    __shared__ double yw[NWT][MAXR * TS];
+    constexpr int NRC = (RMAX * TS + 63) / 64;     // own rows per control lane
+    constexpr int RPT = (LMAX + CW0 - 1) / CW0;    // line rows per tile-wave thread (mp <= LMAX)
+    __shared__ double z[LMAX];
+    __shared__ double vup[LMAX];                   // vector of the line above (t - 1)
+    __shared__ double vdn[LMAX];                   // vector of the line below (t + 1)
+    __shared__ double yw[NWT][RMAX * TS];
     __shared__ int sh_ok;
 
-    const int mode = A.mode;
-    int sub, rank;
+    const int mode = A.mode, G = A.groups;
+    int sub, grp, rank;
     {
         const int x = blockIdx.x % 8, slot = blockIdx.x / 8;
+        const int P0 = A.subs[0].P;
         if (mode == 1) {
             if (x != 0) return;                        // idle slot
             sub = A.nsub;
-            rank = slot;
+            grp = slot / P0;
+            rank = slot % P0;
         } else {
-            const int P0 = A.subs[0].P;
-            sub = x + 8 * (slot / P0);
+            sub = x + 8 * (slot / (G * P0));
+            grp = (slot % (G * P0)) / P0;
             rank = slot % P0;
             if (sub >= A.nsub) return;                 // idle slot
         }
@@ -145,21 +182,38 @@ __global__ void __launch_bounds__(SOLVE_THREADS) k_sweep(SweepArgs A) {
     if (mode == 0 && A.done[d.pair]) return;   // uniform over the subdomain's ranks
     const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
     const bool ctl = wv == NWT;
-    const int P = d.P, m = d.m, mp = d.mp, ms = d.ms, nt = d.nt, NT = d.NT;
-    const int R = (NT - rank + P - 1) / P;         // block rows of this rank: rank + P*i, i < R
+    const int P = d.P, m = d.m, mp = d.mp, ms = d.ms, nt = d.nt, NT = d.NT, km = d.kmid;
+    int R = 0;                                     // own block rows: own_row(i), i < R
+    while (R < RMAX && own_row(R, rank, P) < NT) ++R;
+    if (R == 0) return;                            // no rows (P > NT): nothing to do
     const int ntw = R * NT;                        // tiles per phase for this rank
     const int nrow = R * TS;                       // rows finished by this rank
+    const int L = grp == 0 ? km : nt - 1 - km;     // lines of this group's chain
+    const int nphase = 2 * L + 1;
     const int64_t nn = (int64_t)A.W * A.H;
     const int64_t tstride = (int64_t)d.ntiles * TSZ;       // tiles of one line
     const double* __restrict__ Tb = A.factors + d.foff;
     const double* __restrict__ Bb = A.factors + d.boff;
     double* __restrict__ wst = A.work + d.woff;            // w_t, then x_t, of this rank's rows
-    // published rows: [2][mp] pairs of 64-bit words (tag << 32 | half of the double)
+    // published rows: per group [3][mp] pairs of 64-bit words (tag << 32 | half
+    // of a double); slots 0/1 by phase parity, slot 2 for the last forward line
     uint64_t* __restrict__ pub = reinterpret_cast<uint64_t*>(A.work + d.poff);
+    uint64_t* __restrict__ mypub = pub + (int64_t)grp * 6 * mp;
     DevStatus* st = A.status;
     const long long spin = A.spin_limit;
-    const int nphase = 2 * nt - 1;
     const uint32_t epoch = A.epoch;
+    auto tag_of = [&](int g, int q) -> uint32_t { return epoch + 2u * (uint32_t)q + (uint32_t)g; };
+    auto slot_of = [&](int g, int q) -> const uint64_t* {
+        const int Lg = g == 0 ? km : nt - 1 - km;
+        const int sl = q == Lg - 1 ? 2 : (q & 1);
+        return pub + ((int64_t)g * 3 + sl) * 2 * mp;
+    };
+    // phase q -> line, kind, couplings
+    auto line_of = [&](int q) -> int {
+        if (q < L) return grp == 0 ? q : nt - 1 - q;
+        if (q == L) return km;
+        return grp == 0 ? 2 * L - q : km + (q - L);
+    };
 
     // local unknown a of line t sits at global index gbase(a) + t * gstep
     const int64_t gstep = d.cols ? 1 : (int64_t)A.W;
@@ -168,62 +222,112 @@ __global__ void __launch_bounds__(SOLVE_THREADS) k_sweep(SweepArgs A) {
         const int x = d.cols ? d.bx0 : d.bx0 + s, y = d.cols ? d.by0 + s : d.by0;
         return ((int64_t)d.pair * 3 + c) * nn + (int64_t)y * A.W + x;
     };
-    // right-hand side of row a = tid
-    const double* __restrict__ rsrc = mode == 1 ? A.b_local + tid : A.r + (tid < m ? gbase(tid) : 0);
+    // right-hand side of the rows a = tid + CW0 * j of this thread
+    const double* __restrict__ rsrc[RPT];
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+        const int a = tid + CW0 * j;
+        rsrc[j] = mode == 1 ? A.b_local + a : A.r + (a < m ? gbase(a) : 0);
+    }
     const int64_t rstep = mode == 1 ? m : gstep;
-    // B coefficient rows of this thread (forward: row a; backward: rows 3s.., 3s+3..)
-    const int zs = tid / 3, ze = tid % 3;
-    // this thread's tiles (fixed for all lines): offsets inside a line
-    const int tj = lane & 31, th = lane >> 5;
+    // this thread's prefetched tiles (fixed for all lines): offsets inside a line
     int64_t toff[PF];
 #pragma unroll
     for (int p = 0; p < PF; ++p) {
-        const int qt = wv + NWT * p;
-        const int I = rank + P * (qt / NT), J = qt % NT;
-        const int k = J <= I ? I * (I + 1) / 2 + J : J * (J + 1) / 2 + I;
-        toff[p] = (int64_t)k * TSZ + (16 * th) * TS + tj;
+        const int qt = min(wv + NWT * p, ntw - 1);
+        toff[p] = tile_lane_offset(own_row(qt / NT, rank, P), qt % NT);
     }
     // own rows of the control lanes
     int crow[NRC];
 #pragma unroll
     for (int i = 0; i < NRC; ++i) {
         const int k = tid - CW0 + 64 * i;
-        crow[i] = k < nrow ? (rank + P * (k / TS)) * TS + k % TS : -1;
+        crow[i] = k < nrow ? own_row(k / TS, rank, P) * TS + k % TS : -1;
     }
 
     double pre[PF][16];
-    double pr = 0.0, pb[6] = {0, 0, 0, 0, 0, 0};
+    double pr[RPT], pbu[RPT][6], pbd[RPT][6];
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+        pr[j] = 0.0;
+#pragma unroll
+        for (int e = 0; e < 6; ++e) pbu[j][e] = pbd[j][e] = 0.0;
+    }
+    // coupling terms of phase q: up = B_t (rows of line t, nodes s-1, s of
+    // line t-1), dn = B_{t+1}^T (nodes s, s+1 of line t+1)
+    auto has_up = [&](int q, int t) -> bool {
+        return (q < L) ? (grp == 0 && t > 0) : (q == L ? t > 0 : grp == 1);
+    };
+    auto has_dn = [&](int q, int t) -> bool {
+        return (q < L) ? (grp == 1 && t < nt - 1) : (q == L ? t < nt - 1 : grp == 0);
+    };
     auto prefetch = [&](int q) {                    // tile waves
-        const int t = q < nt ? q : 2 * nt - 2 - q;
-        if (tid < m) {                              // z terms first: needed earlier
-            if (q < nt) {
-                pr = rsrc[t * rstep];
-                if (t > 0) {
-                    const double* cf = Bb + ((int64_t)t * m + tid) * 6;
+        const int t = line_of(q);
+        const bool hu = has_up(q, t), hd = has_dn(q, t);
 #pragma unroll
-                    for (int e = 0; e < 6; ++e) pb[e] = cf[e];
+        for (int j = 0; j < RPT; ++j) {             // z terms first: needed earlier
+            const int a = tid + CW0 * j, zs = a / 3, ze = a % 3;
+            if (a < m) {
+                if (q <= L) pr[j] = rsrc[j][t * rstep];
+                if (hu) {
+                    const double* cf = Bb + ((int64_t)t * m + a) * 6;
+#pragma unroll
+                    for (int e = 0; e < 6; ++e) pbu[j][e] = cf[e];
                 }
-            } else {
-                const double* Bt = Bb + (int64_t)(t + 1) * m * 6;
+                if (hd) {
+                    const double* Bt = Bb + (int64_t)(t + 1) * m * 6;
 #pragma unroll
-                for (int c = 0; c < 3; ++c) pb[c] = Bt[(int64_t)(3 * zs + c) * 6 + 3 + ze];
+                    for (int c = 0; c < 3; ++c) pbd[j][c] = Bt[(int64_t)(3 * zs + c) * 6 + 3 + ze];
 #pragma unroll
-                for (int c = 0; c < 3; ++c) pb[3 + c] = zs + 1 < ms ? Bt[(int64_t)(3 * (zs + 1) + c) * 6 + ze] : 0.0;
+                    for (int c = 0; c < 3; ++c)
+                        pbd[j][3 + c] = zs + 1 < ms ? Bt[(int64_t)(3 * (zs + 1) + c) * 6 + ze] : 0.0;
+                }
             }
         }
         const double* Tl = Tb + (int64_t)t * tstride;
 #pragma unroll
         for (int p = 0; p < PF; ++p)
-            if (wv + NWT * p < ntw) {
+            if (wv + NWT * p < ntw) load_tile(Tl + toff[p], pre[p]);
+    };
+    // control wave: poll the published words of (group g, phase q) into dst
+    auto gather = [&](int g, int q, double* dst) -> int {
+        const uint32_t tag = tag_of(g, q);
+        const uint64_t* pbuf = slot_of(g, q);
+        constexpr int NG = LMAX / 64;
+        uint64_t lo[NG], hi[NG];
+        unsigned pending = 0;
 #pragma unroll
-                for (int i = 0; i < 16; ++i) pre[p][i] = Tl[toff[p] + i * TS];
-            }
+        for (int u = 0; u < NG; ++u)
+            if (lane + 64 * u < mp) pending |= 1u << u;
+        long long n = 0;
+        while (pending) {
+#pragma unroll
+            for (int u = 0; u < NG; ++u)
+                if (pending & (1u << u)) {
+                    const int a = lane + 64 * u;
+                    lo[u] = __hip_atomic_load(const_cast<uint64_t*>(pbuf + 2 * a), __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT);
+                    hi[u] = __hip_atomic_load(const_cast<uint64_t*>(pbuf + 2 * a + 1), __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT);
+                }
+#pragma unroll
+            for (int u = 0; u < NG; ++u)
+                if ((pending & (1u << u)) && (uint32_t)(lo[u] >> 32) == tag && (uint32_t)(hi[u] >> 32) == tag) {
+                    dst[lane + 64 * u] = __longlong_as_double((long long)((hi[u] << 32) | (lo[u] & 0xffffffffull)));
+                    pending &= ~(1u << u);
+                }
+            if (!pending) break;
+            if (++n > spin || __hip_atomic_load(&st->code, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == SF_ERR_DEVICE)
+                return 0;
+            __builtin_amdgcn_s_sleep(1);
+        }
+        return 1;
     };
     double pw[NRC];
 #pragma unroll
     for (int i = 0; i < NRC; ++i) pw[i] = 0.0;
 
-    for (int i = tid; i < NWT * MAXR * TS; i += SOLVE_THREADS) (&yw[0][0])[i] = 0.0;
+    for (int i = tid; i < NWT * RMAX * TS; i += SOLVE_THREADS) (&yw[0][0])[i] = 0.0;
     if (!ctl) prefetch(0);
     // Phase structure (B = workgroup barrier):
     //   control wave: [gather(q)] B z B  .  B [finish, publish(q)]
@@ -234,47 +338,18 @@ __global__ void __launch_bounds__(SOLVE_THREADS) k_sweep(SweepArgs A) {
     // transfers the data; no separate flag, counter or store acknowledgement.
     __syncthreads();
     for (int q = 0; q < nphase; ++q) {
-        const int t = q < nt ? q : 2 * nt - 2 - q;
-        const bool fwd = q < nt;
-        if (q > 0) {
+        const int t = line_of(q);
+        const bool back = q > L;
+        const bool up = has_up(q, t), dn = has_dn(q, t);
+        if (up || dn) {
             if (ctl) {
-                // each lane needs mp/64 entries: issue all loads, then re-poll
-                // only the entries whose tags are not there yet
-                const uint32_t tag = epoch + (uint32_t)(q - 1);
-                const uint64_t* pbuf = pub + (int64_t)((q - 1) & 1) * mp * 2;
-                constexpr int NG = MAXMP / 64;
-                uint64_t lo[NG], hi[NG];
-                unsigned pending = 0;
-#pragma unroll
-                for (int g = 0; g < NG; ++g)
-                    if (lane + 64 * g < mp) pending |= 1u << g;
-                long long n = 0;
                 int ok = 1;
-                while (pending) {
-#pragma unroll
-                    for (int g = 0; g < NG; ++g)
-                        if (pending & (1u << g)) {
-                            const int a = lane + 64 * g;
-                            lo[g] = __hip_atomic_load(const_cast<uint64_t*>(pbuf + 2 * a), __ATOMIC_RELAXED,
-                                                      __HIP_MEMORY_SCOPE_AGENT);
-                            hi[g] = __hip_atomic_load(const_cast<uint64_t*>(pbuf + 2 * a + 1), __ATOMIC_RELAXED,
-                                                      __HIP_MEMORY_SCOPE_AGENT);
-                        }
-#pragma unroll
-                    for (int g = 0; g < NG; ++g)
-                        if ((pending & (1u << g)) && (uint32_t)(lo[g] >> 32) == tag && (uint32_t)(hi[g] >> 32) == tag) {
-                            full[lane + 64 * g] = __longlong_as_double((long long)((hi[g] << 32) | (lo[g] & 0xffffffffull)));
-                            pending &= ~(1u << g);
-                        }
-                    if (!pending) break;
-                    if (++n > spin ||
-                        __hip_atomic_load(&st->code, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == SF_ERR_DEVICE) {
-                        ok = 0;
-                        break;
-                    }
-                    __builtin_amdgcn_s_sleep(1);
+                if (q == L) {                      // middle: last forward vectors of both chains
+                    if (up) ok = gather(0, km - 1, vup);
+                    if (dn && ok) ok = gather(1, nt - 2 - km, vdn);
+                } else {
+                    ok = gather(grp, q - 1, up ? vup : vdn);
                 }
-                // wave-wide outcome
                 const int all_ok = __all(ok);
                 if (lane == 0) {
                     if (!all_ok && atomicCAS(&st->code, 0, SF_ERR_DEVICE) == 0) {
@@ -287,30 +362,33 @@ __global__ void __launch_bounds__(SOLVE_THREADS) k_sweep(SweepArgs A) {
             __syncthreads();
             if (!sh_ok) return;
         }
-        // z: forward r_t - B_t w_{t-1}; backward B_{t+1}^T x_{t+1}
-        if (!ctl && tid < mp) {
-            double v = 0.0;
-            if (tid < m) {
-                if (fwd) {
-                    v = pr;
-                    if (t > 0) {
-                        double bw = 0.0;
+        // z: forward / middle r_t - (coupling terms); backward the coupling term
+        if (!ctl) {
+#pragma unroll
+            for (int j = 0; j < RPT; ++j) {
+                const int a = tid + CW0 * j, zs = a / 3;
+                if (a >= mp) break;
+                double v = 0.0;
+                if (a < m) {
+                    double cu = 0.0;
+                    if (up) {
                         if (zs > 0)
 #pragma unroll
-                            for (int e = 0; e < 3; ++e) bw = fma(pb[e], full[3 * (zs - 1) + e], bw);
+                            for (int e = 0; e < 3; ++e) cu = fma(pbu[j][e], vup[3 * (zs - 1) + e], cu);
 #pragma unroll
-                        for (int e = 0; e < 3; ++e) bw = fma(pb[3 + e], full[3 * zs + e], bw);
-                        v -= bw;
+                        for (int e = 0; e < 3; ++e) cu = fma(pbu[j][3 + e], vup[3 * zs + e], cu);
                     }
-                } else {
+                    if (dn) {
 #pragma unroll
-                    for (int c = 0; c < 3; ++c) v = fma(pb[c], full[3 * zs + c], v);
-                    if (zs + 1 < ms)
+                        for (int e = 0; e < 3; ++e) cu = fma(pbd[j][e], vdn[3 * zs + e], cu);
+                        if (zs + 1 < ms)
 #pragma unroll
-                        for (int c = 0; c < 3; ++c) v = fma(pb[3 + c], full[3 * (zs + 1) + c], v);
+                            for (int e = 0; e < 3; ++e) cu = fma(pbd[j][3 + e], vdn[3 * (zs + 1) + e], cu);
+                    }
+                    v = back ? cu : pr[j] - cu;
                 }
+                z[a] = v;
             }
-            z[tid] = v;
         }
         __syncthreads();
         if (!ctl) {
@@ -318,16 +396,13 @@ __global__ void __launch_bounds__(SOLVE_THREADS) k_sweep(SweepArgs A) {
 #pragma unroll
             for (int p = 0; p < PF; ++p) {
                 const int qt = wv + NWT * p;
-                if (qt < ntw) {
-                    const int i = qt / NT;
-                    tile_apply(pre[p], rank + P * i, qt % NT, z, &yw[wv][i * TS]);
-                }
+                if (qt < ntw) tile_apply(pre[p], own_row(qt / NT, rank, P), qt % NT, z, &yw[wv][(qt / NT) * TS]);
             }
             for (int qt = wv + NWT * PF; qt < ntw; qt += NWT) {
-                const int i = qt / NT;
+                const int i = qt / NT, I = own_row(i, rank, P);
                 double tv[16];
-                load_tile(Tb + (int64_t)t * tstride, rank + P * i, qt % NT, tv);
-                tile_apply(tv, rank + P * i, qt % NT, z, &yw[wv][i * TS]);
+                load_tile(Tb + (int64_t)t * tstride + tile_lane_offset(I, qt % NT), tv);
+                tile_apply(tv, I, qt % NT, z, &yw[wv][i * TS]);
             }
         }
         __syncthreads();
@@ -335,8 +410,9 @@ __global__ void __launch_bounds__(SOLVE_THREADS) k_sweep(SweepArgs A) {
             if (q + 1 < nphase) prefetch(q + 1);
         } else {
             // finish and publish this rank's rows; keep them; prefetch w
-            const uint64_t tag = (uint64_t)(epoch + (uint32_t)q) << 32;
-            uint64_t* pout = pub + (int64_t)(q & 1) * mp * 2;
+            const uint64_t tag = (uint64_t)tag_of(grp, q) << 32;
+            uint64_t* pout = const_cast<uint64_t*>(slot_of(grp, q));
+            const bool keep = !(q == L && grp == 1);           // group 0 stores the middle line
             double* wt = wst + (int64_t)t * mp;
 #pragma unroll
             for (int i = 0; i < NRC; ++i) {
@@ -347,27 +423,29 @@ __global__ void __launch_bounds__(SOLVE_THREADS) k_sweep(SweepArgs A) {
                         y += yw[w][k];
                         yw[w][k] = 0.0;
                     }
-                    if (!fwd) y = pw[i] - y;               // x_t = w_t - S_t^{-1} v
+                    if (back) y = pw[i] - y;               // x_t = w_t - S_t^{-1} v
                     const uint64_t bits = (uint64_t)__double_as_longlong(y);
                     __hip_atomic_store(pout + 2 * crow[i], tag | (bits & 0xffffffffull), __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_AGENT);
                     __hip_atomic_store(pout + 2 * crow[i] + 1, tag | (bits >> 32), __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_AGENT);
-                    wt[crow[i]] = y;                               // w_t or x_t
+                    if (keep) wt[crow[i]] = y;                     // w_t or x_t
                 }
             }
-            if (q + 1 < nphase && q + 1 >= nt) {
-                const double* wn = wst + (int64_t)(2 * nt - 3 - q) * mp;   // line of phase q + 1
+            if (q + 1 < nphase && q + 1 > L) {
+                const double* wn = wst + (int64_t)line_of(q + 1) * mp;   // w of the next backward line
 #pragma unroll
                 for (int i = 0; i < NRC; ++i) pw[i] = crow[i] >= 0 ? wn[crow[i]] : 0.0;
             }
         }
     }
-    // U[O_i] += x on the owned nodes of this rank's rows (x_{nt-1} = w_{nt-1})
+    // U[O_i] += x on the owned nodes of this rank's rows and of this group's
+    // lines: group 0 lines 0..k, group 1 lines k+1..nt-1
     __syncthreads();
-    for (int i = tid; i < nt * nrow; i += SOLVE_THREADS) {
-        const int t = i / nrow, k = i % nrow;
-        const int a = (rank + P * (k / TS)) * TS + k % TS;
+    const int t0 = grp == 0 ? 0 : km + 1, t1 = grp == 0 ? km + 1 : nt;
+    for (int i = tid; i < (t1 - t0) * nrow; i += SOLVE_THREADS) {
+        const int t = t0 + i / nrow, k = i % nrow;
+        const int a = own_row(k / TS, rank, P) * TS + k % TS;
         if (a >= m) continue;
         const double v = wst[(int64_t)t * mp + a];
         if (mode == 1) {
@@ -386,7 +464,8 @@ __global__ void k_zero_u32(uint32_t* p, int n) {
     if (i < n) p[i] = 0u;
 }
 
-const void* sweep_kernel() { return (const void*)k_sweep; }
+const void* sweep_kernel() { return (const void*)k_sweep<MAXR, 4, MAXMP>; }
+const void* sweep_kernel_small() { return (const void*)k_sweep<2, 8, 384>; }
 
 int launch_sweep(sf_context* c, double* U, const double* r, int single_sub, const double* b_local, double* x_local) {
     SweepArgs a;
@@ -399,22 +478,26 @@ int launch_sweep(sf_context* c, double* U, const double* r, int single_sub, cons
     a.done = c->done_d;
     a.b_local = b_local;
     a.x_local = x_local;
-    a.counters = c->counters;
     a.status = c->status_d;
     a.W = c->W;
     a.H = c->H;
     a.mode = single_sub >= 0 ? 1 : 0;
+    a.groups = c->groups;
     a.spin_limit = 1ll << 20;
     // tags must differ from every tag left in the exchange buffers by earlier
-    // launches: advance by more than the phases of one launch
+    // launches: advance by more than the tags of one launch (2 per phase)
     a.epoch = c->sweep_epoch;
     int maxph = 0;
     for (const auto& d : c->subs) maxph = std::max(maxph, 2 * d.nt);
-    c->sweep_epoch += (uint32_t)maxph + 2;
-    const int grid = single_sub >= 0 ? 8 * c->maxP : c->sweep_grid;
-    const void* kern = (const void*)k_sweep;
+    c->sweep_epoch += 2u * (uint32_t)maxph + 4;
+    const int ranks = c->groups * c->maxP;
+    const int grid = single_sub >= 0 ? 8 * ranks : c->sweep_grid;
+    int maxmp = 0;
+    for (const auto& d : c->subs) maxmp = std::max(maxmp, d.mp);
+    const void* kern = c->sweep_rows <= 2 && maxmp <= 384 ? (const void*)k_sweep<2, 8, 384>
+                                                           : (const void*)k_sweep<MAXR, 4, MAXMP>;
     void* args[] = {&a};
-    if (c->maxP > 1) {
+    if (ranks > 1) {
         if (hipLaunchCooperativeKernel(kern, dim3(grid), dim3(SOLVE_THREADS), args, 0, c->stream) != hipSuccess)
             return SF_ERR_HIP;
     } else {
