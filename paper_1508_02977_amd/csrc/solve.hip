@@ -231,11 +231,24 @@ __global__ void __launch_bounds__(SOLVE_THREADS) k_sweep(SweepArgs A) {
     }
     const int64_t rstep = mode == 1 ? m : gstep;
     // this thread's prefetched tiles (fixed for all lines): offsets inside a line
+    // Fast form (RMAX == 2, NT <= 4 NWT): slot p holds tile (row p % 2,
+    // column wv + NWT (p / 2)), so a wave's tiles of one row are fixed and the
+    // row partials stay in registers until one reduction per row.  General
+    // form: slot p holds the tile qt = wv + NWT p of the rank's row-major list.
+    constexpr bool FAST = RMAX == 2 && PF == 8;
+    auto slot_ok = [&](int p) -> bool {
+        if constexpr (FAST) return (p & 1) < R && wv + NWT * (p >> 1) < NT;
+        else return wv + NWT * p < ntw;
+    };
     int64_t toff[PF];
 #pragma unroll
     for (int p = 0; p < PF; ++p) {
-        const int qt = min(wv + NWT * p, ntw - 1);
-        toff[p] = tile_lane_offset(own_row(qt / NT, rank, P), qt % NT);
+        if constexpr (FAST) {
+            toff[p] = slot_ok(p) ? tile_lane_offset(own_row(p & 1, rank, P), wv + NWT * (p >> 1)) : 0;
+        } else {
+            const int qt = min(wv + NWT * p, ntw - 1);
+            toff[p] = tile_lane_offset(own_row(qt / NT, rank, P), qt % NT);
+        }
     }
     // own rows of the control lanes
     int crow[NRC];
@@ -287,7 +300,7 @@ __global__ void __launch_bounds__(SOLVE_THREADS) k_sweep(SweepArgs A) {
         const double* Tl = Tb + (int64_t)t * tstride;
 #pragma unroll
         for (int p = 0; p < PF; ++p)
-            if (wv + NWT * p < ntw) load_tile(Tl + toff[p], pre[p]);
+            if (slot_ok(p)) load_tile(Tl + toff[p], pre[p]);
     };
     // control wave: poll the published words of (group g, phase q) into dst
     auto gather = [&](int g, int q, double* dst) -> int {
@@ -393,16 +406,78 @@ __global__ void __launch_bounds__(SOLVE_THREADS) k_sweep(SweepArgs A) {
         __syncthreads();
         if (!ctl) {
             // this rank's block rows
+            if constexpr (FAST) {
+                // direct partials dp[i][k] of rows 8h+k and transposed partials
+                // tp[i][0..1] of columns 2c, 2c+1, summed over this wave's tiles
+                const int c = lane & 15, h = lane >> 4;
+                double dp[2][8], tp[2][2];
 #pragma unroll
-            for (int p = 0; p < PF; ++p) {
-                const int qt = wv + NWT * p;
-                if (qt < ntw) tile_apply(pre[p], own_row(qt / NT, rank, P), qt % NT, z, &yw[wv][(qt / NT) * TS]);
-            }
-            for (int qt = wv + NWT * PF; qt < ntw; qt += NWT) {
-                const int i = qt / NT, I = own_row(i, rank, P);
-                double tv[16];
-                load_tile(Tb + (int64_t)t * tstride + tile_lane_offset(I, qt % NT), tv);
-                tile_apply(tv, I, qt % NT, z, &yw[wv][i * TS]);
+                for (int i = 0; i < 2; ++i) {
+                    tp[i][0] = tp[i][1] = 0.0;
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) dp[i][k] = 0.0;
+                }
+#pragma unroll
+                for (int p = 0; p < PF; ++p) {
+                    if (!slot_ok(p)) continue;
+                    const int i = p & 1, I = own_row(i, rank, P), J = wv + NWT * (p >> 1);
+                    if (J >= I) {
+                        const double* zr = z + J * TS + 8 * h;
+#pragma unroll
+                        for (int k = 0; k < 8; ++k) {
+                            tp[i][0] = fma(pre[p][2 * k], zr[k], tp[i][0]);
+                            tp[i][1] = fma(pre[p][2 * k + 1], zr[k], tp[i][1]);
+                        }
+                    } else {
+                        const double z0 = z[J * TS + 2 * c], z1 = z[J * TS + 2 * c + 1];
+#pragma unroll
+                        for (int k = 0; k < 8; ++k) dp[i][k] = fma(pre[p][2 * k], z0, fma(pre[p][2 * k + 1], z1, dp[i][k]));
+                    }
+                }
+                const int b3 = (c >> 3) & 1, b2 = (c >> 2) & 1, b1 = (c >> 1) & 1;
+#pragma unroll
+                for (int i = 0; i < 2; ++i) {
+                    if (i >= R) break;
+                    double* y = &yw[wv][i * TS];
+                    double* d = dp[i];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const double keep = b3 ? d[q + 4] : d[q], send = b3 ? d[q] : d[q + 4];
+                        d[q] = keep + __shfl_xor(send, 8, 64);
+                    }
+#pragma unroll
+                    for (int q = 0; q < 2; ++q) {
+                        const double keep = b2 ? d[q + 2] : d[q], send = b2 ? d[q] : d[q + 2];
+                        d[q] = keep + __shfl_xor(send, 4, 64);
+                    }
+                    {
+                        const double keep = b1 ? d[1] : d[0], send = b1 ? d[0] : d[1];
+                        d[0] = keep + __shfl_xor(send, 2, 64);
+                    }
+                    d[0] += __shfl_xor(d[0], 1, 64);
+                    double s0 = tp[i][0], s1 = tp[i][1];
+                    s0 += __shfl_xor(s0, 16, 64);
+                    s1 += __shfl_xor(s1, 16, 64);
+                    s0 += __shfl_xor(s0, 32, 64);
+                    s1 += __shfl_xor(s1, 32, 64);
+                    if ((c & 1) == 0) y[8 * h + 4 * b3 + 2 * b2 + b1] = d[0];   // yw is zero here
+                    if (h == 0) {
+                        y[2 * c] += s0;
+                        y[2 * c + 1] += s1;
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int p = 0; p < PF; ++p) {
+                    const int qt = wv + NWT * p;
+                    if (qt < ntw) tile_apply(pre[p], own_row(qt / NT, rank, P), qt % NT, z, &yw[wv][(qt / NT) * TS]);
+                }
+                for (int qt = wv + NWT * PF; qt < ntw; qt += NWT) {
+                    const int i = qt / NT, I = own_row(i, rank, P);
+                    double tv[16];
+                    load_tile(Tb + (int64_t)t * tstride + tile_lane_offset(I, qt % NT), tv);
+                    tile_apply(tv, I, qt % NT, z, &yw[wv][i * TS]);
+                }
             }
         }
         __syncthreads();
