@@ -145,15 +145,19 @@ __global__ void k_residual(const double* __restrict__ f0, const double* __restri
 // Stop test of sweep `sweep` (checked before the sweep): per pair relres =
 // ||r||/||F||; a pair stops when relres <= rtol, on F = 0, on a non-finite
 // norm or when sweep == max_sweeps.  Also clears the sweep counters.
+// Stop test, one block per pair: ||r||^2 from the residual kernel's block
+// partials (fixed-order reduction), relres = ||r|| / ||F||; a pair stops at
+// relres <= rtol, on a non-finite norm, at max_sweeps, or at once if F = 0.
 __global__ void k_converge(const double* __restrict__ partials, int npart, const double* __restrict__ Fn2,
                            double* __restrict__ relres, int32_t* __restrict__ sweeps,
-                           int32_t* __restrict__ done, int B, double rtol, int sweep, int max_sweeps,
-                           uint32_t* __restrict__ counters, int nsub) {
-    for (int i = threadIdx.x; i < nsub; i += blockDim.x) counters[i] = 0u;
-    for (int pair = threadIdx.x; pair < B; pair += blockDim.x) {
-        if (done[pair]) continue;
-        double s = 0.0;
-        for (int i = 0; i < npart; ++i) s += partials[pair * npart + i];
+                           int32_t* __restrict__ done, double rtol, int sweep, int max_sweeps) {
+    __shared__ double sh[NODE_THREADS / 64];
+    const int pair = blockIdx.x;
+    if (done[pair]) return;                      // uniform over the block
+    double v = 0.0;
+    for (int i = threadIdx.x; i < npart; i += blockDim.x) v += partials[(int64_t)pair * npart + i];
+    const double s = block_sum(v, sh);
+    if (threadIdx.x == 0) {
         const double fn = Fn2[pair];
         double rel;
         int stop;
@@ -330,9 +334,8 @@ int launch_residual(sf_context* c, const double* U, double* r, int fuse_converge
                        fuse_converge ? (const int32_t*)c->done_d : (const int32_t*)nullptr);
     SF_LAUNCH_CHECK();
     if (fuse_converge) {
-        hipLaunchKernelGGL(k_converge, dim3(1), dim3(256), 0, c->stream, c->partials, c->npart, c->Fn2,
-                           c->relres_d, c->sweeps_d, c->done_d, c->B, rtol, sweep, max_sweeps,
-                           c->counters, c->nsub);
+        hipLaunchKernelGGL(k_converge, dim3(c->B), dim3(NODE_THREADS), 0, c->stream, c->partials, c->npart,
+                           c->Fn2, c->relres_d, c->sweeps_d, c->done_d, rtol, sweep, max_sweeps);
     } else {
         hipLaunchKernelGGL(k_finalize_norm, dim3(c->B), dim3(64), 0, c->stream, c->partials, c->npart,
                            c->relres_d);
