@@ -68,14 +68,14 @@ def measured_traffic():
         return None
 
 
-def sweep_bytes(plan):
+def sweep_bytes(plan, tile_bytes=8):
     """Algorithmic HBM bytes of one sweep launch (all subdomains).
 
     Per subdomain with nt lines of m unknowns: the forward pass streams the
     packed lower triangles of all nt inverse Schur complements, the backward
-    pass nt-1 of them (m(m+1)/2 doubles each), the line couplings once per
-    direction (6 m doubles), the residual gather (m doubles per line) and the
-    owned update of U (read + write).
+    pass nt-1 of them (m(m+1)/2 entries of tile_bytes each), the line
+    couplings once per direction (6 m doubles), the residual gather (m doubles
+    per line) and the owned update of U (read + write).
     """
     total = 0
     for g in plan:
@@ -85,7 +85,7 @@ def sweep_bytes(plan):
         m = 3 * ms
         ox0, ox1, oy0, oy1 = g["own"]
         owned = 3 * (ox1 - ox0) * (oy1 - oy0)
-        total += 8 * ((2 * nt - 1) * (m * (m + 1) // 2) + 2 * nt * 6 * m + nt * m + 2 * owned)
+        total += tile_bytes * (2 * nt - 1) * (m * (m + 1) // 2) + 8 * (2 * nt * 6 * m + nt * m + 2 * owned)
     return total
 
 
@@ -132,6 +132,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    ap.add_argument("--plain-only", action="store_true", help="skip the FP32-tile form")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB -> 256 MiB copy kernel (counter calibration)")
     args = ap.parse_args()
@@ -140,7 +141,6 @@ def main():
                                    "(the sharded design is described in DESIGN.md)"}))
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     from paper_1508_02977_amd import api, synth
@@ -160,40 +160,50 @@ def main():
     I0 = torch.tensor(pair.I0[None], dtype=torch.float64, device=dev)
     I1 = torch.tensor(pair.I1[None], dtype=torch.float64, device=dev)
     A0 = torch.tensor(alpha0[None], dtype=torch.float64, device=dev)
-    Al = torch.empty_like(A0)
-    ctx = api.sf_create(W, H, 1, PX, PY, OVERLAP, lam=LAM)
-    U = torch.zeros(ctx.field_shape(), dtype=torch.float64, device=dev)
-    plan = [api.sf_subdomain_geometry(ctx, i) for i in range(api.sf_num_subdomains(ctx))]
 
-    def step():
-        Al.copy_(A0)
-        U.zero_()
-        return api.run_pipeline(ctx, I0, I1, Al, U, rtol=RTOL, max_sweeps=MAX_SWEEPS, passes=PASSES,
-                                kappa=KAPPA, eta_thr=ETA_THR, alpha_th=ALPHA_TH)
+    def run_form(precision):
+        """Warm up, then time `steps` whole pipeline steps with the given
+        storage of the inverse Schur tiles."""
+        Al = torch.empty_like(A0)
+        ctx = api.sf_create(W, H, 1, PX, PY, OVERLAP, lam=LAM, factor_precision=precision)
+        U = torch.zeros(ctx.field_shape(), dtype=torch.float64, device=dev)
+        plan = [api.sf_subdomain_geometry(ctx, i) for i in range(api.sf_num_subdomains(ctx))]
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    api.sf_profile(ctx, 1)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    results = [step() for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    prof = api.sf_profile(ctx, 0)
-    ms_step = (t1 - t0) * 1e3 / args.steps
-    last = results[-1]
+        def step():
+            Al.copy_(A0)
+            U.zero_()
+            return api.run_pipeline(ctx, I0, I1, Al, U, rtol=RTOL, max_sweeps=MAX_SWEEPS, passes=PASSES,
+                                    kappa=KAPPA, eta_thr=ETA_THR, alpha_th=ALPHA_TH)
+
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        api.sf_profile(ctx, 1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        results = [step() for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        prof = api.sf_profile(ctx, 0)
+        last = results[-1]
+        if any(r[0] > RTOL for r in last.relres):
+            raise SystemExit(f"bench: a solve did not reach {RTOL}: {last.relres}")
+        # the solve loop tests convergence on the host every few sweeps, so a
+        # solve can end with a few launches that find every pair converged and
+        # exit at once: time per working launch = all sweep time / sweeps done
+        sw_ms, sw_n = prof["sweep"]
+        sweeps_timed = sum(s[0] for r in results for s in r.sweeps)
+        ctx.close()
+        return dict(ms_step=(t1 - t0) * 1e3 / args.steps, last=last, prof=prof, plan=plan, U=U.clone(),
+                    sw_ms=sw_ms, sw_n=sw_n, sweeps_timed=sweeps_timed,
+                    avg_sweep_ms=sw_ms / max(sweeps_timed, 1))
+
+    plain = run_form(api.SF_FP64)
+    ms_step = plain["ms_step"]
+    last = plain["last"]
     sweeps = [s[0] for s in last.sweeps]
-    if any(r[0] > RTOL for r in last.relres):
-        raise SystemExit(f"bench: a solve did not reach {RTOL}: {last.relres}")
-
-    # the solve loop tests convergence on the host every few sweeps, so a
-    # solve can end with a few launches that find every pair converged and
-    # exit at once: time per working launch = all sweep time / sweeps done
-    sw_ms, sw_n = prof["sweep"]
-    sweeps_timed = sum(s[0] for r in results for s in r.sweeps)
-    avg_sweep_ms = sw_ms / max(sweeps_timed, 1)
-    bytes_per_sweep = sweep_bytes(plan)
+    avg_sweep_ms = plain["avg_sweep_ms"]
+    bytes_per_sweep = sweep_bytes(plain["plan"])
     achieved = bytes_per_sweep / (avg_sweep_ms * 1e-3) / 1e9
     out = {
         "metric": METRIC,
@@ -210,13 +220,33 @@ def main():
         "data": "synthetic",
         "config": {"workload": "plain640: one 640x480 pair, 4x4 subdomains, 8-node overlap, lambda 1, "
                                "alpha0 0.1, 3 adaptive-alpha passes, every solve to rel. residual 1e-8",
+                   "form": "plain FP64",
                    "sweeps_per_solve": sweeps, "final_relres": [r[0] for r in last.relres]},
         "roofline": {"bound": "hbm", "kernel": "k_sweep", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
                      "bytes_per_launch": bytes_per_sweep, "avg_launch_ms": avg_sweep_ms,
-                     "launches": sw_n, "working_launches": sweeps_timed},
-        "phase_ms_per_step": {k: v[0] / args.steps for k, v in prof.items()},
+                     "launches": plain["sw_n"], "working_launches": plain["sweeps_timed"]},
+        "phase_ms_per_step": {k: v[0] / args.steps for k, v in plain["prof"].items()},
     }
+    if not args.plain_only:
+        # the chosen form: inverse tiles stored in FP32, FP64 arithmetic and
+        # residuals (the Schwarz iteration refines); same workload, same 1e-8
+        ch = run_form(api.SF_FP32)
+        Up, Uc = plain["U"][0], ch["U"][0]
+        field_diff = [float(torch.linalg.norm(Uc[c] - Up[c]) / torch.linalg.norm(Up[c])) for c in range(3)]
+        b32 = sweep_bytes(ch["plan"], tile_bytes=4)
+        out["chosen_form"] = {
+            "form": "inverse Schur tiles stored in FP32, FP64 arithmetic, FP64-residual Schwarz refinement",
+            "value": 3 * W * H / (ch["ms_step"] * 1e-3), "unit": "unknowns/s", "ms_per_step": ch["ms_step"],
+            "speedup_vs_plain": ms_step / ch["ms_step"],
+            "sweeps_per_solve": [s[0] for s in ch["last"].sweeps],
+            "final_relres": [r[0] for r in ch["last"].relres],
+            "rel_diff_vs_plain_per_field": field_diff,
+            "sweep_avg_launch_ms": ch["avg_sweep_ms"],
+            "sweep_bytes_per_launch": b32,
+            "sweep_achieved_GBs": b32 / (ch["avg_sweep_ms"] * 1e-3) / 1e9,
+            "phase_ms_per_step": {k: v[0] / args.steps for k, v in ch["prof"].items()},
+        }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(pair, alpha0, sum(sweeps), len(sweeps), PASSES)
     print(json.dumps(out), flush=True)

@@ -51,6 +51,11 @@ extern "C" {
 
 /* factor_precision */
 #define SF_FP64      0          /* subdomain factors stored and applied in FP64 */
+#define SF_FP32      1          /* inverse Schur tiles computed in FP64, stored in
+                                   FP32 and applied in FP64 arithmetic: an inexact
+                                   local solve whose error the Schwarz iteration on
+                                   FP64 residuals removes (iterative refinement);
+                                   the iteration converges to the same solution  */
 
 typedef struct sf_config {
     int32_t width;            /* W >= 2 nodes                                    */
@@ -61,7 +66,7 @@ typedef struct sf_config {
     int32_t overlap;          /* delta >= 0: nodes shared by neighbouring boxes   */
     double  lambda;           /* regularisation of m (> 0), constant (Section 2.3) */
     double  sigma;            /* Gaussian presmoothing of the frames; must be 0   */
-    int32_t factor_precision; /* SF_FP64                                          */
+    int32_t factor_precision; /* SF_FP64 or SF_FP32                               */
     int32_t band_tile;        /* sweep workgroups per chain of a subdomain; 0 = auto */
 } sf_config;
 

@@ -28,6 +28,7 @@ SF_NOT_SPD = 1
 SF_NOT_CONVERGED = 2
 SF_NONFINITE = 3
 SF_FP64 = 0
+SF_FP32 = 1
 
 c_int32 = ctypes.c_int32
 c_double = ctypes.c_double

@@ -73,7 +73,8 @@ int check_config(const sf_config& k) {
     if (k.width < 2 || k.height < 2 || k.batch < 1) return SF_ERR_INVALID;
     if (k.parts_x < 1 || k.parts_y < 1 || k.parts_x > k.width || k.parts_y > k.height) return SF_ERR_INVALID;
     if (k.overlap < 0 || !(k.lambda > 0.0) || !std::isfinite(k.lambda)) return SF_ERR_INVALID;
-    if (k.sigma != 0.0 || k.factor_precision != SF_FP64 || k.band_tile < 0) return SF_ERR_INVALID;
+    if (k.sigma != 0.0 || (k.factor_precision != SF_FP64 && k.factor_precision != SF_FP32) || k.band_tile < 0)
+        return SF_ERR_INVALID;
     if ((int64_t)k.width * k.height * k.batch > (1ll << 31)) return SF_ERR_INVALID;
     return SF_OK;
 }
@@ -275,7 +276,8 @@ int sf_create(const sf_config* cfg, void* stream, sf_context** out) {
         d.P = P;
         d.kmid = G == 2 ? (d.nt - 1) / 2 : d.nt - 1;
         d.foff = foff;
-        foff += (int64_t)d.nt * d.ntiles * sfdd::TSZ;
+        // tiles in doubles, or in floats packed two per double
+        foff += (int64_t)d.nt * d.ntiles * sfdd::TSZ / (k.factor_precision == SF_FP32 ? 2 : 1);
         d.boff = foff;
         foff += (int64_t)d.nt * d.m * 6;
         d.aoff = foff;

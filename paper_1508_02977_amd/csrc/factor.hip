@@ -92,6 +92,15 @@ __device__ __forceinline__ void acc_store(const double acc[4][4], double* C, int
         for (int c = 0; c < 4; ++c) C[(4 * br + r) * ldc + 4 * bc + c] = scale * acc[r][c];
 }
 
+// the same into a tile of single-precision storage (each value rounded once)
+__device__ __forceinline__ void acc_store_f(const double acc[4][4], float* C, int ldc) {
+    const int lane = threadIdx.x & 63, br = lane >> 3, bc = lane & 7;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) C[(4 * br + r) * ldc + 4 * bc + c] = (float)acc[r][c];
+}
+
 __device__ __forceinline__ void acc_store_t(const double acc[4][4], double* C, int ldc) {
     const int lane = threadIdx.x & 63, br = lane >> 3, bc = lane & 7;
 #pragma unroll
@@ -110,7 +119,7 @@ __device__ void set_status(DevStatus* st, int code, int sub, int64_t row) {
 __global__ void __launch_bounds__(FACTOR_THREADS)
 k_factor(const SubDesc* __restrict__ subs, const double* __restrict__ f0_all, const double* __restrict__ al_all,
          double* __restrict__ factors, double* __restrict__ work, DevStatus* __restrict__ status,
-         int W, int H, double lam) {
+         int W, int H, double lam, int fp32) {
     const int sub = blockIdx.x;
     const SubDesc d = subs[sub];
     const int tid = threadIdx.x, wv = tid >> 6, nw = FACTOR_THREADS / 64;
@@ -318,7 +327,8 @@ k_factor(const SubDesc* __restrict__ subs, const double* __restrict__ f0_all, co
             acc_zero(acc);
             for (int k = i; k < NT; ++k)
                 tile_mm<true, false>(Y + (int64_t)(k * TS) * mp + i * TS, mp, Y + (int64_t)(k * TS) * mp + j * TS, mp, acc);
-            acc_store(acc, Tout + ((int64_t)t * d.ntiles + q) * TSZ, TS);
+            if (fp32) acc_store_f(acc, reinterpret_cast<float*>(Tout) + ((int64_t)t * d.ntiles + q) * TSZ, TS);
+            else      acc_store(acc, Tout + ((int64_t)t * d.ntiles + q) * TSZ, TS);
             acc_store(acc, Pv + (int64_t)(i * TS) * mp + j * TS, mp);
             if (i != j) acc_store_t(acc, Pv + (int64_t)(j * TS) * mp + i * TS, mp);
         }
@@ -336,7 +346,8 @@ int launch_factor(sf_context* c) {
     hipLaunchKernelGGL(k_zero_status, dim3(1), dim3(1), 0, c->stream, c->status_d);
     if (hipGetLastError() != hipSuccess) return SF_ERR_HIP;
     hipLaunchKernelGGL(k_factor, dim3(c->nsub), dim3(FACTOR_THREADS), 0, c->stream, c->d_subs, c->f0, c->alpha,
-                       c->factors, c->work, c->status_d, c->W, c->H, c->cfg.lambda);
+                       c->factors, c->work, c->status_d, c->W, c->H, c->cfg.lambda,
+                       c->cfg.factor_precision == SF_FP32 ? 1 : 0);
     if (hipGetLastError() != hipSuccess) return SF_ERR_HIP;
     return SF_OK;
 }

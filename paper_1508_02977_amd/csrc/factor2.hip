@@ -46,6 +46,7 @@ struct FactorArgs {
     int sub0, nsub;           // subdomains [sub0, nsub) of this launch; sub0 % 8 == 0
     int pf;                   // rank slots per chain (the largest ceil(NT / 2))
     int groups;               // chains per subdomain: 1 (top to bottom) or 2 (twisted)
+    int fp32;                 // 1: store the inverse tiles in single precision
     const double* f0;
     const double* al;
     double* factors;
@@ -538,14 +539,21 @@ __global__ void __launch_bounds__(F2_THREADS) k_factor2(FactorArgs A) {
                     f2_tile_of(blk >> 2, rowA, rowB, I, J);
                     const int qi = (blk >> 1) & 1, qj = blk & 1;
                     const int q0 = I * (I + 1) / 2 + J;
-                    double* tl = Tout + ((int64_t)t * d.ntiles + q0) * TSZ;
+                    const int64_t toff = ((int64_t)t * d.ntiles + q0) * TSZ;
+                    double* tl = Tout + toff;
+                    float* tf = reinterpret_cast<float*>(Tout) + toff;
                     #pragma unroll
                     for (int q = 0; q < 4; ++q) {
                         const int r = 16 * qi + cr + 4 * q, c = 16 * qj + cc;
                         if (I == J && r < c) continue;           // diagonal tiles: mirror the lower half
                         const double v = -bscr[(b * 4 + q) * 64 + lane];
-                        tl[r * TS + c] = v;
-                        if (I == J) tl[c * TS + r] = v;
+                        if (A.fp32) {
+                            tf[r * TS + c] = (float)v;
+                            if (I == J) tf[c * TS + r] = (float)v;
+                        } else {
+                            tl[r * TS + c] = v;
+                            if (I == J) tl[c * TS + r] = v;
+                        }
                         if (!mid) {                              // the next line of this chain needs it
                             const int ga = I * TS + r, gc = J * TS + c;
                             xstore(Sown + (int64_t)ga * mp + gc, v);
@@ -576,6 +584,7 @@ int launch_factor2(sf_context* c, int sub0, int nsub_chunk, int Pf) {
     a.nsub = sub0 + nsub_chunk;
     a.pf = Pf;
     a.groups = c->groups;
+    a.fp32 = c->cfg.factor_precision == SF_FP32 ? 1 : 0;
     a.f0 = c->f0;
     a.al = c->alpha;
     a.factors = c->factors;

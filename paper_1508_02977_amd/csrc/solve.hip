@@ -63,9 +63,19 @@ __device__ __forceinline__ void load_tile(const double* __restrict__ T, double t
         tv[2 * i + 1] = v.y;
     }
 }
+// single-precision tiles: 8-byte loads, same lane layout
+__device__ __forceinline__ void load_tile(const float* __restrict__ T, float tv[16]) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const float2 v = *reinterpret_cast<const float2*>(T + i * TS);
+        tv[2 * i] = v.x;
+        tv[2 * i + 1] = v.y;
+    }
+}
 
 // y_I += (tile) z_J for one tile of the block row, into the wave's row buffer y[32].
-__device__ __forceinline__ void tile_apply(const double tv[16], int I, int J, const double* z, double* y) {
+template <typename TT>
+__device__ __forceinline__ void tile_apply(const TT tv[16], int I, int J, const double* z, double* y) {
     const int lane = threadIdx.x & 63;
     const int c = lane & 15, h = lane >> 4;
     if (J >= I) {
@@ -75,8 +85,8 @@ __device__ __forceinline__ void tile_apply(const double tv[16], int I, int J, co
         double s0 = 0.0, s1 = 0.0;
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
-            s0 = fma(tv[2 * i], zr[i], s0);
-            s1 = fma(tv[2 * i + 1], zr[i], s1);
+            s0 = fma((double)tv[2 * i], zr[i], s0);
+            s1 = fma((double)tv[2 * i + 1], zr[i], s1);
         }
         s0 += __shfl_xor(s0, 16, 64);
         s1 += __shfl_xor(s1, 16, 64);
@@ -93,7 +103,7 @@ __device__ __forceinline__ void tile_apply(const double tv[16], int I, int J, co
         const double z0 = z[J * TS + 2 * c], z1 = z[J * TS + 2 * c + 1];
         double p[8];
 #pragma unroll
-        for (int i = 0; i < 8; ++i) p[i] = fma(tv[2 * i], z0, tv[2 * i + 1] * z1);
+        for (int i = 0; i < 8; ++i) p[i] = fma((double)tv[2 * i], z0, (double)tv[2 * i + 1] * z1);
         const int b3 = (c >> 3) & 1, b2 = (c >> 2) & 1, b1 = (c >> 1) & 1;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -148,7 +158,7 @@ __device__ __forceinline__ int own_row(int i, int rank, int P) {
 // workgroups g with g % 8 == i % 8, so the tiles that two ranks of one
 // subdomain both read are shared through one L2.  Correctness does not depend
 // on the placement: the exchange uses device-scope accesses.
-template <int RMAX, int PF, int LMAX>
+template <typename TT, int RMAX, int PF, int LMAX>
 __global__ void __launch_bounds__(SOLVE_THREADS) k_sweep(SweepArgs A) {
     constexpr int NW = SOLVE_THREADS / 64;
     constexpr int NWT = NW - 1;                    // tile waves
@@ -192,7 +202,7 @@ __global__ void __launch_bounds__(SOLVE_THREADS) k_sweep(SweepArgs A) {
     const int nphase = 2 * L + 1;
     const int64_t nn = (int64_t)A.W * A.H;
     const int64_t tstride = (int64_t)d.ntiles * TSZ;       // tiles of one line
-    const double* __restrict__ Tb = A.factors + d.foff;
+    const TT* __restrict__ Tb = reinterpret_cast<const TT*>(A.factors + d.foff);   // tiles of double or float
     const double* __restrict__ Bb = A.factors + d.boff;
     double* __restrict__ wst = A.work + d.woff;            // w_t, then x_t, of this rank's rows
     // published rows: per group [3][mp] pairs of 64-bit words (tag << 32 | half
@@ -258,7 +268,7 @@ __global__ void __launch_bounds__(SOLVE_THREADS) k_sweep(SweepArgs A) {
         crow[i] = k < nrow ? own_row(k / TS, rank, P) * TS + k % TS : -1;
     }
 
-    double pre[PF][16];
+    TT pre[PF][16];
     double pr[RPT], pbu[RPT][6], pbd[RPT][6];
 #pragma unroll
     for (int j = 0; j < RPT; ++j) {
@@ -297,7 +307,7 @@ __global__ void __launch_bounds__(SOLVE_THREADS) k_sweep(SweepArgs A) {
                 }
             }
         }
-        const double* Tl = Tb + (int64_t)t * tstride;
+        const TT* Tl = Tb + (int64_t)t * tstride;
 #pragma unroll
         for (int p = 0; p < PF; ++p)
             if (slot_ok(p)) load_tile(Tl + toff[p], pre[p]);
@@ -425,13 +435,14 @@ __global__ void __launch_bounds__(SOLVE_THREADS) k_sweep(SweepArgs A) {
                         const double* zr = z + J * TS + 8 * h;
 #pragma unroll
                         for (int k = 0; k < 8; ++k) {
-                            tp[i][0] = fma(pre[p][2 * k], zr[k], tp[i][0]);
-                            tp[i][1] = fma(pre[p][2 * k + 1], zr[k], tp[i][1]);
+                            tp[i][0] = fma((double)pre[p][2 * k], zr[k], tp[i][0]);
+                            tp[i][1] = fma((double)pre[p][2 * k + 1], zr[k], tp[i][1]);
                         }
                     } else {
                         const double z0 = z[J * TS + 2 * c], z1 = z[J * TS + 2 * c + 1];
 #pragma unroll
-                        for (int k = 0; k < 8; ++k) dp[i][k] = fma(pre[p][2 * k], z0, fma(pre[p][2 * k + 1], z1, dp[i][k]));
+                        for (int k = 0; k < 8; ++k)
+                            dp[i][k] = fma((double)pre[p][2 * k], z0, fma((double)pre[p][2 * k + 1], z1, dp[i][k]));
                     }
                 }
                 const int b3 = (c >> 3) & 1, b2 = (c >> 2) & 1, b1 = (c >> 1) & 1;
@@ -474,7 +485,7 @@ __global__ void __launch_bounds__(SOLVE_THREADS) k_sweep(SweepArgs A) {
                 }
                 for (int qt = wv + NWT * PF; qt < ntw; qt += NWT) {
                     const int i = qt / NT, I = own_row(i, rank, P);
-                    double tv[16];
+                    TT tv[16];
                     load_tile(Tb + (int64_t)t * tstride + tile_lane_offset(I, qt % NT), tv);
                     tile_apply(tv, I, qt % NT, z, &yw[wv][i * TS]);
                 }
@@ -539,8 +550,8 @@ __global__ void k_zero_u32(uint32_t* p, int n) {
     if (i < n) p[i] = 0u;
 }
 
-const void* sweep_kernel() { return (const void*)k_sweep<MAXR, 4, MAXMP>; }
-const void* sweep_kernel_small() { return (const void*)k_sweep<2, 8, 384>; }
+const void* sweep_kernel() { return (const void*)k_sweep<double, MAXR, 4, MAXMP>; }
+const void* sweep_kernel_small() { return (const void*)k_sweep<double, 2, 8, 384>; }
 
 int launch_sweep(sf_context* c, double* U, const double* r, int single_sub, const double* b_local, double* x_local) {
     SweepArgs a;
@@ -569,8 +580,12 @@ int launch_sweep(sf_context* c, double* U, const double* r, int single_sub, cons
     const int grid = single_sub >= 0 ? 8 * ranks : c->sweep_grid;
     int maxmp = 0;
     for (const auto& d : c->subs) maxmp = std::max(maxmp, d.mp);
-    const void* kern = c->sweep_rows <= 2 && maxmp <= 384 ? (const void*)k_sweep<2, 8, 384>
-                                                           : (const void*)k_sweep<MAXR, 4, MAXMP>;
+    const bool fast = c->sweep_rows <= 2 && maxmp <= 384;
+    const void* kern;
+    if (c->cfg.factor_precision == SF_FP32)
+        kern = fast ? (const void*)k_sweep<float, 2, 8, 384> : (const void*)k_sweep<float, MAXR, 4, MAXMP>;
+    else
+        kern = fast ? (const void*)k_sweep<double, 2, 8, 384> : (const void*)k_sweep<double, MAXR, 4, MAXMP>;
     void* args[] = {&a};
     if (ranks > 1) {
         if (hipLaunchCooperativeKernel(kern, dim3(grid), dim3(SOLVE_THREADS), args, 0, c->stream) != hipSuccess)
