@@ -310,25 +310,63 @@ __global__ void __launch_bounds__(F2_THREADS) k_factor2(FactorArgs A) {
             constexpr int WN = 21;
             double* win = colk + 4608 + wv * (WN * WN + WN * 16);   // [WN][WN]
             double* zb = win + WN * WN;                             // [WN][16]
-            auto term = [&](const double* S, const double* cf, int dn, int r0, int c0, d4& v) {
-                const int wr0 = max(0, 3 * (r0 / 3 - 1 + dn)), wr1 = min(m, 3 * ((r0 + 15) / 3 + dn) + 3);
-                const int wc0 = max(0, 3 * (c0 / 3 - 1 + dn)), wc1 = min(m, 3 * ((c0 + 15) / 3 + dn) + 3);
-                const int nr = max(0, wr1 - wr0), nc = max(0, wc1 - wc0);
-                // (i) window of the neighbour's inverse
-                double wv_[(WN * WN + 63) / 64];
+            constexpr int NWL = (WN * WN + 63) / 64;              // window entries per lane
+            // Work items: (block b of this wave, term).  The window loads of the
+            // next item are issued before the current item is computed, so the
+            // round trip to the neighbour's inverse overlaps the arithmetic.
+            const int nbw = nblk > wv ? (nblk - wv + F2_NW - 1) / F2_NW : 0;
+            const int nterm = (hup ? 1 : 0) + (hdn ? 1 : 0);
+            const int nitem = nbw * nterm;
+            auto item = [&](int it, int& b, int& dn, int& r0, int& c0) {
+                b = nterm == 2 ? it >> 1 : it;
+                dn = nterm == 2 ? (it & 1) : (hup ? 0 : 1);
+                int I, J;
+                const int blk = wv + F2_NW * b;
+                f2_tile_of(blk >> 2, rowA, rowB, I, J);
+                r0 = I * TS + 16 * ((blk >> 1) & 1);
+                c0 = J * TS + 16 * (blk & 1);
+            };
+            auto win_rows = [&](int x0, int dn, int& w0, int& n) {
+                w0 = max(0, 3 * (x0 / 3 - 1 + dn));
+                n = max(0, min(m, 3 * ((x0 + 15) / 3 + dn) + 3) - w0);
+            };
+            auto issue = [&](int it, double (&w)[NWL]) {
+                int b, dn, r0, c0, wr0, nr, wc0, nc;
+                item(it, b, dn, r0, c0);
+                win_rows(r0, dn, wr0, nr);
+                win_rows(c0, dn, wc0, nc);
+                const double* S = dn ? Sdn : Sup;
 #pragma unroll
-                for (int u = 0; u < (WN * WN + 63) / 64; ++u) {
+                for (int u = 0; u < NWL; ++u) {
                     const int e = lane + 64 * u, i = e / WN, j = e % WN;
-                    wv_[u] = (i < nr && j < nc) ? xload(S + (int64_t)(wr0 + i) * mp + wc0 + j) : 0.0;
+                    w[u] = (i < nr && j < nc) ? xload(S + (int64_t)(wr0 + i) * mp + wc0 + j) : 0.0;
                 }
+            };
+            d4 v = {0.0, 0.0, 0.0, 0.0};
+            auto a_init = [&](int r0, int c0) {
+                const int a2 = c0 + cc;
 #pragma unroll
-                for (int u = 0; u < (WN * WN + 63) / 64; ++u) {
+                for (int q = 0; q < 4; ++q) {
+                    const int a = r0 + cr + 4 * q;
+                    v[q] = (a < m && a2 < m) ? a_entry(a, a2) : (a == a2 ? 1.0 : 0.0);   // identity on the padding
+                }
+            };
+            // subtract the item's term C_R Z, Z = S^{-1}[W(R), W(C)] C_C^T, from v
+            auto process = [&](int it, const double (&w)[NWL]) {
+                int b, dn, r0, c0, wr0, nr, wc0, nc;
+                item(it, b, dn, r0, c0);
+                win_rows(r0, dn, wr0, nr);
+                win_rows(c0, dn, wc0, nc);
+                const double* cf = dn ? Cl : Bl;
+                if (nterm == 1 || dn == 0) a_init(r0, c0);         // first term of the block
+#pragma unroll
+                for (int u = 0; u < NWL; ++u) {
                     const int e = lane + 64 * u;
-                    if (e < WN * WN) win[e] = wv_[u];
+                    if (e < WN * WN) win[e] = w[u];
                 }
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                // (ii) Z[i][jc] = sum over the coupled nodes of column c0 + jc
+                // Z[i][jc] = sum over the coupled nodes of column c0 + jc
                 for (int e = lane; e < WN * 16; e += 64) {
                     const int i = e / 16, jc = e % 16, a2 = c0 + jc;
                     double zv = 0.0;
@@ -345,7 +383,7 @@ __global__ void __launch_bounds__(F2_THREADS) k_factor2(FactorArgs A) {
                 }
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                // (iii) this lane's 4 entries: v -= C_R Z
+                // this lane's 4 entries: v -= C_R Z
                 const int a2 = c0 + cc;
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
@@ -364,30 +402,37 @@ __global__ void __launch_bounds__(F2_THREADS) k_factor2(FactorArgs A) {
                 }
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            };
-            // one copy of the block code (not unrolled: the accumulators stay out
-            // of its register budget); blocks go through this wave's scratch
-#pragma unroll 1
-            for (int b = 0; b < F2_MAXBLK; ++b) {
-                const int blk = wv + F2_NW * b;
-                d4 v = {0.0, 0.0, 0.0, 0.0};
-                if (blk < nblk) {
-                    int I, J;
-                    f2_tile_of(blk >> 2, rowA, rowB, I, J);
-                    const int qi = (blk >> 1) & 1, qj = blk & 1;
-                    const int r0 = I * TS + 16 * qi, c0 = J * TS + 16 * qj;
-                    const int a2 = c0 + cc;
+                if (nterm == 1 || dn == 1) {                          // last term of the block
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const int a = r0 + cr + 4 * q;
-                        v[q] = (a < m && a2 < m) ? a_entry(a, a2) : (a == a2 ? 1.0 : 0.0);   // identity on the padding
-                    }
-                    if (hup) term(Sup, Bl, 0, r0, c0, v);
-                    if (hdn) term(Sdn, Cl, 1, r0, c0, v);
+                    for (int q = 0; q < 4; ++q) bscr[(b * 4 + q) * 64 + lane] = v[q];
                 }
+            };
+            if (nterm == 0) {
+                // first line of a chain: S_t = A_tt
+#pragma unroll 1
+                for (int b = 0; b < nbw; ++b) {
+                    int I, J;
+                    const int blk = wv + F2_NW * b;
+                    f2_tile_of(blk >> 2, rowA, rowB, I, J);
+                    a_init(I * TS + 16 * ((blk >> 1) & 1), J * TS + 16 * (blk & 1));
 #pragma unroll
-                for (int q = 0; q < 4; ++q) bscr[(b * 4 + q) * 64 + lane] = v[q];
+                    for (int q = 0; q < 4; ++q) bscr[(b * 4 + q) * 64 + lane] = v[q];
+                }
+            } else {
+                double wa[NWL], wb[NWL];
+                if (nitem > 0) issue(0, wa);
+#pragma unroll 1
+                for (int it = 0; it < nitem; it += 2) {
+                    if (it + 1 < nitem) issue(it + 1, wb);
+                    process(it, wa);
+                    if (it + 2 < nitem) issue(it + 2, wa);
+                    if (it + 1 < nitem) process(it + 1, wb);
+                }
             }
+            // blocks of this wave beyond nbw stay zero (never used)
+            for (int b = nbw; b < F2_MAXBLK; ++b)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) bscr[(b * 4 + q) * 64 + lane] = 0.0;
 #pragma unroll
             for (int b = 0; b < F2_MAXBLK; ++b)
 #pragma unroll
@@ -427,40 +472,112 @@ __global__ void __launch_bounds__(F2_THREADS) k_factor2(FactorArgs A) {
                 }
             }
             __syncthreads();
-            // Pi = S_kk^{-1}: unblocked symmetric sweep of the 32x32 pivot block,
-            // in the registers of wave 0 (lane (j, h) holds rows 16h..16h+15 of
-            // column j); the other waves wait at the barrier.
+            // Pi = S_kk^{-1} by 2x2 blocks of 16 in wave 0 (the other waves wait
+            // at the barrier).  With S_kk = [[A, B^T], [B, C]] (symmetrised on
+            // load): A^-1 and C'^-1, C' = C - B A^-1 B^T, by the symmetric
+            // sweep (16 steps each, every lane holding 4 entries in the MFMA
+            // accumulator layout); then with X = B A^-1 on FP64 MFMA:
+            // Pi = [[A^-1 + X^T C'^-1 X, -(C'^-1 X)^T], [-C'^-1 X, C'^-1]].
+            // The pivots met are those of the unblocked sweep, so the SPD
+            // test is unchanged.
             __builtin_amdgcn_sched_barrier(0);
             if (wv == 0) {
-                const int j = lane & 31, h = lane >> 5;
-                double v[16];
+                constexpr int PB = 17;                        // pitch of the 16x16 scratch blocks
+                double* bA = xr;                              // A^-1
+                double* bB = bA + 16 * PB;                    // B, then -C'^-1 X
+                double* bX = bB + 16 * PB;                    // X = B A^-1
+                double* bC = bX + 16 * PB;                    // C'^-1
+                double* prow = bC + 16 * PB;                  // pivot row
+                const int ci = lane & 15, ri = lane >> 4;     // element q of a lane: row ri + 4q, column ci
+                const double* Sk = colk + k * LTILE;
+                d4 Av, Bv, Cv;
 #pragma unroll
-                for (int r = 0; r < 16; ++r) v[r] = colk[k * LTILE + (16 * h + r) * LDP + j];
-#pragma unroll
-                for (int p = 0; p < TS; ++p) {
-                    const int hp = p >> 4, rp = p & 15;
-                    const double pp = __shfl(v[rp], p + 32 * hp, 64);
-                    if (lane == 0 && !(pp > 1e-13 * adiag[k * TS + p] && isfinite(pp))) {
-                        if (atomicCAS(&A.status->code, 0, SF_NOT_SPD) == 0) {
-                            A.status->sub = sub;
-                            A.status->row = (int64_t)t * m + k * TS + p;
-                        }
-                    }
-                    const double ip = 1.0 / pp;
-                    const double rowp = __shfl(v[rp], j + 32 * hp, 64);     // S[p][j]
-#pragma unroll
-                    for (int r = 0; r < 16; ++r) {
-                        const int i = 16 * h + r;
-                        const double colp = __shfl(v[r], p + 32 * h, 64);   // S[16h+r][p]
-                        if (i != p && j != p) v[r] = v[r] - colp * rowp * ip;
-                        else if (i == p && j == p) v[r] = -ip;
-                        else if (i == p) v[r] = rowp * ip;
-                        else v[r] = colp * ip;
-                    }
+                for (int q = 0; q < 4; ++q) {
+                    const int i = ri + 4 * q, j = ci;
+                    Av[q] = 0.5 * (Sk[i * LDP + j] + Sk[j * LDP + i]);
+                    Bv[q] = 0.5 * (Sk[(16 + i) * LDP + j] + Sk[j * LDP + 16 + i]);
+                    Cv[q] = 0.5 * (Sk[(16 + i) * LDP + 16 + j] + Sk[(16 + j) * LDP + 16 + i]);
                 }
-                // the sweep left -S_kk^{-1}
+                // v (symmetric 16x16) <- -v^{-1}; pivots checked against A_tt's diagonal
+                auto sweep16 = [&](d4& v, int poff) {
 #pragma unroll
-                for (int r = 0; r < 16; ++r) piv[(16 * h + r) * LDP + j] = -v[r];
+                    for (int p = 0; p < 16; ++p) {
+                        if (ri == (p & 3)) prow[ci] = v[p >> 2];             // row p = column p
+                        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                        const double pp = prow[p];
+                        const double rowp = prow[ci];
+                        double colp[4];
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) colp[q] = prow[ri + 4 * q];
+                        if (lane == 0 && !(pp > 1e-13 * adiag[k * TS + poff + p] && isfinite(pp))) {
+                            if (atomicCAS(&A.status->code, 0, SF_NOT_SPD) == 0) {
+                                A.status->sub = sub;
+                                A.status->row = (int64_t)t * m + k * TS + poff + p;
+                            }
+                        }
+                        const double ip = 1.0 / pp;
+                        const bool jp = ci == p;
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            const bool iq = ri + 4 * q == p;
+                            const double upd = v[q] - colp[q] * rowp * ip;
+                            const double side = jp ? colp[q] * ip : upd;
+                            v[q] = iq ? (jp ? -ip : rowp * ip) : side;
+                        }
+                        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                    }
+                };
+                auto put = [&](double* buf, const d4& v, double sgn) {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) buf[(ri + 4 * q) * PB + ci] = sgn * v[q];
+                };
+                // D = op(P) op(Q) on MFMA; operand rows from 16x16 scratch blocks
+                auto mm = [&](const double* P, bool Pt, const double* Q, bool Qt) -> d4 {
+                    const int ii = lane & 15, kk = lane >> 4;
+                    d4 d = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                    for (int ks = 0; ks < 4; ++ks) {
+                        const int kx = 4 * ks + kk;
+                        const double a = Pt ? P[kx * PB + ii] : P[ii * PB + kx];
+                        const double b = Qt ? Q[ii * PB + kx] : Q[kx * PB + ii];
+                        d = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, d, 0, 0, 0);
+                    }
+                    return d;
+                };
+                auto sync_lds = [&]() {
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                };
+                sweep16(Av, 0);                               // Av = -A^-1
+                put(bA, Av, -1.0);
+                put(bB, Bv, 1.0);
+                sync_lds();
+                const d4 Xv = mm(bB, false, bA, false);       // X = B A^-1
+                put(bX, Xv, 1.0);
+                sync_lds();
+                const d4 T = mm(bX, false, bB, true);         // X B^T
+                d4 Cp;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) Cp[q] = Cv[q] - T[q];
+                sweep16(Cp, 16);                              // Cp = -C'^-1
+                put(bC, Cp, -1.0);
+                sync_lds();
+                d4 P21 = mm(bC, false, bX, false);            // C'^-1 X
+#pragma unroll
+                for (int q = 0; q < 4; ++q) P21[q] = -P21[q];
+                put(bB, P21, 1.0);
+                sync_lds();
+                const d4 T3 = mm(bX, true, bB, false);        // X^T (-C'^-1 X)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int i = ri + 4 * q, j = ci;
+                    piv[i * LDP + j] = -Av[q] - T3[q];                  // A^-1 + X^T C'^-1 X
+                    piv[(16 + i) * LDP + j] = P21[q];                   // -C'^-1 X
+                    piv[j * LDP + 16 + i] = P21[q];                     // its transpose
+                    piv[(16 + i) * LDP + 16 + j] = -Cp[q];              // C'^-1
+                }
             }
             __builtin_amdgcn_sched_barrier(0);
             __syncthreads();
