@@ -600,13 +600,19 @@ __global__ void __launch_bounds__(F2_THREADS) k_factor2(FactorArgs A) {
                 }
             }
             __syncthreads();
-            // update own blocks
+            // update own blocks.  When another pivot step follows, the blocks of
+            // column k+1 go first; that column is published and signalled, and
+            // the other ranks' wait and column load overlap the remaining updates.
+            const int kn = k + 1;
+#pragma unroll
+            for (int pass = 0; pass < 2; ++pass) {
 #pragma unroll
             for (int b = 0; b < F2_MAXBLK; ++b) {
                 const int blk = wv + F2_NW * b;
                 if (blk >= nblk) continue;
                 int I, J;
                 f2_tile_of(blk >> 2, rowA, rowB, I, J);
+                if (kn < NT ? ((pass == 0) != (I == kn || J == kn)) : pass == 1) continue;
                 const int qi = (blk >> 1) & 1, qj = blk & 1;
                 const int rr = (I == rowA) ? 0 : 1;
                 if (I != k && J != k) {
@@ -638,9 +644,12 @@ __global__ void __launch_bounds__(F2_THREADS) k_factor2(FactorArgs A) {
                 // blocks at once (register budget)
                 __builtin_amdgcn_sched_barrier(0);
             }
-            if (k + 1 < NT) {
-                f2_publish(acc, xch + (int64_t)(phase & 1) * NT * TSZ, k + 1, nblk, rowA, rowB, wv, cr, cc);
-            } else {
+            if (pass == 0 && kn < NT) {
+                f2_publish(acc, xch + (int64_t)(phase & 1) * NT * TSZ, kn, nblk, rowA, rowB, wv, cr, cc);
+                f2_signal(cnt);
+            }
+            }
+            if (kn >= NT) {
                 // ---------- line done: blocks hold -S_t^{-1} ----------------------
                 // (through this wave's scratch, so that the store code is not
                 // unrolled over the accumulators)
@@ -678,8 +687,8 @@ __global__ void __launch_bounds__(F2_THREADS) k_factor2(FactorArgs A) {
                         }
                     }
                 }
+                f2_signal(cnt);
             }
-            f2_signal(cnt);
         }
     }
 }
