@@ -216,10 +216,10 @@ int sf_create(const sf_config* cfg, void* stream, sf_context** out) {
         sf_destroy(c);
         return SF_ERR_HIP;
     }
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, sfdd::sweep_kernel(), sfdd::SOLVE_THREADS, 0) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, sfdd::sweep_kernel(), sfdd::sweep_threads(0), 0) !=
             hipSuccess || occ < 1)
         occ = 1;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ_b, sfdd::sweep_kernel_small(), sfdd::SOLVE_THREADS, 0) ==
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ_b, sfdd::sweep_kernel_small(), 256, 0) ==
             hipSuccess && occ_b >= 1)
         occ = std::min(occ, occ_b);
     const int capacity = ncu * occ;

@@ -11,7 +11,6 @@ namespace sfdd {
 
 constexpr int TS = 32;          // factor tile edge (doubles)
 constexpr int TSZ = TS * TS;    // doubles per tile
-constexpr int SOLVE_THREADS = 256;    // sweep: 3 tile waves + 1 control wave, one wave per SIMD
 constexpr int FACTOR_THREADS = 256;
 
 // One subdomain: a box of the pixel grid cut into lines along its shorter side.
@@ -114,6 +113,7 @@ int launch_sweep(sf_context* c, double* U, const double* r, int single_sub, cons
                  double* x_local);
 const void* sweep_kernel();
 const void* sweep_kernel_small();
+int sweep_threads(int fast);
 // timing helpers (api.hip): bracket a launch of kernel class `kind`
 int prof_begin(sf_context* c, int kind);
 int prof_end(sf_context* c);

@@ -49,10 +49,10 @@ constexpr int MAXR = 16;   // block rows per rank (NT <= 16)
 // h = lane / 16, holds columns 2c, 2c+1 of rows 8h..8h+7 of the stored tile:
 // tv[2i] = T[8h+i][2c], tv[2i+1] = T[8h+i][2c+1] (16-byte loads, a wave
 // instruction reads 4 rows of 256 bytes).
-__device__ __forceinline__ int64_t tile_lane_offset(int I, int J) {
+__device__ __forceinline__ int32_t tile_lane_offset(int I, int J) {
     const int lane = threadIdx.x & 63;
     const int k = J <= I ? I * (I + 1) / 2 + J : J * (J + 1) / 2 + I;
-    return (int64_t)k * TSZ + (8 * (lane >> 4)) * TS + 2 * (lane & 15);
+    return k * TSZ + (8 * (lane >> 4)) * TS + 2 * (lane & 15);
 }
 
 __device__ __forceinline__ void load_tile(const double* __restrict__ T, double tv[16]) {
@@ -158,9 +158,10 @@ __device__ __forceinline__ int own_row(int i, int rank, int P) {
 // workgroups g with g % 8 == i % 8, so the tiles that two ranks of one
 // subdomain both read are shared through one L2.  Correctness does not depend
 // on the placement: the exchange uses device-scope accesses.
-template <typename TT, int RMAX, int PF, int LMAX>
-__global__ void __launch_bounds__(SOLVE_THREADS) k_sweep(SweepArgs A) {
-    constexpr int NW = SOLVE_THREADS / 64;
+template <typename TT, int RMAX, int PF, int LMAX, int NWV>
+__global__ void __launch_bounds__(64 * NWV) k_sweep(SweepArgs A) {
+    constexpr int NTHR = 64 * NWV;
+    constexpr int NW = NWV;
     constexpr int NWT = NW - 1;                    // tile waves
     constexpr int CW0 = NWT * 64;                  // first thread of the control wave
     constexpr int NRC = (RMAX * TS + 63) / 64;     // own rows per control lane
@@ -241,16 +242,16 @@ __global__ void __launch_bounds__(SOLVE_THREADS) k_sweep(SweepArgs A) {
     }
     const int64_t rstep = mode == 1 ? m : gstep;
     // this thread's prefetched tiles (fixed for all lines): offsets inside a line
-    // Fast form (RMAX == 2, NT <= 4 NWT): slot p holds tile (row p % 2,
+    // Fast form (RMAX == 2, NT <= NWT PF / 2): slot p holds tile (row p % 2,
     // column wv + NWT (p / 2)), so a wave's tiles of one row are fixed and the
     // row partials stay in registers until one reduction per row.  General
     // form: slot p holds the tile qt = wv + NWT p of the rank's row-major list.
-    constexpr bool FAST = RMAX == 2 && PF == 8;
+    constexpr bool FAST = RMAX == 2;
     auto slot_ok = [&](int p) -> bool {
         if constexpr (FAST) return (p & 1) < R && wv + NWT * (p >> 1) < NT;
         else return wv + NWT * p < ntw;
     };
-    int64_t toff[PF];
+    int32_t toff[PF];                              // < ntiles * TSZ elements
 #pragma unroll
     for (int p = 0; p < PF; ++p) {
         if constexpr (FAST) {
@@ -269,13 +270,25 @@ __global__ void __launch_bounds__(SOLVE_THREADS) k_sweep(SweepArgs A) {
     }
 
     TT pre[PF][16];
-    double pr[RPT], pbu[RPT][6], pbd[RPT][6];
+    // prefetched right-hand side and coupling coefficients of this thread's
+    // rows: pb holds the up coefficients when the phase has an up term, else
+    // the down ones (the middle phase, which has both, reads the down ones in z)
+    double pr[RPT], pb[RPT][6];
 #pragma unroll
     for (int j = 0; j < RPT; ++j) {
         pr[j] = 0.0;
 #pragma unroll
-        for (int e = 0; e < 6; ++e) pbu[j][e] = pbd[j][e] = 0.0;
+        for (int e = 0; e < 6; ++e) pb[j][e] = 0.0;
     }
+    // B_{t+1}^T row a (nodes s, s+1 of line t+1) from the stored rows of B_{t+1}
+    auto dn_coeffs = [&](int t, int a, double* c6) {
+        const int zs = a / 3, ze = a % 3;
+        const double* Bt = Bb + (int64_t)(t + 1) * m * 6;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) c6[c] = Bt[(int64_t)(3 * zs + c) * 6 + 3 + ze];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) c6[3 + c] = zs + 1 < ms ? Bt[(int64_t)(3 * (zs + 1) + c) * 6 + ze] : 0.0;
+    };
     // coupling terms of phase q: up = B_t (rows of line t, nodes s-1, s of
     // line t-1), dn = B_{t+1}^T (nodes s, s+1 of line t+1)
     auto has_up = [&](int q, int t) -> bool {
@@ -289,21 +302,15 @@ __global__ void __launch_bounds__(SOLVE_THREADS) k_sweep(SweepArgs A) {
         const bool hu = has_up(q, t), hd = has_dn(q, t);
 #pragma unroll
         for (int j = 0; j < RPT; ++j) {             // z terms first: needed earlier
-            const int a = tid + CW0 * j, zs = a / 3, ze = a % 3;
+            const int a = tid + CW0 * j;
             if (a < m) {
                 if (q <= L) pr[j] = rsrc[j][t * rstep];
                 if (hu) {
                     const double* cf = Bb + ((int64_t)t * m + a) * 6;
 #pragma unroll
-                    for (int e = 0; e < 6; ++e) pbu[j][e] = cf[e];
-                }
-                if (hd) {
-                    const double* Bt = Bb + (int64_t)(t + 1) * m * 6;
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) pbd[j][c] = Bt[(int64_t)(3 * zs + c) * 6 + 3 + ze];
-#pragma unroll
-                    for (int c = 0; c < 3; ++c)
-                        pbd[j][3 + c] = zs + 1 < ms ? Bt[(int64_t)(3 * (zs + 1) + c) * 6 + ze] : 0.0;
+                    for (int e = 0; e < 6; ++e) pb[j][e] = cf[e];
+                } else if (hd) {
+                    dn_coeffs(t, a, pb[j]);
                 }
             }
         }
@@ -350,7 +357,7 @@ __global__ void __launch_bounds__(SOLVE_THREADS) k_sweep(SweepArgs A) {
 #pragma unroll
     for (int i = 0; i < NRC; ++i) pw[i] = 0.0;
 
-    for (int i = tid; i < NWT * RMAX * TS; i += SOLVE_THREADS) (&yw[0][0])[i] = 0.0;
+    for (int i = tid; i < NWT * RMAX * TS; i += NTHR) (&yw[0][0])[i] = 0.0;
     if (!ctl) prefetch(0);
     // Phase structure (B = workgroup barrier):
     //   control wave: [gather(q)] B z B  .  B [finish, publish(q)]
@@ -397,16 +404,22 @@ __global__ void __launch_bounds__(SOLVE_THREADS) k_sweep(SweepArgs A) {
                     if (up) {
                         if (zs > 0)
 #pragma unroll
-                            for (int e = 0; e < 3; ++e) cu = fma(pbu[j][e], vup[3 * (zs - 1) + e], cu);
+                            for (int e = 0; e < 3; ++e) cu = fma(pb[j][e], vup[3 * (zs - 1) + e], cu);
 #pragma unroll
-                        for (int e = 0; e < 3; ++e) cu = fma(pbu[j][3 + e], vup[3 * zs + e], cu);
+                        for (int e = 0; e < 3; ++e) cu = fma(pb[j][3 + e], vup[3 * zs + e], cu);
                     }
                     if (dn) {
+                        double cd[6];
+                        if (up) dn_coeffs(t, a, cd);                 // middle phase only
+                        else {
 #pragma unroll
-                        for (int e = 0; e < 3; ++e) cu = fma(pbd[j][e], vdn[3 * zs + e], cu);
+                            for (int e = 0; e < 6; ++e) cd[e] = pb[j][e];
+                        }
+#pragma unroll
+                        for (int e = 0; e < 3; ++e) cu = fma(cd[e], vdn[3 * zs + e], cu);
                         if (zs + 1 < ms)
 #pragma unroll
-                            for (int e = 0; e < 3; ++e) cu = fma(pbd[j][3 + e], vdn[3 * (zs + 1) + e], cu);
+                            for (int e = 0; e < 3; ++e) cu = fma(cd[3 + e], vdn[3 * (zs + 1) + e], cu);
                     }
                     v = back ? cu : pr[j] - cu;
                 }
@@ -505,9 +518,15 @@ __global__ void __launch_bounds__(SOLVE_THREADS) k_sweep(SweepArgs A) {
                 const int k = tid - CW0 + 64 * i;
                 if (crow[i] >= 0) {
                     double y = 0.0;
-                    for (int w = 0; w < NWT; ++w) {
-                        y += yw[w][k];
-                        yw[w][k] = 0.0;
+                    if constexpr (FAST) {
+                        // every tile wave rewrites all its rows each phase
+#pragma unroll
+                        for (int w = 0; w < NWT; ++w) y += yw[w][k];
+                    } else {
+                        for (int w = 0; w < NWT; ++w) {
+                            y += yw[w][k];
+                            yw[w][k] = 0.0;
+                        }
                     }
                     if (back) y = pw[i] - y;               // x_t = w_t - S_t^{-1} v
                     const uint64_t bits = (uint64_t)__double_as_longlong(y);
@@ -529,7 +548,7 @@ __global__ void __launch_bounds__(SOLVE_THREADS) k_sweep(SweepArgs A) {
     // lines: group 0 lines 0..k, group 1 lines k+1..nt-1
     __syncthreads();
     const int t0 = grp == 0 ? 0 : km + 1, t1 = grp == 0 ? km + 1 : nt;
-    for (int i = tid; i < (t1 - t0) * nrow; i += SOLVE_THREADS) {
+    for (int i = tid; i < (t1 - t0) * nrow; i += NTHR) {
         const int t = t0 + i / nrow, k = i % nrow;
         const int a = own_row(k / TS, rank, P) * TS + k % TS;
         if (a >= m) continue;
@@ -550,8 +569,25 @@ __global__ void k_zero_u32(uint32_t* p, int n) {
     if (i < n) p[i] = 0u;
 }
 
-const void* sweep_kernel() { return (const void*)k_sweep<double, MAXR, 4, MAXMP>; }
-const void* sweep_kernel_small() { return (const void*)k_sweep<double, 2, 8, 384>; }
+// Launch forms.  General: 4 waves (3 tile waves; one wave per SIMD, 512
+// registers each).  Fast (at most 2 block rows per rank, lines up to 384),
+// all of a phase's tiles in registers: FP64 tiles with 4 waves (8 tiles per
+// tile wave, partly in AGPRs), FP32 tiles with 8 waves (7 tile waves, 4
+// tiles each, within 256 VGPRs).
+constexpr int GEN_WAVES = 4;
+const void* sweep_kernel() { return (const void*)k_sweep<double, MAXR, 4, MAXMP, GEN_WAVES>; }
+const void* sweep_kernel_small() { return (const void*)k_sweep<double, 2, 8, 384, 4>; }
+
+static void sweep_form(const sf_context* c, bool fast, const void** kern, int* threads) {
+    if (c->cfg.factor_precision == SF_FP32) {
+        *kern = fast ? (const void*)k_sweep<float, 2, 4, 384, 8> : (const void*)k_sweep<float, MAXR, 4, MAXMP, GEN_WAVES>;
+        *threads = fast ? 512 : 64 * GEN_WAVES;
+    } else {
+        *kern = fast ? (const void*)k_sweep<double, 2, 8, 384, 4> : (const void*)k_sweep<double, MAXR, 4, MAXMP, GEN_WAVES>;
+        *threads = 64 * (fast ? 4 : GEN_WAVES);
+    }
+}
+int sweep_threads(int fast) { return fast ? 512 : 64 * GEN_WAVES; }
 
 int launch_sweep(sf_context* c, double* U, const double* r, int single_sub, const double* b_local, double* x_local) {
     SweepArgs a;
@@ -582,16 +618,14 @@ int launch_sweep(sf_context* c, double* U, const double* r, int single_sub, cons
     for (const auto& d : c->subs) maxmp = std::max(maxmp, d.mp);
     const bool fast = c->sweep_rows <= 2 && maxmp <= 384;
     const void* kern;
-    if (c->cfg.factor_precision == SF_FP32)
-        kern = fast ? (const void*)k_sweep<float, 2, 8, 384> : (const void*)k_sweep<float, MAXR, 4, MAXMP>;
-    else
-        kern = fast ? (const void*)k_sweep<double, 2, 8, 384> : (const void*)k_sweep<double, MAXR, 4, MAXMP>;
+    int threads;
+    sweep_form(c, fast, &kern, &threads);
     void* args[] = {&a};
     if (ranks > 1) {
-        if (hipLaunchCooperativeKernel(kern, dim3(grid), dim3(SOLVE_THREADS), args, 0, c->stream) != hipSuccess)
+        if (hipLaunchCooperativeKernel(kern, dim3(grid), dim3(threads), args, 0, c->stream) != hipSuccess)
             return SF_ERR_HIP;
     } else {
-        if (hipLaunchKernel(kern, dim3(grid), dim3(SOLVE_THREADS), args, 0, c->stream) != hipSuccess)
+        if (hipLaunchKernel(kern, dim3(grid), dim3(threads), args, 0, c->stream) != hipSuccess)
             return SF_ERR_HIP;
     }
     return SF_OK;
