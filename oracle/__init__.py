@@ -22,6 +22,8 @@ illumination"):
 * ``adapt``    - residual error indicator eta_K (equation (errind)) and the
                  alpha decrease rule (Section 2.3).
 * ``metrics``  - AAE and EE (Section 4).
+* ``variants`` - Gaussian presmoothing of the frames (Section 1) and the
+                 area/perimeter choice of the image split (Section 3.1).
 
 Functions whose result the paper does not fix by any printed value or closed
 form are marked "parity unpinned" in their docstrings.
