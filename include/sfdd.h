@@ -49,6 +49,8 @@ extern "C" {
 #define SF_NOT_CONVERGED    2   /* max_sweeps reached above rtol; U is written */
 #define SF_NONFINITE        3   /* NaN/Inf in the inputs or in a residual norm */
 
+#define SF_SIGMA_MAX 16.0
+
 /* factor_precision */
 #define SF_FP64      0          /* subdomain factors stored and applied in FP64 */
 #define SF_FP32      1          /* inverse Schur tiles computed in FP64, stored in
@@ -65,7 +67,10 @@ typedef struct sf_config {
     int32_t parts_y;          /* tiles down,   1 <= parts_y <= H                  */
     int32_t overlap;          /* delta >= 0: nodes shared by neighbouring boxes   */
     double  lambda;           /* regularisation of m (> 0), constant (Section 2.3) */
-    double  sigma;            /* Gaussian presmoothing of the frames; must be 0   */
+    double  sigma;            /* Gaussian presmoothing of the frames, 0 = off,
+                                 at most SF_SIGMA_MAX (Section 1: f = K_sigma * I;
+                                 sampled Gaussian |k| <= ceil(3 sigma), normalised,
+                                 rows then columns, clamp to edge)              */
     int32_t factor_precision; /* SF_FP64 or SF_FP32                               */
     int32_t band_tile;        /* sweep workgroups per chain of a subdomain; 0 = auto */
 } sf_config;
@@ -85,8 +90,8 @@ int sf_create(const sf_config* cfg, void* stream, sf_context** out);
 void sf_destroy(sf_context* ctx);
 
 /* Section 1 and 2.2: copy I0, I1 and alpha into the context and build the
- * right-hand side F_i = -int f_t a phi_i, a = (f_x, f_y, -f), f = I0 (P1),
- * f_t = I1 - I0 (P1), integrated exactly.  Returns SF_NONFINITE if a frame
+ * right-hand side F_i = -int f_t a phi_i, a = (f_x, f_y, -f), f = K_sigma * I0
+ * (P1), f_t = K_sigma * (I1 - I0) (P1), integrated exactly.  Returns SF_NONFINITE if a frame
  * value is not finite and SF_ERR_INVALID if an alpha is not finite or <= 0.
  * Makes previous factors stale.                                             */
 int sf_assemble(sf_context* ctx, const double* I0, const double* I1, const double* alpha);
@@ -153,6 +158,16 @@ int sf_plan(const sf_config* cfg, int32_t* geom);
  * stop test, 3 other.  enable: 1 = reset and start, 0 = reset and stop,
  * -1 = only read.                                                          */
 int sf_profile(sf_context* ctx, int32_t enable, double* ms, int64_t* launches);
+
+/* Section 3.1: the split parts_x x parts_y = nparts of a width x height image
+ * whose parts have the largest area / perimeter, with a part of
+ * w = width / parts_x by h = height / parts_y pixels (real-valued) having area
+ * w h and perimeter 2 (w + h); ties go to the larger parts_x.  Host-only, no
+ * device needed.  Outputs (HOST, any may be NULL): parts_x, parts_y, ratio.
+ * SF_ERR_INVALID if no split of at most one part per pixel column / row
+ * exists.                                                                  */
+int sf_choose_split(int32_t width, int32_t height, int32_t nparts, int32_t* parts_x, int32_t* parts_y,
+                    double* ratio);
 
 /* Number of subdomains over all pairs (B * parts_x * parts_y).             */
 int sf_num_subdomains(const sf_context* ctx);

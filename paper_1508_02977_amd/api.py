@@ -29,6 +29,7 @@ SF_NOT_CONVERGED = 2
 SF_NONFINITE = 3
 SF_FP64 = 0
 SF_FP32 = 1
+SF_SIGMA_MAX = 16.0
 
 c_int32 = ctypes.c_int32
 c_double = ctypes.c_double
@@ -72,6 +73,7 @@ _SIGS = {
     "sf_subdomain_geometry": (c_int32, [c_void_p, c_int32, c_void_p]),
     "sf_subdomain_solve": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p]),
     "sf_profile": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p]),
+    "sf_choose_split": (c_int32, [c_int32, c_int32, c_int32, c_void_p, c_void_p, c_void_p]),
 }
 
 _lib = None
@@ -257,6 +259,14 @@ def _geom(g):
     if len(g) > 10:
         out.update(P=g[10], chains=g[11], kmid=g[12])
     return out
+
+
+def sf_choose_split(width: int, height: int, nparts: int):
+    """(parts_x, parts_y, ratio) with the largest area / perimeter of a part (host-only)."""
+    px, py, r = c_int32(), c_int32(), c_double()
+    _check(lib().sf_choose_split(int(width), int(height), int(nparts), ctypes.byref(px), ctypes.byref(py),
+                                 ctypes.byref(r)), "sf_choose_split")
+    return px.value, py.value, r.value
 
 
 PROFILE_CLASSES = ("sweep", "factor", "residual", "other")

@@ -73,7 +73,8 @@ int check_config(const sf_config& k) {
     if (k.width < 2 || k.height < 2 || k.batch < 1) return SF_ERR_INVALID;
     if (k.parts_x < 1 || k.parts_y < 1 || k.parts_x > k.width || k.parts_y > k.height) return SF_ERR_INVALID;
     if (k.overlap < 0 || !(k.lambda > 0.0) || !std::isfinite(k.lambda)) return SF_ERR_INVALID;
-    if (k.sigma != 0.0 || (k.factor_precision != SF_FP64 && k.factor_precision != SF_FP32) || k.band_tile < 0)
+    if (!(k.sigma >= 0.0 && k.sigma <= SF_SIGMA_MAX) || (k.factor_precision != SF_FP64 && k.factor_precision != SF_FP32) ||
+        k.band_tile < 0)
         return SF_ERR_INVALID;
     if ((int64_t)k.width * k.height * k.batch > (1ll << 31)) return SF_ERR_INVALID;
     return SF_OK;
@@ -177,7 +178,7 @@ void sf_destroy(sf_context* c) {
     if (!c) return;
     void* ptrs[] = {c->d_subs, c->f0, c->ft, c->alpha, c->F, c->r, c->eta, c->Fn2,
                     c->partials, c->relres_d, c->sweeps_d, c->done_d, c->counters, c->etamax_bits,
-                    c->flags_d, c->factors, c->work, c->status_d};
+                    c->flags_d, c->factors, c->work, c->status_d, c->blur_w};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (c->host_stage) (void)hipHostFree(c->host_stage);
@@ -313,6 +314,18 @@ int sf_create(const sf_config* cfg, void* stream, sf_context** out) {
     rc |= dalloc(&c->factors, (size_t)c->factor_doubles);
     rc |= dalloc(&c->work, (size_t)c->work_doubles);
     rc |= dalloc(&c->status_d, 1);
+    // presmoothing weights (Section 1): sampled Gaussian, |k| <= ceil(3 sigma), normalised
+    std::vector<double> bw;
+    if (k.sigma > 0.0) {
+        c->blur_r = (int)std::ceil(3.0 * k.sigma);
+        double sum = 0.0;
+        for (int i = -c->blur_r; i <= c->blur_r; ++i) {
+            bw.push_back(std::exp(-(double)i * i / (2.0 * k.sigma * k.sigma)));
+            sum += bw.back();
+        }
+        for (auto& v : bw) v /= sum;
+        rc |= dalloc(&c->blur_w, bw.size());
+    }
     if (rc != SF_OK) { sf_destroy(c); return SF_ERR_OOM; }
     const size_t stage = STAGE_A + 24 * (size_t)c->B + 64;
     if (hipHostMalloc(&c->host_stage, stage, hipHostMallocDefault) != hipSuccess) {
@@ -331,6 +344,11 @@ int sf_create(const sf_config* cfg, void* stream, sf_context** out) {
         return SF_ERR_HIP;
     }
     c->sweep_epoch = 1;
+    if (!bw.empty() &&
+        hipMemcpy(c->blur_w, bw.data(), bw.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
+        sf_destroy(c);
+        return SF_ERR_HIP;
+    }
 
     hipLaunchKernelGGL(k_zero_status_api, dim3(1), dim3(1), 0, c->stream, c->status_d);
     if (hipGetLastError() != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess) {
@@ -352,7 +370,18 @@ int sf_assemble(sf_context* c, const double* I0, const double* I1, const double*
     SF_HIP(hipStreamSynchronize(c->stream));
     if (hf[0]) return SF_NONFINITE;
     if (hf[1]) return SF_ERR_INVALID;
-    SF_TRY(sfdd::launch_assemble(c, I0, I1, alpha));
+    if (c->blur_r > 0) {
+        // smoothed frames in the residual array (free until the first solve)
+        const int64_t n = (int64_t)c->W * c->H * c->B;
+        double* s0 = c->r;
+        double* s1 = c->r + n;
+        double* tmp = c->r + 2 * n;
+        SF_TRY(sfdd::launch_presmooth(c, I0, s0, tmp));
+        SF_TRY(sfdd::launch_presmooth(c, I1, s1, tmp));
+        SF_TRY(sfdd::launch_assemble(c, s0, s1, alpha));
+    } else {
+        SF_TRY(sfdd::launch_assemble(c, I0, I1, alpha));
+    }
     c->state = ST_ASSEMBLED;
     return SF_OK;
 }
@@ -483,6 +512,30 @@ int sf_indicator(sf_context* c, const double* U, double* eta) {
     if (!c || !U || !eta) return SF_ERR_INVALID;
     if (c->state < ST_ASSEMBLED) return SF_ERR_STATE;
     return sfdd::launch_indicator(c, U, eta, 1);
+}
+
+int sf_choose_split(int32_t width, int32_t height, int32_t nparts, int32_t* parts_x, int32_t* parts_y,
+                    double* ratio) {
+    if (width < 2 || height < 2 || nparts < 1) return SF_ERR_INVALID;
+    int bx = 0, by = 0;
+    double br = -1.0;
+    for (int px = 1; px <= nparts; ++px) {
+        if (nparts % px) continue;
+        const int py = nparts / px;
+        if (px > width || py > height) continue;
+        const double w = (double)width / px, h = (double)height / py;
+        const double r = (w * h) / (2.0 * (w + h));
+        if (r > br || (r == br && px > bx)) {
+            bx = px;
+            by = py;
+            br = r;
+        }
+    }
+    if (bx == 0) return SF_ERR_INVALID;
+    if (parts_x) *parts_x = bx;
+    if (parts_y) *parts_y = by;
+    if (ratio) *ratio = br;
+    return SF_OK;
 }
 
 int sf_num_subdomains(const sf_context* c) { return c ? c->nsub : SF_ERR_INVALID; }

@@ -305,6 +305,37 @@ __global__ void k_zero_u64(uint64_t* p, int n) {
         if (hipGetLastError() != hipSuccess) return SF_ERR_HIP; \
     } while (0)
 
+// --- presmoothing (Section 1): f = K_sigma * I ------------------------------
+// One pass of the separable Gaussian along x (axis 0) or y (axis 1): every
+// output pixel sums w[k+R] in[clamped neighbour at offset k], k = -R..R in
+// increasing order; B frames of W x H, row-major.
+__global__ void k_blur(const double* __restrict__ in, double* __restrict__ out, const double* __restrict__ w,
+                       int R, int W, int H, int64_t n, int axis) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t frame = i / ((int64_t)W * H);
+    const int p = (int)(i - frame * W * H), x = p % W, y = p / W;
+    const double* f = in + frame * W * H;
+    double s = 0.0;
+    for (int k = -R; k <= R; ++k) {
+        const int xx = axis == 0 ? min(max(x + k, 0), W - 1) : x;
+        const int yy = axis == 1 ? min(max(y + k, 0), H - 1) : y;
+        s += w[k + R] * f[(int64_t)yy * W + xx];
+    }
+    out[i] = s;
+}
+
+// I -> smoothed frames in out (B frames), through tmp
+int launch_presmooth(sf_context* c, const double* I, double* out, double* tmp) {
+    const int64_t n = (int64_t)c->W * c->H * c->B;
+    const unsigned blocks = (unsigned)((n + 255) / 256);
+    hipLaunchKernelGGL(k_blur, dim3(blocks), dim3(256), 0, c->stream, I, tmp, c->blur_w, c->blur_r, c->W, c->H, n, 0);
+    SF_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_blur, dim3(blocks), dim3(256), 0, c->stream, tmp, out, c->blur_w, c->blur_r, c->W, c->H, n, 1);
+    SF_LAUNCH_CHECK();
+    return SF_OK;
+}
+
 int launch_validate(sf_context* c, const double* I0, const double* I1, const double* alpha) {
     const int64_t nn = (int64_t)c->W * c->H * c->B;
     const int64_t ne = (int64_t)(c->W - 1) * (c->H - 1) * 2 * c->B;

@@ -66,6 +66,8 @@ struct sf_context {
     int factor_pf;                  // workgroups per subdomain in the cooperative factor (0: one-WG factor)
     int factor_chunk;               // subdomains per cooperative factor launch
     uint32_t sweep_epoch;           // tag base for the sweep's published rows
+    double* blur_w;                 // presmoothing weights, 2 blur_r + 1 (sigma > 0)
+    int blur_r;
     // per-pair field data
     double *f0, *ft, *alpha;        // [B][H][W], [B][H][W], [B][H-1][W-1][2]
     double *F, *r;                  // [B][3][H][W]
@@ -100,6 +102,7 @@ struct sf_context {
 namespace sfdd {
 int launch_validate(sf_context* c, const double* I0, const double* I1, const double* alpha);
 int launch_assemble(sf_context* c, const double* I0, const double* I1, const double* alpha);
+int launch_presmooth(sf_context* c, const double* I, double* out, double* tmp);
 int launch_residual(sf_context* c, const double* U, double* r, int fuse_converge, double rtol,
                     int sweep, int max_sweeps);
 int launch_indicator(sf_context* c, const double* U, double* eta, int reset_max);

@@ -60,3 +60,30 @@ def test_plan_batch_and_invalid():
         api.sf_plan(1, 10, 1, 1, 1, 0)
     with pytest.raises(api.SfError):
         api.sf_plan(10, 10, 1, 11, 1, 0)
+
+
+@pytest.mark.parametrize("W,H,n", [(48, 48, 12), (640, 480, 16), (1920, 1080, 84), (37, 29, 6), (64, 64, 7),
+                                   (300, 136, 2), (5, 40, 8)])
+def test_split_chooser_matches_oracle(W, H, n):
+    from oracle import variants
+    _ensure_built()
+    assert api.sf_choose_split(W, H, n) == variants.choose_split(W, H, n)
+
+
+def test_split_chooser_worked_example_and_invalid():
+    _ensure_built()
+    px, py, r = api.sf_choose_split(48, 48, 12)
+    assert (px, py) == (4, 3) and round(r, 3) == 3.429
+    with pytest.raises(api.SfError):
+        api.sf_choose_split(3, 3, 16)        # no split with at most one part per pixel
+    with pytest.raises(api.SfError):
+        api.sf_choose_split(48, 48, 0)
+
+
+def test_sigma_bounds():
+    _ensure_built()
+    cfg_ok = api.make_config(32, 32, 1, 2, 2, 4, sigma=api.SF_SIGMA_MAX)
+    cfg_bad = api.make_config(32, 32, 1, 2, 2, 4, sigma=api.SF_SIGMA_MAX + 0.5)
+    assert api.lib().sf_plan(cfg_ok, None) == 4
+    assert api.lib().sf_plan(cfg_bad, None) == api.SF_ERR_INVALID
+    assert api.lib().sf_plan(api.make_config(32, 32, 1, 2, 2, 4, sigma=-1.0), None) == api.SF_ERR_INVALID
