@@ -24,6 +24,8 @@ illumination"):
 * ``metrics``  - AAE and EE (Section 4).
 * ``variants`` - Gaussian presmoothing of the frames (Section 1) and the
                  area/perimeter choice of the image split (Section 3.1).
+* ``adjoint``  - gradients of a loss of the solution with respect to the
+                 frames and alpha by the adjoint of the discrete system.
 
 Functions whose result the paper does not fix by any printed value or closed
 form are marked "parity unpinned" in their docstrings.
