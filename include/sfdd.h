@@ -109,11 +109,33 @@ int sf_factor_subdomains(sf_context* ctx);
  * stop a pair when relres <= rtol or after max_sweeps sweeps; otherwise
  * U[O_i] += (A_i^{-1} r[S_i])[O_i] for every subdomain i (O_i its owned
  * nodes).  U [B][3][H][W] is read and overwritten.  sweeps [B] and relres
- * [B] are HOST arrays (either may be NULL).  A pair with F = 0 returns
+ * [B] are HOST arrays (either may be NULL).  A pair with F = 0 gets
  * U = 0 after 0 sweeps.  Returns SF_NOT_CONVERGED if a pair stopped on
  * max_sweeps above rtol (U still written), SF_NONFINITE on a NaN norm.   */
 int sf_schwarz_solve(sf_context* ctx, double* U, double rtol, int32_t max_sweeps,
                      int32_t* sweeps, double* relres);
+
+/* Gradients of a loss L(U) of the discrete solution (Section 2.2, A U = F)
+ * with respect to the frames and alpha, by the adjoint method.  The adjoint
+ * state P solves A P = G, G = dL/dU (A is symmetric), with the same
+ * factors and RAS iteration as sf_schwarz_solve (stop at
+ * ||G - A P|| <= rtol ||G|| or max_sweeps; a pair with G = 0 gets P = 0).
+ * Then, with p = a.P, e = a.U + f_t and a = (f_x, f_y, -f):
+ *   dalpha_K = -|K| (grad P1.grad U1 + grad P2.grad U2)
+ *   dI1_n    = -int p phi_n
+ *   dI0_n    = -int (grad phi_n.(P1,P2) - phi_n P3) e
+ *                   + p (grad phi_n.(U1,U2) - phi_n U3 - phi_n)
+ * (the frame integrals by a degree-4 exact triangle rule).  U, G, P are
+ * [B][3][H][W] device arrays; P holds the initial iterate on entry (zeros
+ * are a fine start) and the adjoint state on return.  dI0, dI1 [B][H][W] and
+ * dalpha [B][H-1][W-1][2] are device outputs, any may be NULL.  sweeps and
+ * relres [B] are HOST arrays or NULL.  Needs current factors
+ * (SF_ERR_STATE otherwise); SF_ERR_INVALID when the context presmooths
+ * (sigma > 0).  Returns SF_NOT_CONVERGED (gradients still written) like
+ * sf_schwarz_solve.                                                       */
+int sf_adjoint(sf_context* ctx, const double* U, const double* G, double* P,
+               double* dI0, double* dI1, double* dalpha,
+               double rtol, int32_t max_sweeps, int32_t* sweeps, double* relres);
 
 /* Section 2.3: residual indicator eta_K (flow components, alpha weights,
  * element residual + half the flux jumps) and the decrease rule

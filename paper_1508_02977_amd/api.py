@@ -62,6 +62,8 @@ _SIGS = {
     "sf_assemble": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "sf_factor_subdomains": (c_int32, [c_void_p]),
     "sf_schwarz_solve": (c_int32, [c_void_p, c_void_p, c_double, c_int32, c_void_p, c_void_p]),
+    "sf_adjoint": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_double,
+                             c_int32, c_void_p, c_void_p]),
     "sf_update_alpha": (c_int32, [c_void_p, c_void_p, c_void_p, c_double, c_double, c_double, c_void_p]),
     "sf_error_detail": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "sf_status_string": (ctypes.c_char_p, [c_int32]),
@@ -134,6 +136,7 @@ class Context:
 
     handle: c_void_p
     cfg: sf_config
+    version: int = 0          # bumped by every assemble / factor through this module
 
     @property
     def W(self):
@@ -191,11 +194,13 @@ def sf_destroy(ctx: Context) -> None:
 
 
 def sf_assemble(ctx: Context, I0, I1, alpha) -> None:
+    ctx.version += 1
     _check(lib().sf_assemble(ctx.handle, _dev(I0, ctx.frame_shape(), "I0"), _dev(I1, ctx.frame_shape(), "I1"),
                              _dev(alpha, ctx.alpha_shape(), "alpha")), "sf_assemble")
 
 
 def sf_factor_subdomains(ctx: Context) -> None:
+    ctx.version += 1
     _check(lib().sf_factor_subdomains(ctx.handle), "sf_factor_subdomains", ctx)
 
 
@@ -209,9 +214,29 @@ def sf_schwarz_solve(ctx: Context, U, rtol: float, max_sweeps: int):
     return code, list(sw), list(rr)
 
 
+def sf_adjoint(ctx: Context, U, G, P, dI0=None, dI1=None, dalpha=None, rtol: float = 1e-10,
+               max_sweeps: int = 1000):
+    """Adjoint state P (A P = G, P is the initial iterate) and the gradients
+    dI0, dI1 [B,H,W], dalpha [B,H-1,W-1,2] (each optional, written in place).
+    Returns (status, sweeps[B], relres[B])."""
+    sw = (c_int32 * ctx.B)()
+    rr = (c_double * ctx.B)()
+
+    def opt(t, shape, name):
+        return c_void_p() if t is None else _dev(t, shape, name)
+
+    code = lib().sf_adjoint(ctx.handle, _dev(U, ctx.field_shape(), "U"), _dev(G, ctx.field_shape(), "G"),
+                            _dev(P, ctx.field_shape(), "P"), opt(dI0, ctx.frame_shape(), "dI0"),
+                            opt(dI1, ctx.frame_shape(), "dI1"), opt(dalpha, ctx.alpha_shape(), "dalpha"),
+                            float(rtol), int(max_sweeps), ctypes.cast(sw, c_void_p), ctypes.cast(rr, c_void_p))
+    _check(code, "sf_adjoint", ctx, allow=(SF_NOT_CONVERGED,))
+    return code, list(sw), list(rr)
+
+
 def sf_update_alpha(ctx: Context, U, alpha, kappa=1.0, eta_thr=0.1, alpha_th=1e-3):
     """Updates ``alpha`` in place; returns ||eta||_inf per pair."""
     em = (c_double * ctx.B)()
+    ctx.version += 1
     _check(lib().sf_update_alpha(ctx.handle, _dev(U, ctx.field_shape(), "U"),
                                  _dev(alpha, ctx.alpha_shape(), "alpha"), float(kappa), float(eta_thr),
                                  float(alpha_th), ctypes.cast(em, c_void_p)), "sf_update_alpha")
@@ -332,3 +357,54 @@ def run_pipeline(ctx: Context, I0, I1, alpha, U, rtol=1e-8, max_sweeps=1000, pas
         if it < passes:
             etas.append(sf_update_alpha(ctx, U, alpha, kappa, eta_thr, alpha_th))
     return PipelineResult(sweeps, rels, etas, status)
+
+
+# ---- autograd ----------------------------------------------------------------
+
+def _schwarz_solve_function():
+    import torch
+
+    class SchwarzSolve(torch.autograd.Function):
+        """U = A(I0, alpha)^{-1} F(I0, I1) by the RAS solver; the backward pass
+        is the adjoint solve of ``sf_adjoint`` with the same factors.  The
+        context must not be re-assembled or re-factored between the two."""
+
+        @staticmethod
+        def forward(fctx, ctx, I0, I1, alpha, rtol, max_sweeps):
+            I0c, I1c, alc = (t.detach().contiguous() for t in (I0, I1, alpha))
+            sf_assemble(ctx, I0c, I1c, alc)
+            sf_factor_subdomains(ctx)
+            U = torch.zeros(ctx.field_shape(), dtype=torch.float64, device=I0.device)
+            sf_schwarz_solve(ctx, U, rtol, max_sweeps)
+            fctx.sf = (ctx, ctx.version, rtol, max_sweeps)
+            fctx.save_for_backward(U)
+            return U
+
+        @staticmethod
+        def backward(fctx, gU):
+            ctx, version, rtol, max_sweeps = fctx.sf
+            if ctx.version != version:
+                raise RuntimeError("SchwarzSolve backward: the context was re-assembled or re-factored "
+                                   "after the forward pass")
+            (U,) = fctx.saved_tensors
+            need = fctx.needs_input_grad
+            P = torch.zeros_like(U)
+            dI0 = torch.empty(ctx.frame_shape(), dtype=torch.float64, device=U.device) if need[1] else None
+            dI1 = torch.empty(ctx.frame_shape(), dtype=torch.float64, device=U.device) if need[2] else None
+            dal = torch.empty(ctx.alpha_shape(), dtype=torch.float64, device=U.device) if need[3] else None
+            sf_adjoint(ctx, U, gU.contiguous(), P, dI0, dI1, dal, rtol, max_sweeps)
+            return None, dI0, dI1, dal, None, None
+
+    return SchwarzSolve
+
+
+_SCHWARZ_SOLVE = None
+
+
+def schwarz_solve(ctx: Context, I0, I1, alpha, rtol: float = 1e-10, max_sweeps: int = 1000):
+    """Differentiable solve: U [B,3,H,W] from I0, I1 [B,H,W] and alpha
+    [B,H-1,W-1,2] (float64 CUDA tensors); gradients by the adjoint method."""
+    global _SCHWARZ_SOLVE
+    if _SCHWARZ_SOLVE is None:
+        _SCHWARZ_SOLVE = _schwarz_solve_function()
+    return _SCHWARZ_SOLVE.apply(ctx, I0, I1, alpha, float(rtol), int(max_sweeps))

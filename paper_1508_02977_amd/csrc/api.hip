@@ -176,7 +176,7 @@ const char* sf_status_string(int s) {
 
 void sf_destroy(sf_context* c) {
     if (!c) return;
-    void* ptrs[] = {c->d_subs, c->f0, c->ft, c->alpha, c->F, c->r, c->eta, c->Fn2,
+    void* ptrs[] = {c->d_subs, c->f0, c->ft, c->alpha, c->F, c->r, c->eta, c->Fn2, c->Gn2,
                     c->partials, c->relres_d, c->sweeps_d, c->done_d, c->counters, c->etamax_bits,
                     c->flags_d, c->factors, c->work, c->status_d, c->blur_w};
     for (void* p : ptrs)
@@ -304,6 +304,7 @@ int sf_create(const sf_config* cfg, void* stream, sf_context** out) {
     rc |= dalloc(&c->F, 3 * nn * c->B);
     rc |= dalloc(&c->r, 3 * nn * c->B);
     rc |= dalloc(&c->Fn2, c->B);
+    rc |= dalloc(&c->Gn2, c->B);
     rc |= dalloc(&c->partials, (size_t)c->npart * c->B);
     rc |= dalloc(&c->relres_d, c->B);
     rc |= dalloc(&c->sweeps_d, c->B);
@@ -415,9 +416,11 @@ int sf_factor_subdomains(sf_context* c) {
     return SF_OK;
 }
 
-int sf_schwarz_solve(sf_context* c, double* U, double rtol, int32_t max_sweeps, int32_t* sweeps, double* relres) {
-    if (!c || !U || max_sweeps < 0 || !(rtol >= 0.0)) return SF_ERR_INVALID;
-    if (c->state != ST_FACTORED) return SF_ERR_STATE;
+// RAS iteration on A U = rhs from the U given, stopping per pair at
+// ||rhs - A U|| <= rtol ||rhs|| (rhs_n2 = ||rhs||^2 on the device).
+static int schwarz_loop(sf_context* c, double* U, const double* rhs, const double* rhs_n2, double rtol,
+                        int32_t max_sweeps, int32_t* sweeps, double* relres) {
+    SF_TRY(sfdd::launch_zero_where_rhs_zero(c, U, rhs_n2));
     SF_TRY(fill_i32(c, c->done_d, c->B, 0));
     hipLaunchKernelGGL(k_zero_status_api, dim3(1), dim3(1), 0, c->stream, c->status_d);
     SF_HIP(hipGetLastError());
@@ -426,7 +429,7 @@ int sf_schwarz_solve(sf_context* c, double* U, double rtol, int32_t max_sweeps, 
     sfdd::DevStatus* hst = (sfdd::DevStatus*)c->host_stage;
     for (int k = 0; k <= max_sweeps; ++k) {
         SF_TRY(sfdd::prof_begin(c, sfdd::PROF_RESIDUAL));
-        SF_TRY(sfdd::launch_residual(c, U, c->r, 1, rtol, k, max_sweeps));
+        SF_TRY(sfdd::launch_residual(c, U, c->r, 1, rtol, k, max_sweeps, rhs, rhs_n2));
         SF_TRY(sfdd::prof_end(c));
         if (k == max_sweeps) break;
         SF_TRY(sfdd::prof_begin(c, sfdd::PROF_SWEEP));
@@ -459,6 +462,25 @@ int sf_schwarz_solve(sf_context* c, double* U, double rtol, int32_t max_sweeps, 
     }
     const int code = pull_status(c);
     if (code != SF_OK) return code;
+    return rc;
+}
+
+int sf_schwarz_solve(sf_context* c, double* U, double rtol, int32_t max_sweeps, int32_t* sweeps, double* relres) {
+    if (!c || !U || max_sweeps < 0 || !(rtol >= 0.0)) return SF_ERR_INVALID;
+    if (c->state != ST_FACTORED) return SF_ERR_STATE;
+    return schwarz_loop(c, U, c->F, c->Fn2, rtol, max_sweeps, sweeps, relres);
+}
+
+int sf_adjoint(sf_context* c, const double* U, const double* G, double* P, double* dI0, double* dI1, double* dalpha,
+               double rtol, int32_t max_sweeps, int32_t* sweeps, double* relres) {
+    if (!c || !U || !G || !P || max_sweeps < 0 || !(rtol >= 0.0)) return SF_ERR_INVALID;
+    if (c->blur_r > 0) return SF_ERR_INVALID;   // gradients are taken with respect to unsmoothed frames
+    if (c->state != ST_FACTORED) return SF_ERR_STATE;
+    SF_TRY(sfdd::launch_norm2(c, G, c->Gn2));
+    const int rc = schwarz_loop(c, P, G, c->Gn2, rtol, max_sweeps, sweeps, relres);
+    if (rc != SF_OK && rc != SF_NOT_CONVERGED) return rc;
+    SF_TRY(sfdd::launch_adjoint_gradients(c, U, P, dI0, dI1, dalpha));
+    SF_HIP(hipStreamSynchronize(c->stream));
     return rc;
 }
 

@@ -305,6 +305,164 @@ __global__ void k_zero_u64(uint64_t* p, int n) {
         if (hipGetLastError() != hipSuccess) return SF_ERR_HIP; \
     } while (0)
 
+// --- adjoint gradients ------------------------------------------------------
+// For a loss L(U) of the solution of A(theta) U = F(theta) and the adjoint
+// state P (A P = dL/dU, A symmetric), dL/dtheta = -d/dtheta [P^T (A U - F)] at
+// fixed U, P.  P^T (A U - F) = sum_K int_K (a.P)(a.U + f_t) + alpha_K
+// (grad P1.grad U1 + grad P2.grad U2) + lambda grad P3.grad U3, a = (f_x, f_y, -f).
+
+// dL/dalpha_K = -|K| sum_{c=1,2} grad P_c . grad U_c, one thread per element
+__global__ void k_adj_alpha(const double* __restrict__ U, const double* __restrict__ P, double* __restrict__ dal,
+                            int W, int H) {
+    const int pair = blockIdx.y;
+    const int64_t nn = (int64_t)W * H, ne = (int64_t)(W - 1) * (H - 1) * 2;
+    const int64_t e_id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e_id >= ne) return;
+    const int t = (int)(e_id & 1), cell = (int)(e_id >> 1);
+    const int cx = cell % (W - 1), cy = cell / (W - 1);
+    const double* Up = U + pair * 3 * nn;
+    const double* Pp = P + pair * 3 * nn;
+    int64_t nv[3];
+#pragma unroll
+    for (int v = 0; v < 3; ++v) nv[v] = (int64_t)(cy + vdy(t, v)) * W + cx + vdx(t, v);
+    double s = 0.0;
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            double su = 0.0;
+#pragma unroll
+            for (int j = 0; j < 3; ++j) su = fma(stiff(t, i, j), Up[c * nn + nv[j]], su);
+            s = fma(Pp[c * nn + nv[i]], su, s);
+        }
+    dal[pair * ne + e_id] = -s;
+}
+
+// gradient of the P1 basis function of local vertex v on T0 / T1
+__device__ __forceinline__ void basis_grad(int t, int v, double& gx, double& gy) {
+    if (t == 0) { gx = v == 0 ? -1.0 : (v == 1 ? 1.0 : 0.0); gy = v == 1 ? -1.0 : (v == 2 ? 1.0 : 0.0); }
+    else        { gx = v == 1 ? 1.0 : (v == 2 ? -1.0 : 0.0); gy = v == 0 ? -1.0 : (v == 2 ? 1.0 : 0.0); }
+}
+
+// dL/dI1_n = -sum_K int_K p phi_n and
+// dL/dI0_n = -sum_K int_K (grad phi_n.(P1,P2) - phi_n P3) e + p (grad phi_n.(U1,U2) - phi_n U3 - phi_n)
+// with p = a.P, e = a.U + f_t: a gather over the six elements around node n,
+// each integrand (degree <= 4) by the 6-point degree-4 Dunavant rule.
+__global__ void k_adj_frames(const double* __restrict__ f0, const double* __restrict__ ft,
+                             const double* __restrict__ U, const double* __restrict__ P,
+                             double* __restrict__ dI0, double* __restrict__ dI1, int W, int H) {
+    const int pair = blockIdx.y;
+    const int64_t nn = (int64_t)W * H;
+    const int64_t node = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (node >= nn) return;
+    const int x = (int)(node % W), y = (int)(node / W);
+    const double* fp = f0 + pair * nn;
+    const double* tp = ft + pair * nn;
+    const double* Up = U + pair * 3 * nn;
+    const double* Pp = P + pair * 3 * nn;
+    const double qa[2] = {0.44594849091596489, 0.091576213509770743};
+    const double qw[2] = {0.22338158967801147, 0.10995174365532187};
+    double s0 = 0.0, s1 = 0.0;
+    for (int k = 0; k < 6; ++k) {
+        const Around a = around(k);
+        const int cx = x + a.dcx, cy = y + a.dcy;
+        if (cx < 0 || cy < 0 || cx >= W - 1 || cy >= H - 1) continue;
+        double fv[3], tv[3], uv[3][3], pv[3][3];
+        for (int v = 0; v < 3; ++v) {
+            const int64_t n = (int64_t)(cy + vdy(a.t, v)) * W + cx + vdx(a.t, v);
+            fv[v] = fp[n];
+            tv[v] = tp[n];
+            for (int c = 0; c < 3; ++c) {
+                uv[v][c] = Up[c * nn + n];
+                pv[v][c] = Pp[c * nn + n];
+            }
+        }
+        double gx, gy, bx, by;
+        elem_grad(a.t, fv, gx, gy);
+        basis_grad(a.t, a.v, bx, by);
+        for (int g = 0; g < 2; ++g) {
+            const double qa_ = qa[g], qb = 1.0 - 2.0 * qa_;
+            for (int q = 0; q < 3; ++q) {
+                double l[3] = {qa_, qa_, qa_};
+                l[q] = qb;
+                double f = 0.0, ftq = 0.0, u[3] = {0.0, 0.0, 0.0}, pq[3] = {0.0, 0.0, 0.0};
+                for (int v = 0; v < 3; ++v) {
+                    f = fma(l[v], fv[v], f);
+                    ftq = fma(l[v], tv[v], ftq);
+                    for (int c = 0; c < 3; ++c) {
+                        u[c] = fma(l[v], uv[v][c], u[c]);
+                        pq[c] = fma(l[v], pv[v][c], pq[c]);
+                    }
+                }
+                const double phi = l[a.v];
+                const double p = gx * pq[0] + gy * pq[1] - f * pq[2];
+                const double e = gx * u[0] + gy * u[1] - f * u[2] + ftq;
+                const double w = 0.5 * qw[g];                         // |K| = 1/2
+                s1 = fma(w, p * phi, s1);
+                const double d0 = (bx * pq[0] + by * pq[1] - phi * pq[2]) * e +
+                                  p * (bx * u[0] + by * u[1] - phi * u[2] - phi);
+                s0 = fma(w, d0, s0);
+            }
+        }
+    }
+    if (dI0) dI0[pair * nn + node] = -s0;
+    if (dI1) dI1[pair * nn + node] = -s1;
+}
+
+// ||G||^2 per pair (block partials, then the fixed-order finish)
+__global__ void k_norm2_partials(const double* __restrict__ G, double* __restrict__ partials, int npart, int64_t nn3) {
+    __shared__ double sh[NODE_THREADS / 64];
+    const int pair = blockIdx.y;
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nn3; i += (int64_t)npart * blockDim.x) {
+        const double v = G[pair * nn3 + i];
+        acc = fma(v, v, acc);
+    }
+    const double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) partials[pair * npart + blockIdx.x] = s;
+}
+
+// A pair whose right-hand side is 0 has the solution 0: clear its iterate.
+__global__ void k_zero_where_rhs_zero(double* __restrict__ U, const double* __restrict__ rhs_n2, int64_t nn3) {
+    const int pair = blockIdx.y;
+    if (rhs_n2[pair] != 0.0) return;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nn3; i += (int64_t)gridDim.x * blockDim.x)
+        U[pair * nn3 + i] = 0.0;
+}
+
+int launch_zero_where_rhs_zero(sf_context* c, double* U, const double* rhs_n2) {
+    hipLaunchKernelGGL(k_zero_where_rhs_zero, dim3(c->npart, c->B), dim3(NODE_THREADS), 0, c->stream, U, rhs_n2,
+                       3ll * c->W * c->H);
+    SF_LAUNCH_CHECK();
+    return SF_OK;
+}
+
+int launch_norm2(sf_context* c, const double* G, double* out) {
+    const int64_t nn3 = 3ll * c->W * c->H;
+    hipLaunchKernelGGL(k_norm2_partials, dim3(c->npart, c->B), dim3(NODE_THREADS), 0, c->stream, G, c->partials,
+                       c->npart, nn3);
+    SF_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_finalize_norm, dim3(c->B), dim3(64), 0, c->stream, c->partials, c->npart, out);
+    SF_LAUNCH_CHECK();
+    return SF_OK;
+}
+
+int launch_adjoint_gradients(sf_context* c, const double* U, const double* P, double* dI0, double* dI1,
+                             double* dal) {
+    const int64_t nn = (int64_t)c->W * c->H, ne = (int64_t)(c->W - 1) * (c->H - 1) * 2;
+    if (dal) {
+        hipLaunchKernelGGL(k_adj_alpha, dim3((unsigned)((ne + 255) / 256), c->B), dim3(256), 0, c->stream, U, P, dal,
+                           c->W, c->H);
+        SF_LAUNCH_CHECK();
+    }
+    if (dI0 || dI1) {
+        hipLaunchKernelGGL(k_adj_frames, dim3((unsigned)((nn + 255) / 256), c->B), dim3(256), 0, c->stream, c->f0,
+                           c->ft, U, P, dI0, dI1, c->W, c->H);
+        SF_LAUNCH_CHECK();
+    }
+    return SF_OK;
+}
+
 // --- presmoothing (Section 1): f = K_sigma * I ------------------------------
 // One pass of the separable Gaussian along x (axis 0) or y (axis 1): every
 // output pixel sums w[k+R] in[clamped neighbour at offset k], k = -R..R in
@@ -357,16 +515,18 @@ int launch_assemble(sf_context* c, const double* I0, const double* I1, const dou
 }
 
 int launch_residual(sf_context* c, const double* U, double* r, int fuse_converge, double rtol, int sweep,
-                    int max_sweeps) {
+                    int max_sweeps, const double* rhs, const double* rhs_n2) {
+    if (!rhs) rhs = c->F;
+    if (!rhs_n2) rhs_n2 = c->Fn2;
     const int64_t nn = (int64_t)c->W * c->H;
     dim3 grid((unsigned)((nn + NODE_THREADS - 1) / NODE_THREADS), c->B);
-    hipLaunchKernelGGL(k_residual, grid, dim3(NODE_THREADS), 0, c->stream, c->f0, c->alpha, c->F, U, r,
+    hipLaunchKernelGGL(k_residual, grid, dim3(NODE_THREADS), 0, c->stream, c->f0, c->alpha, rhs, U, r,
                        c->partials, c->npart, c->W, c->H, c->cfg.lambda,
                        fuse_converge ? (const int32_t*)c->done_d : (const int32_t*)nullptr);
     SF_LAUNCH_CHECK();
     if (fuse_converge) {
         hipLaunchKernelGGL(k_converge, dim3(c->B), dim3(NODE_THREADS), 0, c->stream, c->partials, c->npart,
-                           c->Fn2, c->relres_d, c->sweeps_d, c->done_d, rtol, sweep, max_sweeps);
+                           rhs_n2, c->relres_d, c->sweeps_d, c->done_d, rtol, sweep, max_sweeps);
     } else {
         hipLaunchKernelGGL(k_finalize_norm, dim3(c->B), dim3(64), 0, c->stream, c->partials, c->npart,
                            c->relres_d);

@@ -73,6 +73,7 @@ struct sf_context {
     double *F, *r;                  // [B][3][H][W]
     double *eta;                    // [B][H-1][W-1][2] indicator scratch
     double *Fn2;                    // [B] ||F||^2
+    double *Gn2;                    // [B] ||G||^2 of an adjoint right-hand side
     double *partials;               // reduction scratch
     int npart;                      // partial blocks per pair for node reductions
     double *relres_d;               // [B]
@@ -103,8 +104,12 @@ namespace sfdd {
 int launch_validate(sf_context* c, const double* I0, const double* I1, const double* alpha);
 int launch_assemble(sf_context* c, const double* I0, const double* I1, const double* alpha);
 int launch_presmooth(sf_context* c, const double* I, double* out, double* tmp);
-int launch_residual(sf_context* c, const double* U, double* r, int fuse_converge, double rtol,
-                    int sweep, int max_sweeps);
+int launch_residual(sf_context* c, const double* U, double* r, int fuse_converge, double rtol, int sweep,
+                    int max_sweeps, const double* rhs = nullptr, const double* rhs_n2 = nullptr);
+int launch_norm2(sf_context* c, const double* G, double* out);
+int launch_zero_where_rhs_zero(sf_context* c, double* U, const double* rhs_n2);
+int launch_adjoint_gradients(sf_context* c, const double* U, const double* P, double* dI0, double* dI1,
+                             double* dal);
 int launch_indicator(sf_context* c, const double* U, double* eta, int reset_max);
 int launch_alpha_update(sf_context* c, const double* eta, double* alpha_out, double kappa,
                         double eta_thr, double alpha_th);
