@@ -13,6 +13,7 @@ torch = pytest.importorskip("torch")
 from paper_1508_02977_amd import api  # noqa: E402
 
 CASES = [
+    dict(kind="plain64", seed=1, W=64, H=64, px=2, py=2, d=4),      # the 64x64 crop
     dict(kind="plain64", seed=1, W=48, H=40, px=2, py=2, d=4),
     dict(kind="plain640", seed=3, W=61, H=37, px=3, py=2, d=5),     # ragged tiles
     dict(kind="plain64", seed=7, W=20, H=26, px=1, py=1, d=0),      # one subdomain
@@ -111,6 +112,65 @@ def test_autograd_matches_central_differences(gpu):
             an = float((g * v).sum())
             assert abs(fd - an) <= 1e-5 * max(abs(fd), 1e-2), (name, fd, an)
     ctx.close()
+
+
+def test_gradients_on_64x64_match_64_central_differences(gpu):
+    # 64 random directions per input, h = 1e-6, FP64 solves to 1e-13
+    W, H = 64, 64
+    p = synth.make_pair("plain64", 1, W=W, H=H)
+    al = synth.random_alpha(W, H, 5)
+    w = dev(np.random.default_rng(6).normal(scale=0.5, size=(1, 2, H, W)))
+    ctx = api.sf_create(W, H, 1, 2, 2, 4)
+
+    def loss(I0, I1, a):
+        U = api.schwarz_solve(ctx, I0, I1, a, rtol=1e-13, max_sweeps=5000)
+        d = U[:, :2] - w
+        return torch.sqrt((d * d).sum(dim=1)).mean()
+
+    I0 = dev(p.I0[None]).requires_grad_()
+    I1 = dev(p.I1[None]).requires_grad_()
+    A = dev(al[None]).requires_grad_()
+    loss(I0, I1, A).backward()
+    rng = np.random.default_rng(21)
+    h = 1e-6
+    worst = 0.0
+    with torch.no_grad():
+        for k, (x, g) in enumerate(((I0, I0.grad), (I1, I1.grad), (A, A.grad))):
+            for _ in range(64):
+                v = dev(rng.normal(size=tuple(x.shape)))
+                if k == 2:
+                    v = v * A
+                ap = [I0.detach(), I1.detach(), A.detach()]
+                am = list(ap)
+                ap[k] = ap[k] + h * v
+                am[k] = am[k] - h * v
+                fd = (float(loss(*ap)) - float(loss(*am))) / (2 * h)
+                an = float((g * v).sum())
+                worst = max(worst, abs(fd - an) / max(abs(fd), 1e-2))
+    assert worst <= 1e-5, worst
+    ctx.close()
+
+
+def test_fp32_tile_adjoint_agrees_with_fp64(gpu):
+    # the FP32-tile form refines against FP64 residuals, so at the same
+    # relative residual its gradients agree with the plain form's
+    W, H = 96, 80
+    p = synth.make_pair("plain640", 4, W=W, H=H)
+    al = synth.random_alpha(W, H, 8)
+    w = dev(np.random.default_rng(2).normal(scale=0.5, size=(1, 2, H, W)))
+    grads = []
+    for prec in (api.SF_FP64, api.SF_FP32):
+        ctx = api.sf_create(W, H, 1, 3, 2, 6, factor_precision=prec)
+        I0 = dev(p.I0[None]).requires_grad_()
+        I1 = dev(p.I1[None]).requires_grad_()
+        A = dev(al[None]).requires_grad_()
+        U = api.schwarz_solve(ctx, I0, I1, A, rtol=1e-12, max_sweeps=5000)
+        d = U[:, :2] - w
+        torch.sqrt((d * d).sum(dim=1)).mean().backward()
+        grads.append([host(t.grad) for t in (I0, I1, A)])
+        ctx.close()
+    for g64, g32 in zip(*grads):
+        assert rel(g32, g64) <= 1e-7
 
 
 def test_zero_loss_gradient_and_invalid_uses(gpu):
