@@ -238,11 +238,12 @@ int sf_create(const sf_config* cfg, void* stream, sf_context** out) {
         occ2 = 0;
     const int Pf = (maxnt + 1) / 2;
     c->groups = 1;
-    if (maxnt <= 12 && occ2 >= 1 && 8 * Pf <= ncu * occ2) {
+    // (Pf ranks and one pivot server per chain)
+    if (maxnt <= 12 && occ2 >= 1 && 8 * (Pf + 1) <= ncu * occ2) {
         c->factor_pf = Pf;
-        if (16 * Pf <= ncu * occ2 && 16 * nsx <= capacity) c->groups = 2;
+        if (16 * (Pf + 1) <= ncu * occ2 && 16 * nsx <= capacity) c->groups = 2;
         // subdomains per launch: a multiple of 8 whose slots fit co-resident
-        c->factor_chunk = 8 * ((ncu * occ2) / (8 * c->groups * Pf));
+        c->factor_chunk = 8 * ((ncu * occ2) / (8 * c->groups * (Pf + 1)));
     } else {
         c->factor_pf = 0;
         c->factor_chunk = 0;
@@ -309,7 +310,7 @@ int sf_create(const sf_config* cfg, void* stream, sf_context** out) {
     rc |= dalloc(&c->relres_d, c->B);
     rc |= dalloc(&c->sweeps_d, c->B);
     rc |= dalloc(&c->done_d, c->B);
-    rc |= dalloc(&c->counters, 2 * (size_t)c->nsub);
+    rc |= dalloc(&c->counters, 2 * sfdd::F2_COUNTERS * (size_t)c->nsub);
     rc |= dalloc(&c->etamax_bits, c->B);
     rc |= dalloc(&c->flags_d, 4);
     rc |= dalloc(&c->factors, (size_t)c->factor_doubles);
@@ -397,8 +398,9 @@ int sf_factor_subdomains(sf_context* c) {
         SF_HIP(hipGetLastError());
         for (int s0 = 0; s0 < c->nsub; s0 += c->factor_chunk) {
             const int n = std::min(c->factor_chunk, c->nsub - s0);
-            hipLaunchKernelGGL(k_fill_i32, dim3((2 * c->nsub + 255) / 256), dim3(256), 0, c->stream,
-                               (int32_t*)c->counters, 2 * c->nsub, 0);
+            const int ncnt = 2 * sfdd::F2_COUNTERS * c->nsub;
+            hipLaunchKernelGGL(k_fill_i32, dim3((ncnt + 255) / 256), dim3(256), 0, c->stream,
+                               (int32_t*)c->counters, ncnt, 0);
             SF_HIP(hipGetLastError());
             SF_TRY(sfdd::launch_factor2(c, s0, n, c->factor_pf));
         }

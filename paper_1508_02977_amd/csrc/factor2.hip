@@ -14,7 +14,10 @@
 //
 // Work split: rank r owns block rows r and NT-1-r (balanced: NT+1 lower tiles
 // per rank) and keeps its tiles in MFMA accumulators (v_mfma_f64_16x16x4f64,
-// one 16x16 block per accumulator) for the whole line.  Lane layout of that
+// one 16x16 block per accumulator) for the whole line.  One more workgroup
+// per chain, the pivot server, forms every Pi: the owner of block row k+1
+// updates its diagonal tile first in pivot step k and hands it over, so Pi_{k+1}
+// is ready by the time the ranks finish the rest of step k.  Lane layout of that
 // instruction (checked on gfx950): A[i][k] in lane i + 16k, B[k][j] in lane
 // j + 16k, accumulator element q of lane l is D[l/16 + 4q][l%16].  Each pivot step needs
 // block column k of the current matrix: its owners publish it to a global
@@ -198,6 +201,131 @@ __device__ __forceinline__ void f2_publish(const d4 (&acc)[F2_MAXBLK], double* x
     }
 }
 
+// Pi = S_kk^{-1} of the symmetric 32x32 tile Sk (LDS, pitch LDP) into piv, by
+// one wave, with 2x2 blocks of 16.  With S_kk = [[A, B^T], [B, C]]
+// (symmetrised on load): A^-1 and C'^-1, C' = C - B A^-1 B^T, by the symmetric
+// sweep (16 steps each, every lane holding 4 entries in the MFMA accumulator
+// layout); then with X = B A^-1 on FP64 MFMA:
+// Pi = [[A^-1 + X^T C'^-1 X, -(C'^-1 X)^T], [-C'^-1 X, C'^-1]].
+// The pivots met are those of the unblocked sweep; each is checked against
+// the diagonal entry of A_tt it came from (adiag_k, LDS).
+// Publish the own diagonal tile (col, col) into the pivot-block slot db.
+__device__ __forceinline__ void f2_publish_diag(const d4 (&acc)[F2_MAXBLK], double* db, int col, int nblk, int rowA,
+                                                int rowB, int wv, int cr, int cc) {
+#pragma unroll
+    for (int b = 0; b < F2_MAXBLK; ++b) {
+        const int blk = wv + F2_NW * b;
+        if (blk >= nblk) continue;
+        int I, J;
+        f2_tile_of(blk >> 2, rowA, rowB, I, J);
+        const int qi = (blk >> 1) & 1, qj = blk & 1;
+        if (I == col && J == col) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) xstore(db + (16 * qi + cr + 4 * q) * TS + 16 * qj + cc, acc[b][q]);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+__device__ void f2_pivot_inverse(const double* Sk, double* piv, double* xr, const double* adiag_k, int lane,
+                                 DevStatus* status, int sub, int64_t row0) {
+    constexpr int PB = 17;                        // pitch of the 16x16 scratch blocks
+    double* bA = xr;                              // A^-1
+    double* bB = bA + 16 * PB;                    // B, then -C'^-1 X
+    double* bX = bB + 16 * PB;                    // X = B A^-1
+    double* bC = bX + 16 * PB;                    // C'^-1
+    double* prow = bC + 16 * PB;                  // pivot row
+    const int ci = lane & 15, ri = lane >> 4;     // element q of a lane: row ri + 4q, column ci
+    d4 Av, Bv, Cv;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int i = ri + 4 * q, j = ci;
+        Av[q] = 0.5 * (Sk[i * LDP + j] + Sk[j * LDP + i]);
+        Bv[q] = 0.5 * (Sk[(16 + i) * LDP + j] + Sk[j * LDP + 16 + i]);
+        Cv[q] = 0.5 * (Sk[(16 + i) * LDP + 16 + j] + Sk[(16 + j) * LDP + 16 + i]);
+    }
+    // v (symmetric 16x16) <- -v^{-1}
+    auto sweep16 = [&](d4& v, int poff) {
+#pragma unroll
+        for (int p = 0; p < 16; ++p) {
+            if (ri == (p & 3)) prow[ci] = v[p >> 2];             // row p = column p
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            const double pp = prow[p];
+            const double rowp = prow[ci];
+            double colp[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) colp[q] = prow[ri + 4 * q];
+            if (lane == 0 && !(pp > 1e-13 * adiag_k[poff + p] && isfinite(pp))) {
+                if (atomicCAS(&status->code, 0, SF_NOT_SPD) == 0) {
+                    status->sub = sub;
+                    status->row = row0 + poff + p;
+                }
+            }
+            const double ip = 1.0 / pp;
+            const bool jp = ci == p;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const bool iq = ri + 4 * q == p;
+                const double upd = v[q] - colp[q] * rowp * ip;
+                const double side = jp ? colp[q] * ip : upd;
+                v[q] = iq ? (jp ? -ip : rowp * ip) : side;
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+    };
+    auto put = [&](double* buf, const d4& v, double sgn) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) buf[(ri + 4 * q) * PB + ci] = sgn * v[q];
+    };
+    // D = op(P) op(Q) on MFMA; operand rows from 16x16 scratch blocks
+    auto mm = [&](const double* P, bool Pt, const double* Q, bool Qt) -> d4 {
+        const int ii = lane & 15, kk = lane >> 4;
+        d4 d = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+            const int kx = 4 * ks + kk;
+            const double a = Pt ? P[kx * PB + ii] : P[ii * PB + kx];
+            const double b = Qt ? Q[ii * PB + kx] : Q[kx * PB + ii];
+            d = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, d, 0, 0, 0);
+        }
+        return d;
+    };
+    auto sync_lds = [&]() {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    };
+    sweep16(Av, 0);                               // Av = -A^-1
+    put(bA, Av, -1.0);
+    put(bB, Bv, 1.0);
+    sync_lds();
+    const d4 Xv = mm(bB, false, bA, false);       // X = B A^-1
+    put(bX, Xv, 1.0);
+    sync_lds();
+    const d4 T = mm(bX, false, bB, true);         // X B^T
+    d4 Cp;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) Cp[q] = Cv[q] - T[q];
+    sweep16(Cp, 16);                              // Cp = -C'^-1
+    put(bC, Cp, -1.0);
+    sync_lds();
+    d4 P21 = mm(bC, false, bX, false);            // C'^-1 X
+#pragma unroll
+    for (int q = 0; q < 4; ++q) P21[q] = -P21[q];
+    put(bB, P21, 1.0);
+    sync_lds();
+    const d4 T3 = mm(bX, true, bB, false);        // X^T (-C'^-1 X)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int i = ri + 4 * q, j = ci;
+        piv[i * LDP + j] = -Av[q] - T3[q];                  // A^-1 + X^T C'^-1 X
+        piv[(16 + i) * LDP + j] = P21[q];                   // -C'^-1 X
+        piv[j * LDP + 16 + i] = P21[q];                     // its transpose
+        piv[(16 + i) * LDP + 16 + j] = -Cp[q];              // C'^-1
+    }
+}
+
 __global__ void __launch_bounds__(F2_THREADS) k_factor2(FactorArgs A) {
     // LDS: exchange column (NT tiles), pivot inverse, scaled rows X_I (2 tiles)
     __shared__ double colk[F2_MAXNT * LTILE];
@@ -209,15 +337,17 @@ __global__ void __launch_bounds__(F2_THREADS) k_factor2(FactorArgs A) {
 
     // workgroup g runs on XCD g % 8: the ranks of subdomain i are the slots
     // with g % 8 == i % 8, so its exchange stays inside one L2
-    const int slot = blockIdx.x / 8, per = A.groups * A.pf;
+    // per chain: ranks 0..pf-1 and the pivot server (rank pf)
+    const int ps = A.pf + 1, slot = blockIdx.x / 8, per = A.groups * ps;
     const int sub = A.sub0 + (int)(blockIdx.x % 8) + 8 * (slot / per);
-    const int chain = (slot % per) / A.pf, rank = slot % A.pf;
+    const int chain = (slot % per) / ps, rank = slot % ps;
+    const bool server = rank == A.pf;
     if (sub >= A.nsub) return;                           // idle slot
     const SubDesc d = A.subs[sub];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int m = d.m, mp = d.mp, NT = d.NT, ms = d.ms;
     const int Pf = (NT + 1) / 2;
-    if (rank >= Pf) return;                              // surplus slot of a short subdomain
+    if (!server && rank >= Pf) return;                   // surplus slot of a short subdomain
     double* Tout = A.factors + d.foff;
     double* Bst = A.factors + d.boff;
     // per chain: the full symmetric inverse of its latest line (mp x mp),
@@ -228,8 +358,39 @@ __global__ void __launch_bounds__(F2_THREADS) k_factor2(FactorArgs A) {
     double* Sdn = Sup + cstride;                        // bottom chain: S_{t+1}^{-1}
     double* Sown = chain == 0 ? Sup : Sdn;
     double* xch = Sown + (int64_t)mp * mp;
-    double* bscr = xch + 2ll * NT * TSZ + (int64_t)(rank * F2_NW + wv) * F2_MAXBLK * 256;
-    uint32_t* cnt = A.counters + 2 * sub + chain;
+    double* dslot = xch + 2ll * NT * TSZ;               // [2] pivot blocks S_kk, by pivot parity
+    double* pslot = dslot + 2 * TSZ;                    // [2] Pi_k, by pivot parity
+    double* bscr = pslot + 2 * TSZ + (int64_t)(rank * F2_NW + wv) * F2_MAXBLK * 256;
+    uint32_t* cnt = A.counters + F2_COUNTERS * (2 * sub + chain);   // column parts published
+    uint32_t* dcnt = cnt + 1;                                        // pivot blocks handed over
+    uint32_t* pcnt = cnt + 2;                                        // pivot inverses published
+
+    const int nt = d.nt, km = d.kmid;
+    const int nl1 = nt - 1 - km;                       // lines of the bottom chain
+    const int nlines = chain == 0 ? km + 1 : nl1;
+    if (server) {
+        // pivot server: for every pivot of every line of the chain, wait for
+        // the pivot block S_kk, form Pi_k (wave 0) and publish it
+        uint32_t npiv = 0;
+        for (int li = 0; li < nlines; ++li) {
+            const int t = chain == 0 ? li : nt - 1 - li;
+            const double* Ag = A.factors + d.aoff + (int64_t)t * ms * 18;
+            for (int a = tid; a < mp; a += F2_THREADS) adiag[a] = a < m ? Ag[18 * (a / 3) + 4 * (a % 3)] : 1.0;
+            for (int k = 0; k < NT; ++k) {
+                ++npiv;
+                if (!f2_wait(dcnt, npiv, A, sub, &sh_ok)) return;
+                const double* db = dslot + (npiv & 1) * TSZ;
+                for (int i = tid; i < TSZ; i += F2_THREADS) colk[(i / TS) * LDP + i % TS] = xload(db + i);
+                __syncthreads();
+                if (wv == 0) f2_pivot_inverse(colk, piv, xr, adiag + k * TS, lane, A.status, sub, (int64_t)t * m + k * TS);
+                __syncthreads();
+                double* pb = pslot + (npiv & 1) * TSZ;
+                for (int i = tid; i < TSZ; i += F2_THREADS) xstore(pb + i, piv[(i / TS) * LDP + i % TS]);
+                f2_signal(pcnt);
+            }
+        }
+        return;
+    }
 
     // own block rows and tiles; tile list: row r first, then row NT-1-r
     const int rowA = rank, rowB = NT - 1 - rank;
@@ -249,10 +410,7 @@ __global__ void __launch_bounds__(F2_THREADS) k_factor2(FactorArgs A) {
     // chain k = nt - 1).  Top line t: S_t = A_tt - B_t S_{t-1}^{-1} B_t^T.
     // Bottom line t: S_t = A_tt - B_{t+1}^T S_{t+1}^{-1} B_{t+1}.  Middle: both
     // terms, after the bottom chain has finished.
-    const int nt = d.nt, km = d.kmid;
-    const int nl1 = nt - 1 - km;                       // lines of the bottom chain
-    const int nlines = chain == 0 ? km + 1 : nl1;
-    uint32_t phase = 0;
+    uint32_t phase = 0, npiv = 0;
     for (int li = 0; li < nlines; ++li) {
         const int t = chain == 0 ? li : nt - 1 - li;
         const bool mid = chain == 0 && li == km;
@@ -304,7 +462,8 @@ __global__ void __launch_bounds__(F2_THREADS) k_factor2(FactorArgs A) {
         // symmetric inverse left by the neighbouring line in its own LDS
         // scratch, forms Z = S^{-1}[W(R), .] C_C^T, then subtracts C_R Z.
         if (li > 0 && !f2_wait(cnt, Pf * phase, A, sub, &sh_ok)) return;
-        if (mid && nl1 > 0 && !f2_wait(A.counters + 2 * sub + 1, (uint32_t)(Pf * (NT + 1) * nl1), A, sub, &sh_ok))
+        if (mid && nl1 > 0 &&
+            !f2_wait(A.counters + F2_COUNTERS * (2 * sub + 1), (uint32_t)(Pf * (NT + 1) * nl1), A, sub, &sh_ok))
             return;
         {
             constexpr int WN = 21;
@@ -440,6 +599,10 @@ __global__ void __launch_bounds__(F2_THREADS) k_factor2(FactorArgs A) {
         }
         __syncthreads();   // LDS (Aself/Anext/Bl) is reused for the exchange column below
 
+        if (rowA == 0) {                                  // hand the first pivot block to the server
+            f2_publish_diag(acc, dslot + ((npiv + 1) & 1) * TSZ, 0, nblk, rowA, rowB, wv, cr, cc);
+            f2_signal(dcnt);
+        }
         f2_publish(acc, xch + (int64_t)(phase & 1) * NT * TSZ, 0, nblk, rowA, rowB, wv, cr, cc);
         f2_signal(cnt);
         ++phase;
@@ -452,9 +615,15 @@ __global__ void __launch_bounds__(F2_THREADS) k_factor2(FactorArgs A) {
             fk = (tido >> 4) & 3;
             cr = fk;
             cc = fr;
+            ++npiv;
             if (!f2_wait(cnt, Pf * phase, A, sub, &sh_ok)) return;
+            if (!f2_wait(pcnt, npiv, A, sub, &sh_ok)) return;
             const double* xb = xch + (int64_t)((phase - 1) & 1) * NT * TSZ;
-            // the column in two batches of loads (register budget)
+            const double* pb = pslot + (npiv & 1) * TSZ;
+            // Pi_k (issued first) and the column in two batches of loads (register budget)
+            double pvl[TSZ / F2_THREADS];
+#pragma unroll
+            for (int u = 0; u < TSZ / F2_THREADS; ++u) pvl[u] = xload(pb + tido + F2_THREADS * u);
 #pragma unroll
             for (int half = 0; half < 2; ++half) {
                 constexpr int NL = F2_MAXNT * TSZ / F2_THREADS / 2;
@@ -471,113 +640,10 @@ __global__ void __launch_bounds__(F2_THREADS) k_factor2(FactorArgs A) {
                     if (i < NT * TSZ) colk[J * LTILE + r * LDP + c] = tmp[u];
                 }
             }
-            __syncthreads();
-            // Pi = S_kk^{-1} by 2x2 blocks of 16 in wave 0 (the other waves wait
-            // at the barrier).  With S_kk = [[A, B^T], [B, C]] (symmetrised on
-            // load): A^-1 and C'^-1, C' = C - B A^-1 B^T, by the symmetric
-            // sweep (16 steps each, every lane holding 4 entries in the MFMA
-            // accumulator layout); then with X = B A^-1 on FP64 MFMA:
-            // Pi = [[A^-1 + X^T C'^-1 X, -(C'^-1 X)^T], [-C'^-1 X, C'^-1]].
-            // The pivots met are those of the unblocked sweep, so the SPD
-            // test is unchanged.
-            __builtin_amdgcn_sched_barrier(0);
-            if (wv == 0) {
-                constexpr int PB = 17;                        // pitch of the 16x16 scratch blocks
-                double* bA = xr;                              // A^-1
-                double* bB = bA + 16 * PB;                    // B, then -C'^-1 X
-                double* bX = bB + 16 * PB;                    // X = B A^-1
-                double* bC = bX + 16 * PB;                    // C'^-1
-                double* prow = bC + 16 * PB;                  // pivot row
-                const int ci = lane & 15, ri = lane >> 4;     // element q of a lane: row ri + 4q, column ci
-                const double* Sk = colk + k * LTILE;
-                d4 Av, Bv, Cv;
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int i = ri + 4 * q, j = ci;
-                    Av[q] = 0.5 * (Sk[i * LDP + j] + Sk[j * LDP + i]);
-                    Bv[q] = 0.5 * (Sk[(16 + i) * LDP + j] + Sk[j * LDP + 16 + i]);
-                    Cv[q] = 0.5 * (Sk[(16 + i) * LDP + 16 + j] + Sk[(16 + j) * LDP + 16 + i]);
-                }
-                // v (symmetric 16x16) <- -v^{-1}; pivots checked against A_tt's diagonal
-                auto sweep16 = [&](d4& v, int poff) {
-#pragma unroll
-                    for (int p = 0; p < 16; ++p) {
-                        if (ri == (p & 3)) prow[ci] = v[p >> 2];             // row p = column p
-                        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                        const double pp = prow[p];
-                        const double rowp = prow[ci];
-                        double colp[4];
-#pragma unroll
-                        for (int q = 0; q < 4; ++q) colp[q] = prow[ri + 4 * q];
-                        if (lane == 0 && !(pp > 1e-13 * adiag[k * TS + poff + p] && isfinite(pp))) {
-                            if (atomicCAS(&A.status->code, 0, SF_NOT_SPD) == 0) {
-                                A.status->sub = sub;
-                                A.status->row = (int64_t)t * m + k * TS + poff + p;
-                            }
-                        }
-                        const double ip = 1.0 / pp;
-                        const bool jp = ci == p;
-#pragma unroll
-                        for (int q = 0; q < 4; ++q) {
-                            const bool iq = ri + 4 * q == p;
-                            const double upd = v[q] - colp[q] * rowp * ip;
-                            const double side = jp ? colp[q] * ip : upd;
-                            v[q] = iq ? (jp ? -ip : rowp * ip) : side;
-                        }
-                        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                    }
-                };
-                auto put = [&](double* buf, const d4& v, double sgn) {
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) buf[(ri + 4 * q) * PB + ci] = sgn * v[q];
-                };
-                // D = op(P) op(Q) on MFMA; operand rows from 16x16 scratch blocks
-                auto mm = [&](const double* P, bool Pt, const double* Q, bool Qt) -> d4 {
-                    const int ii = lane & 15, kk = lane >> 4;
-                    d4 d = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-                    for (int ks = 0; ks < 4; ++ks) {
-                        const int kx = 4 * ks + kk;
-                        const double a = Pt ? P[kx * PB + ii] : P[ii * PB + kx];
-                        const double b = Qt ? Q[ii * PB + kx] : Q[kx * PB + ii];
-                        d = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, d, 0, 0, 0);
-                    }
-                    return d;
-                };
-                auto sync_lds = [&]() {
-                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                };
-                sweep16(Av, 0);                               // Av = -A^-1
-                put(bA, Av, -1.0);
-                put(bB, Bv, 1.0);
-                sync_lds();
-                const d4 Xv = mm(bB, false, bA, false);       // X = B A^-1
-                put(bX, Xv, 1.0);
-                sync_lds();
-                const d4 T = mm(bX, false, bB, true);         // X B^T
-                d4 Cp;
-#pragma unroll
-                for (int q = 0; q < 4; ++q) Cp[q] = Cv[q] - T[q];
-                sweep16(Cp, 16);                              // Cp = -C'^-1
-                put(bC, Cp, -1.0);
-                sync_lds();
-                d4 P21 = mm(bC, false, bX, false);            // C'^-1 X
-#pragma unroll
-                for (int q = 0; q < 4; ++q) P21[q] = -P21[q];
-                put(bB, P21, 1.0);
-                sync_lds();
-                const d4 T3 = mm(bX, true, bB, false);        // X^T (-C'^-1 X)
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int i = ri + 4 * q, j = ci;
-                    piv[i * LDP + j] = -Av[q] - T3[q];                  // A^-1 + X^T C'^-1 X
-                    piv[(16 + i) * LDP + j] = P21[q];                   // -C'^-1 X
-                    piv[j * LDP + 16 + i] = P21[q];                     // its transpose
-                    piv[(16 + i) * LDP + 16 + j] = -Cp[q];              // C'^-1
-                }
+            for (int u = 0; u < TSZ / F2_THREADS; ++u) {
+                const int i = tido + F2_THREADS * u;
+                piv[(i / TS) * LDP + i % TS] = pvl[u];
             }
             __builtin_amdgcn_sched_barrier(0);
             __syncthreads();
@@ -600,19 +666,24 @@ __global__ void __launch_bounds__(F2_THREADS) k_factor2(FactorArgs A) {
                 }
             }
             __syncthreads();
-            // update own blocks.  When another pivot step follows, the blocks of
-            // column k+1 go first; that column is published and signalled, and
-            // the other ranks' wait and column load overlap the remaining updates.
+            // update own blocks.  When another pivot step follows, the next
+            // pivot block goes first (its owner hands it to the pivot server),
+            // then the rest of column k+1, which is published and signalled, so
+            // that the server and the other ranks' waits overlap the remaining
+            // updates.
             const int kn = k + 1;
+            const bool own_next = kn < NT && (rowA == kn || rowB == kn);
 #pragma unroll
-            for (int pass = 0; pass < 2; ++pass) {
+            for (int pass = 0; pass < 3; ++pass) {
+            if (pass == 0 && !own_next) continue;
 #pragma unroll
             for (int b = 0; b < F2_MAXBLK; ++b) {
                 const int blk = wv + F2_NW * b;
                 if (blk >= nblk) continue;
                 int I, J;
                 f2_tile_of(blk >> 2, rowA, rowB, I, J);
-                if (kn < NT ? ((pass == 0) != (I == kn || J == kn)) : pass == 1) continue;
+                const int bp = kn >= NT ? 2 : (I == kn && J == kn ? 0 : (I == kn || J == kn ? 1 : 2));
+                if (bp != pass) continue;
                 const int qi = (blk >> 1) & 1, qj = blk & 1;
                 const int rr = (I == rowA) ? 0 : 1;
                 if (I != k && J != k) {
@@ -644,7 +715,11 @@ __global__ void __launch_bounds__(F2_THREADS) k_factor2(FactorArgs A) {
                 // blocks at once (register budget)
                 __builtin_amdgcn_sched_barrier(0);
             }
-            if (pass == 0 && kn < NT) {
+            if (pass == 0) {
+                f2_publish_diag(acc, dslot + ((npiv + 1) & 1) * TSZ, kn, nblk, rowA, rowB, wv, cr, cc);
+                f2_signal(dcnt);
+            }
+            if (pass == 1 && kn < NT) {
                 f2_publish(acc, xch + (int64_t)(phase & 1) * NT * TSZ, kn, nblk, rowA, rowB, wv, cr, cc);
                 f2_signal(cnt);
             }
@@ -722,7 +797,7 @@ int launch_factor2(sf_context* c, int sub0, int nsub_chunk, int Pf) {
     a.lam = c->cfg.lambda;
     a.spin_limit = 1ll << 20;
     void* args[] = {&a};
-    if (hipLaunchCooperativeKernel((const void*)k_factor2, dim3(8 * ((nsub_chunk + 7) / 8) * c->groups * Pf), dim3(F2_THREADS), args, 0,
+    if (hipLaunchCooperativeKernel((const void*)k_factor2, dim3(8 * ((nsub_chunk + 7) / 8) * c->groups * (Pf + 1)), dim3(F2_THREADS), args, 0,
                                    c->stream) != hipSuccess)
         return SF_ERR_HIP;
     return SF_OK;
