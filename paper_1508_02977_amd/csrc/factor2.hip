@@ -617,13 +617,10 @@ __global__ void __launch_bounds__(F2_THREADS) k_factor2(FactorArgs A) {
             cc = fr;
             ++npiv;
             if (!f2_wait(cnt, Pf * phase, A, sub, &sh_ok)) return;
-            if (!f2_wait(pcnt, npiv, A, sub, &sh_ok)) return;
             const double* xb = xch + (int64_t)((phase - 1) & 1) * NT * TSZ;
             const double* pb = pslot + (npiv & 1) * TSZ;
-            // Pi_k (issued first) and the column in two batches of loads (register budget)
-            double pvl[TSZ / F2_THREADS];
-#pragma unroll
-            for (int u = 0; u < TSZ / F2_THREADS; ++u) pvl[u] = xload(pb + tido + F2_THREADS * u);
+            // the column in two batches of loads (register budget), while the
+            // pivot server is still forming Pi_k
 #pragma unroll
             for (int half = 0; half < 2; ++half) {
                 constexpr int NL = F2_MAXNT * TSZ / F2_THREADS / 2;
@@ -640,10 +637,11 @@ __global__ void __launch_bounds__(F2_THREADS) k_factor2(FactorArgs A) {
                     if (i < NT * TSZ) colk[J * LTILE + r * LDP + c] = tmp[u];
                 }
             }
+            if (!f2_wait(pcnt, npiv, A, sub, &sh_ok)) return;
 #pragma unroll
             for (int u = 0; u < TSZ / F2_THREADS; ++u) {
                 const int i = tido + F2_THREADS * u;
-                piv[(i / TS) * LDP + i % TS] = pvl[u];
+                piv[(i / TS) * LDP + i % TS] = xload(pb + i);
             }
             __builtin_amdgcn_sched_barrier(0);
             __syncthreads();
