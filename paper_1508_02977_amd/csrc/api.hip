@@ -346,6 +346,7 @@ int sf_create(const sf_config* cfg, void* stream, sf_context** out) {
         return SF_ERR_HIP;
     }
     c->sweep_epoch = 1;
+    c->factor_epoch = 1;
     if (!bw.empty() &&
         hipMemcpy(c->blur_w, bw.data(), bw.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
         sf_destroy(c);

@@ -17,7 +17,9 @@
 // one 16x16 block per accumulator) for the whole line.  One more workgroup
 // per chain, the pivot server, forms every Pi: the owner of block row k+1
 // updates its diagonal tile first in pivot step k and hands it over, so Pi_{k+1}
-// is ready by the time the ranks finish the rest of step k.  Lane layout of that
+// is ready by the time the ranks finish the rest of step k.  Pivot blocks and
+// Pi travel as tagged 64-bit words (32-bit tag, half of a double), so one
+// poll both synchronises and transfers them.  Lane layout of that
 // instruction (checked on gfx950): A[i][k] in lane i + 16k, B[k][j] in lane
 // j + 16k, accumulator element q of lane l is D[l/16 + 4q][l%16].  Each pivot step needs
 // block column k of the current matrix: its owners publish it to a global
@@ -59,6 +61,7 @@ struct FactorArgs {
     int W, H;
     double lam;
     long long spin_limit;
+    uint32_t epoch;           // tag base of this launch (pivot-block and Pi words carry epoch + pivot)
 };
 
 __device__ void f2_stencil_block(const double* __restrict__ f0, const double* __restrict__ al, int W, int H,
@@ -172,6 +175,53 @@ __device__ __forceinline__ void f2_signal(uint32_t* cnt) {
     if (threadIdx.x == 0) __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// a double as two tagged 64-bit words
+__device__ __forceinline__ void f2_tstore(uint64_t* p, uint32_t tag, double v) {
+    const uint64_t bits = (uint64_t)__double_as_longlong(v), tg = (uint64_t)tag << 32;
+    __hip_atomic_store(p, tg | (bits & 0xffffffffull), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(p + 1, tg | (bits >> 32), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Poll the 32x32 tile of tagged words at src until every entry carries `tag`;
+// entry i = tix + 256 u (tix: this thread's index) goes to the LDS tile dst
+// (pitch LDP) as soon as it is seen.  False (and SF_ERR_DEVICE) when the
+// wait is abandoned; the result is uniform over the workgroup.
+__device__ bool f2_tpoll(const uint64_t* src, uint32_t tag, double* dst, const DevStatus* stc, DevStatus* st,
+                         long long spin, int sub, int tix) {
+    constexpr int NU = TSZ / 256;
+    unsigned pending = (1u << NU) - 1;
+    long long n = 0;
+    int ok = 1;
+    while (pending) {
+        uint64_t lo[NU], hi[NU];
+#pragma unroll
+        for (int u = 0; u < NU; ++u)
+            if (pending & (1u << u)) {
+                const uint64_t* w = src + 2 * (tix + 256 * u);
+                lo[u] = __hip_atomic_load(const_cast<uint64_t*>(w), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                hi[u] = __hip_atomic_load(const_cast<uint64_t*>(w + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+#pragma unroll
+        for (int u = 0; u < NU; ++u)
+            if ((pending & (1u << u)) && (uint32_t)(lo[u] >> 32) == tag && (uint32_t)(hi[u] >> 32) == tag) {
+                const int i = tix + 256 * u;
+                dst[(i / TS) * LDP + i % TS] = __longlong_as_double((long long)((hi[u] << 32) | (lo[u] & 0xffffffffull)));
+                pending &= ~(1u << u);
+            }
+        if (!pending) break;
+        if (++n > spin || __hip_atomic_load(&stc->code, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == SF_ERR_DEVICE) {
+            ok = 0;
+            break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+    if (!ok && atomicCAS(&st->code, 0, SF_ERR_DEVICE) == 0) {
+        st->sub = sub;
+        st->row = (int64_t)tag;
+    }
+    return __syncthreads_and(ok) != 0;
+}
+
 __device__ __forceinline__ void f2_tile_of(int q, int rowA, int rowB, int& I, int& J) {
     if (q <= rowA) { I = rowA; J = q; }
     else           { I = rowB; J = q - rowA - 1; }
@@ -209,9 +259,9 @@ __device__ __forceinline__ void f2_publish(const d4 (&acc)[F2_MAXBLK], double* x
 // Pi = [[A^-1 + X^T C'^-1 X, -(C'^-1 X)^T], [-C'^-1 X, C'^-1]].
 // The pivots met are those of the unblocked sweep; each is checked against
 // the diagonal entry of A_tt it came from (adiag_k, LDS).
-// Publish the own diagonal tile (col, col) into the pivot-block slot db.
-__device__ __forceinline__ void f2_publish_diag(const d4 (&acc)[F2_MAXBLK], double* db, int col, int nblk, int rowA,
-                                                int rowB, int wv, int cr, int cc) {
+// Publish the own diagonal tile (col, col) as tagged words into the pivot-block slot db.
+__device__ __forceinline__ void f2_publish_diag(const d4 (&acc)[F2_MAXBLK], uint64_t* db, uint32_t tag, int col,
+                                                int nblk, int rowA, int rowB, int wv, int cr, int cc) {
 #pragma unroll
     for (int b = 0; b < F2_MAXBLK; ++b) {
         const int blk = wv + F2_NW * b;
@@ -221,7 +271,7 @@ __device__ __forceinline__ void f2_publish_diag(const d4 (&acc)[F2_MAXBLK], doub
         const int qi = (blk >> 1) & 1, qj = blk & 1;
         if (I == col && J == col) {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) xstore(db + (16 * qi + cr + 4 * q) * TS + 16 * qj + cc, acc[b][q]);
+            for (int q = 0; q < 4; ++q) f2_tstore(db + 2 * ((16 * qi + cr + 4 * q) * TS + 16 * qj + cc), tag, acc[b][q]);
         }
         __builtin_amdgcn_sched_barrier(0);
     }
@@ -244,8 +294,15 @@ __device__ void f2_pivot_inverse(const double* Sk, double* piv, double* xr, cons
         Bv[q] = 0.5 * (Sk[(16 + i) * LDP + j] + Sk[j * LDP + 16 + i]);
         Cv[q] = 0.5 * (Sk[(16 + i) * LDP + 16 + j] + Sk[(16 + j) * LDP + 16 + i]);
     }
-    // v (symmetric 16x16) <- -v^{-1}
+    // v (symmetric 16x16) <- -v^{-1}.  The pivot test is recorded per step and
+    // reported once after the sweep (first failing pivot), and 1/pp is the
+    // hardware reciprocal refined by two Newton steps r <- r + r (1 - pp r),
+    // which keeps every step of this latency-bound chain short.
     auto sweep16 = [&](d4& v, int poff) {
+        double adg[16];
+#pragma unroll
+        for (int p = 0; p < 16; ++p) adg[p] = adiag_k[poff + p];
+        int bad = -1;
 #pragma unroll
         for (int p = 0; p < 16; ++p) {
             if (ri == (p & 3)) prow[ci] = v[p >> 2];             // row p = column p
@@ -256,13 +313,11 @@ __device__ void f2_pivot_inverse(const double* Sk, double* piv, double* xr, cons
             double colp[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) colp[q] = prow[ri + 4 * q];
-            if (lane == 0 && !(pp > 1e-13 * adiag_k[poff + p] && isfinite(pp))) {
-                if (atomicCAS(&status->code, 0, SF_NOT_SPD) == 0) {
-                    status->sub = sub;
-                    status->row = row0 + poff + p;
-                }
-            }
-            const double ip = 1.0 / pp;
+            const bool okp = pp > 1e-13 * adg[p] && isfinite(pp);
+            bad = (bad < 0 && !okp) ? p : bad;
+            double ip = __builtin_amdgcn_rcp(pp);
+            ip = fma(fma(-pp, ip, 1.0), ip, ip);
+            ip = fma(fma(-pp, ip, 1.0), ip, ip);
             const bool jp = ci == p;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
@@ -273,6 +328,10 @@ __device__ void f2_pivot_inverse(const double* Sk, double* piv, double* xr, cons
             }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+        if (lane == 0 && bad >= 0 && atomicCAS(&status->code, 0, SF_NOT_SPD) == 0) {
+            status->sub = sub;
+            status->row = row0 + poff + bad;
         }
     };
     auto put = [&](double* buf, const d4& v, double sgn) {
@@ -358,12 +417,10 @@ __global__ void __launch_bounds__(F2_THREADS) k_factor2(FactorArgs A) {
     double* Sdn = Sup + cstride;                        // bottom chain: S_{t+1}^{-1}
     double* Sown = chain == 0 ? Sup : Sdn;
     double* xch = Sown + (int64_t)mp * mp;
-    double* dslot = xch + 2ll * NT * TSZ;               // [2] pivot blocks S_kk, by pivot parity
-    double* pslot = dslot + 2 * TSZ;                    // [2] Pi_k, by pivot parity
-    double* bscr = pslot + 2 * TSZ + (int64_t)(rank * F2_NW + wv) * F2_MAXBLK * 256;
+    uint64_t* dslot = reinterpret_cast<uint64_t*>(xch + 2ll * NT * TSZ);   // [2][TSZ] tagged pivot blocks
+    uint64_t* pslot = dslot + 4 * TSZ;                                        // [2][TSZ] tagged Pi
+    double* bscr = reinterpret_cast<double*>(pslot + 4 * TSZ) + (int64_t)(rank * F2_NW + wv) * F2_MAXBLK * 256;
     uint32_t* cnt = A.counters + F2_COUNTERS * (2 * sub + chain);   // column parts published
-    uint32_t* dcnt = cnt + 1;                                        // pivot blocks handed over
-    uint32_t* pcnt = cnt + 2;                                        // pivot inverses published
 
     const int nt = d.nt, km = d.kmid;
     const int nl1 = nt - 1 - km;                       // lines of the bottom chain
@@ -378,15 +435,13 @@ __global__ void __launch_bounds__(F2_THREADS) k_factor2(FactorArgs A) {
             for (int a = tid; a < mp; a += F2_THREADS) adiag[a] = a < m ? Ag[18 * (a / 3) + 4 * (a % 3)] : 1.0;
             for (int k = 0; k < NT; ++k) {
                 ++npiv;
-                if (!f2_wait(dcnt, npiv, A, sub, &sh_ok)) return;
-                const double* db = dslot + (npiv & 1) * TSZ;
-                for (int i = tid; i < TSZ; i += F2_THREADS) colk[(i / TS) * LDP + i % TS] = xload(db + i);
-                __syncthreads();
+                if (!f2_tpoll(dslot + (npiv & 1) * 2 * TSZ, A.epoch + npiv, colk, A.status, A.status, A.spin_limit, sub,
+                              tid))
+                    return;
                 if (wv == 0) f2_pivot_inverse(colk, piv, xr, adiag + k * TS, lane, A.status, sub, (int64_t)t * m + k * TS);
                 __syncthreads();
-                double* pb = pslot + (npiv & 1) * TSZ;
-                for (int i = tid; i < TSZ; i += F2_THREADS) xstore(pb + i, piv[(i / TS) * LDP + i % TS]);
-                f2_signal(pcnt);
+                uint64_t* pb = pslot + (npiv & 1) * 2 * TSZ;
+                for (int i = tid; i < TSZ; i += F2_THREADS) f2_tstore(pb + 2 * i, A.epoch + npiv, piv[(i / TS) * LDP + i % TS]);
             }
         }
         return;
@@ -599,10 +654,9 @@ __global__ void __launch_bounds__(F2_THREADS) k_factor2(FactorArgs A) {
         }
         __syncthreads();   // LDS (Aself/Anext/Bl) is reused for the exchange column below
 
-        if (rowA == 0) {                                  // hand the first pivot block to the server
-            f2_publish_diag(acc, dslot + ((npiv + 1) & 1) * TSZ, 0, nblk, rowA, rowB, wv, cr, cc);
-            f2_signal(dcnt);
-        }
+        if (rowA == 0)                                    // hand the first pivot block to the server
+            f2_publish_diag(acc, dslot + ((npiv + 1) & 1) * 2 * TSZ, A.epoch + npiv + 1, 0, nblk, rowA, rowB, wv,
+                            cr, cc);
         f2_publish(acc, xch + (int64_t)(phase & 1) * NT * TSZ, 0, nblk, rowA, rowB, wv, cr, cc);
         f2_signal(cnt);
         ++phase;
@@ -618,7 +672,7 @@ __global__ void __launch_bounds__(F2_THREADS) k_factor2(FactorArgs A) {
             ++npiv;
             if (!f2_wait(cnt, Pf * phase, A, sub, &sh_ok)) return;
             const double* xb = xch + (int64_t)((phase - 1) & 1) * NT * TSZ;
-            const double* pb = pslot + (npiv & 1) * TSZ;
+            const uint64_t* pb = pslot + (npiv & 1) * 2 * TSZ;
             // the column in two batches of loads (register budget), while the
             // pivot server is still forming Pi_k
 #pragma unroll
@@ -637,12 +691,7 @@ __global__ void __launch_bounds__(F2_THREADS) k_factor2(FactorArgs A) {
                     if (i < NT * TSZ) colk[J * LTILE + r * LDP + c] = tmp[u];
                 }
             }
-            if (!f2_wait(pcnt, npiv, A, sub, &sh_ok)) return;
-#pragma unroll
-            for (int u = 0; u < TSZ / F2_THREADS; ++u) {
-                const int i = tido + F2_THREADS * u;
-                piv[(i / TS) * LDP + i % TS] = xload(pb + i);
-            }
+            if (!f2_tpoll(pb, A.epoch + npiv, piv, A.status, A.status, A.spin_limit, sub, tido)) return;
             __builtin_amdgcn_sched_barrier(0);
             __syncthreads();
             // X_I = S_Ik Pi for the own rows I != k
@@ -713,10 +762,9 @@ __global__ void __launch_bounds__(F2_THREADS) k_factor2(FactorArgs A) {
                 // blocks at once (register budget)
                 __builtin_amdgcn_sched_barrier(0);
             }
-            if (pass == 0) {
-                f2_publish_diag(acc, dslot + ((npiv + 1) & 1) * TSZ, kn, nblk, rowA, rowB, wv, cr, cc);
-                f2_signal(dcnt);
-            }
+            if (pass == 0)
+                f2_publish_diag(acc, dslot + ((npiv + 1) & 1) * 2 * TSZ, A.epoch + npiv + 1, kn, nblk, rowA, rowB, wv,
+                                cr, cc);
             if (pass == 1 && kn < NT) {
                 f2_publish(acc, xch + (int64_t)(phase & 1) * NT * TSZ, kn, nblk, rowA, rowB, wv, cr, cc);
                 f2_signal(cnt);
@@ -794,6 +842,11 @@ int launch_factor2(sf_context* c, int sub0, int nsub_chunk, int Pf) {
     a.H = c->H;
     a.lam = c->cfg.lambda;
     a.spin_limit = 1ll << 20;
+    // tags must differ from those left in the slots by earlier launches
+    a.epoch = c->factor_epoch;
+    int maxpiv = 0;
+    for (const auto& d : c->subs) maxpiv = std::max(maxpiv, d.nt * d.NT);
+    c->factor_epoch += (uint32_t)maxpiv + 4;
     void* args[] = {&a};
     if (hipLaunchCooperativeKernel((const void*)k_factor2, dim3(8 * ((nsub_chunk + 7) / 8) * c->groups * (Pf + 1)), dim3(F2_THREADS), args, 0,
                                    c->stream) != hipSuccess)

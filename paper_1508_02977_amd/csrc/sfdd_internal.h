@@ -66,6 +66,7 @@ struct sf_context {
     int factor_pf;                  // workgroups per subdomain in the cooperative factor (0: one-WG factor)
     int factor_chunk;               // subdomains per cooperative factor launch
     uint32_t sweep_epoch;           // tag base for the sweep's published rows
+    uint32_t factor_epoch;          // tag base for the factor's pivot blocks and inverses
     double* blur_w;                 // presmoothing weights, 2 blur_r + 1 (sigma > 0)
     int blur_r;
     // per-pair field data
