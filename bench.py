@@ -89,6 +89,22 @@ def sweep_bytes(plan, tile_bytes=8):
     return total
 
 
+def factor_flops(plan):
+    """Algorithmic flops of one factorisation: every line matrix S_t of order
+    m = 3 ms is inverted (m^3 for the symmetric sweep); the sparse Schur
+    updates are not counted."""
+    total = 0
+    for g in plan:
+        x0, x1, y0, y1 = g["box"]
+        bw, bh = x1 - x0, y1 - y0
+        ms, nt = (bh, bw) if g["cols"] else (bw, bh)
+        total += nt * (3 * ms) ** 3
+    return total
+
+
+RESIDUAL_BYTES_PER_NODE = 96   # f0 8, alpha 2 x 8, F 24, U 24 in; r 24 out
+
+
 def cpu_baseline(pair, alpha0, sweeps_total, solves, updates):
     """The oracle on the host: a bounded sample of the same job, extrapolated."""
     import numpy as np
@@ -227,6 +243,21 @@ def main():
                      "bytes_per_launch": bytes_per_sweep, "avg_launch_ms": avg_sweep_ms,
                      "launches": plain["sw_n"], "working_launches": plain["sweeps_timed"]},
         "phase_ms_per_step": {k: v[0] / args.steps for k, v in plain["prof"].items()},
+    }
+    # the other two hot kernels, from the same HIP-event phase timings (the
+    # residual phase also holds the small per-pair convergence kernel, the
+    # factor phase the line-coefficient kernel)
+    fl = factor_flops(plain["plan"])
+    f_ms, f_n = plain["prof"]["factor"]
+    r_ms, r_n = plain["prof"]["residual"]
+    rb = RESIDUAL_BYTES_PER_NODE * W * H
+    out["secondary"] = {
+        "k_factor2": {"bound": "mfma", "flop_per_launch": fl, "avg_launch_ms": f_ms / max(f_n, 1),
+                      "achieved": fl * f_n / (f_ms * 1e-3) / 1e12, "peak": 78.6, "unit": "TFLOP/s",
+                      "frac": fl * f_n / (f_ms * 1e-3) / 1e12 / 78.6},
+        "k_residual": {"bound": "hbm", "bytes_per_launch": rb, "avg_launch_ms": r_ms / max(r_n, 1),
+                       "achieved": rb * r_n / (r_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": rb * r_n / (r_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
     }
     if not args.plain_only:
         # the chosen form: inverse tiles stored in FP32, FP64 arithmetic and
