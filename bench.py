@@ -25,6 +25,7 @@ METRIC = "Schwarz-solved unknowns/s at 1e-8 rel. residual, plain FP64 vs chosen 
 W, H, PX, PY, OVERLAP = 640, 480, 4, 4, 8
 SEED, ALPHA0, LAM = 2, 0.1, 1.0
 RTOL, MAX_SWEEPS, PASSES = 1e-8, 2000, 3
+BATCH = 2                      # pairs of the batched form
 KAPPA, ETA_THR, ALPHA_TH = 1.0, 0.1, 1e-3
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sweep_plain640_traffic.txt")
@@ -157,6 +158,7 @@ def main():
                                    "(the sharded design is described in DESIGN.md)"}))
         sys.exit(2)
 
+    import numpy as np
     import torch
 
     from paper_1508_02977_amd import api, synth
@@ -177,18 +179,25 @@ def main():
     I1 = torch.tensor(pair.I1[None], dtype=torch.float64, device=dev)
     A0 = torch.tensor(alpha0[None], dtype=torch.float64, device=dev)
 
-    def run_form(precision):
+    def run_form(precision, batch=1):
         """Warm up, then time `steps` whole pipeline steps with the given
-        storage of the inverse Schur tiles."""
-        Al = torch.empty_like(A0)
-        ctx = api.sf_create(W, H, 1, PX, PY, OVERLAP, lam=LAM, factor_precision=precision)
+        storage of the inverse Schur tiles, on `batch` pairs at once."""
+        if batch == 1:
+            I0b, I1b, A0b = I0, I1, A0
+        else:
+            more = [pair] + [synth.make_pair("plain640", SEED + i) for i in range(1, batch)]
+            I0b = torch.tensor(np.stack([q.I0 for q in more]), dtype=torch.float64, device=dev)
+            I1b = torch.tensor(np.stack([q.I1 for q in more]), dtype=torch.float64, device=dev)
+            A0b = A0.expand(batch, -1, -1, -1).contiguous()
+        Al = torch.empty_like(A0b)
+        ctx = api.sf_create(W, H, batch, PX, PY, OVERLAP, lam=LAM, factor_precision=precision)
         U = torch.zeros(ctx.field_shape(), dtype=torch.float64, device=dev)
         plan = [api.sf_subdomain_geometry(ctx, i) for i in range(api.sf_num_subdomains(ctx))]
 
         def step():
-            Al.copy_(A0)
+            Al.copy_(A0b)
             U.zero_()
-            return api.run_pipeline(ctx, I0, I1, Al, U, rtol=RTOL, max_sweeps=MAX_SWEEPS, passes=PASSES,
+            return api.run_pipeline(ctx, I0b, I1b, Al, U, rtol=RTOL, max_sweeps=MAX_SWEEPS, passes=PASSES,
                                     kappa=KAPPA, eta_thr=ETA_THR, alpha_th=ALPHA_TH)
 
         for _ in range(args.warmup):
@@ -202,13 +211,13 @@ def main():
         t1 = time.perf_counter()
         prof = api.sf_profile(ctx, 0)
         last = results[-1]
-        if any(r[0] > RTOL for r in last.relres):
+        if any(x > RTOL for r in last.relres for x in r):
             raise SystemExit(f"bench: a solve did not reach {RTOL}: {last.relres}")
         # the solve loop tests convergence on the host every few sweeps, so a
         # solve can end with a few launches that find every pair converged and
         # exit at once: time per working launch = all sweep time / sweeps done
         sw_ms, sw_n = prof["sweep"]
-        sweeps_timed = sum(s[0] for r in results for s in r.sweeps)
+        sweeps_timed = sum(max(s) for r in results for s in r.sweeps)
         ctx.close()
         return dict(ms_step=(t1 - t0) * 1e3 / args.steps, last=last, prof=prof, plan=plan, U=U.clone(),
                     sw_ms=sw_ms, sw_n=sw_n, sweeps_timed=sweeps_timed,
@@ -277,6 +286,18 @@ def main():
             "sweep_bytes_per_launch": b32,
             "sweep_achieved_GBs": b32 / (ch["avg_sweep_ms"] * 1e-3) / 1e9,
             "phase_ms_per_step": {k: v[0] / args.steps for k, v in ch["prof"].items()},
+        }
+    if not args.plain_only:
+        # batching: two pairs (seeds 2 and 3) share every launch, plain FP64
+        bt = run_form(api.SF_FP64, batch=BATCH)
+        out["batched_form"] = {
+            "form": f"{BATCH} pairs per launch (plain640 seeds {SEED}..{SEED + BATCH - 1}), plain FP64",
+            "value": BATCH * 3 * W * H / (bt["ms_step"] * 1e-3), "unit": "unknowns/s",
+            "ms_per_step": bt["ms_step"], "speedup_vs_plain": BATCH * ms_step / bt["ms_step"],
+            "sweeps_per_solve": [list(s) for s in zip(*bt["last"].sweeps)],
+            "final_relres": [list(r) for r in zip(*bt["last"].relres)],
+            "sweep_avg_launch_ms": bt["avg_sweep_ms"],
+            "phase_ms_per_step": {k: v[0] / args.steps for k, v in bt["prof"].items()},
         }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(pair, alpha0, sum(sweeps), len(sweeps), PASSES)

@@ -115,6 +115,15 @@ int sf_factor_subdomains(sf_context* ctx);
 int sf_schwarz_solve(sf_context* ctx, double* U, double rtol, int32_t max_sweeps,
                      int32_t* sweeps, double* relres);
 
+/* Autotuning of the sweep's launch shape: with current factors, time
+ * `trials` RAS sweeps for every number of workgroups per chain that changes
+ * the block rows each one owns (clamped to what fits co-resident), keep the
+ * fastest and return it in *band_tile (HOST, may be NULL).  U [B][3][H][W]
+ * (device) is the iterate of the timing sweeps and is overwritten.  A shape
+ * only reorders the partial sums inside a row, so later solves agree with
+ * earlier ones to rounding.  SF_ERR_STATE without current factors.         */
+int sf_autotune(sf_context* ctx, double* U, int32_t trials, int32_t* band_tile);
+
 /* Gradients of a loss L(U) of the discrete solution (Section 2.2, A U = F)
  * with respect to the frames and alpha, by the adjoint method.  The adjoint
  * state P solves A P = G, G = dL/dU (A is symmetric), with the same

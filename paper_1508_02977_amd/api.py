@@ -62,6 +62,7 @@ _SIGS = {
     "sf_assemble": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "sf_factor_subdomains": (c_int32, [c_void_p]),
     "sf_schwarz_solve": (c_int32, [c_void_p, c_void_p, c_double, c_int32, c_void_p, c_void_p]),
+    "sf_autotune": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p]),
     "sf_adjoint": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_double,
                              c_int32, c_void_p, c_void_p]),
     "sf_update_alpha": (c_int32, [c_void_p, c_void_p, c_void_p, c_double, c_double, c_double, c_void_p]),
@@ -212,6 +213,15 @@ def sf_schwarz_solve(ctx: Context, U, rtol: float, max_sweeps: int):
                                   ctypes.cast(sw, c_void_p), ctypes.cast(rr, c_void_p))
     _check(code, "sf_schwarz_solve", ctx, allow=(SF_NOT_CONVERGED,))
     return code, list(sw), list(rr)
+
+
+def sf_autotune(ctx: Context, U, trials: int = 3) -> int:
+    """Time the sweep's launch shapes on the current factors and keep the
+    fastest; returns the chosen workgroups per chain.  ``U`` is overwritten."""
+    bt = c_int32()
+    _check(lib().sf_autotune(ctx.handle, _dev(U, ctx.field_shape(), "U"), int(trials), ctypes.byref(bt)),
+           "sf_autotune", ctx)
+    return bt.value
 
 
 def sf_adjoint(ctx: Context, U, G, P, dI0=None, dI1=None, dalpha=None, rtol: float = 1e-10,

@@ -186,6 +186,28 @@ void sf_destroy(sf_context* c) {
     delete c;
 }
 
+// Sweep workgroups per chain (P, clamped to the line matrices' block rows and
+// to co-residency) and the launch shape that follows; host side only.
+static void set_sweep_shape(sf_context* c, int P) {
+    int min_nt = 1 << 30, maxnt = 0;
+    for (const auto& d : c->subs) {
+        min_nt = std::min(min_nt, d.NT);
+        maxnt = std::max(maxnt, d.NT);
+    }
+    const int nsx = (c->nsub + 7) / 8, G = c->groups;
+    P = std::min(std::min(P, min_nt), 255);
+    if ((int64_t)P * 8 * nsx * G > c->sweep_capacity) P = std::max(1, c->sweep_capacity / (8 * nsx * G));
+    c->maxP = P;
+    c->sweep_grid = 8 * nsx * G * P;
+    c->sweep_rows = 0;
+    for (int r = 0; r < P; ++r) {
+        int R = 0;
+        while (2 * P * (R / 2) + ((R & 1) ? 2 * P - 1 - r : r) < maxnt) ++R;
+        c->sweep_rows = std::max(c->sweep_rows, R);
+    }
+    for (auto& d : c->subs) d.P = P;
+}
+
 int sf_create(const sf_config* cfg, void* stream, sf_context** out) {
     if (!cfg || !out) return SF_ERR_INVALID;
     *out = nullptr;
@@ -252,6 +274,7 @@ int sf_create(const sf_config* cfg, void* stream, sf_context** out) {
 
     // sweep workgroups per chain: at most one per 32-row block row of the line
     // matrices, and the fewest that give the largest per-rank share
+    c->sweep_capacity = capacity;
     int P;
     if (k.band_tile > 0) {
         P = k.band_tile;
@@ -260,22 +283,11 @@ int sf_create(const sf_config* cfg, void* stream, sf_context** out) {
         const int rows = (min_nt + P - 1) / P;
         P = (min_nt + rows - 1) / rows;
     }
-    P = std::min(P, min_nt);
-    P = std::min(P, 255);
-    if ((int64_t)P * 8 * nsx * G > capacity) P = std::max(1, capacity / (8 * nsx * G));
-    c->maxP = P;
-    c->sweep_grid = 8 * nsx * G * P;
-    c->sweep_rows = 0;
-    for (int r = 0; r < P; ++r) {
-        int R = 0;
-        while (2 * P * (R / 2) + ((R & 1) ? 2 * P - 1 - r : r) < maxnt) ++R;
-        c->sweep_rows = std::max(c->sweep_rows, R);
-    }
+    set_sweep_shape(c, P);
 
     // ---- storage offsets -----------------------------------------------------
     int64_t foff = 0, woff = 0;
     for (auto& d : c->subs) {
-        d.P = P;
         d.kmid = G == 2 ? (d.nt - 1) / 2 : d.nt - 1;
         d.foff = foff;
         // tiles in doubles, or in floats packed two per double
@@ -472,6 +484,61 @@ int sf_schwarz_solve(sf_context* c, double* U, double rtol, int32_t max_sweeps, 
     if (!c || !U || max_sweeps < 0 || !(rtol >= 0.0)) return SF_ERR_INVALID;
     if (c->state != ST_FACTORED) return SF_ERR_STATE;
     return schwarz_loop(c, U, c->F, c->Fn2, rtol, max_sweeps, sweeps, relres);
+}
+
+int sf_autotune(sf_context* c, double* U, int32_t trials, int32_t* band_tile) {
+    if (!c || !U || trials < 1) return SF_ERR_INVALID;
+    if (c->state != ST_FACTORED) return SF_ERR_STATE;
+    int min_nt = 1 << 30;
+    for (const auto& d : c->subs) min_nt = std::min(min_nt, d.NT);
+    // candidates: for every number of block rows per workgroup, the fewest
+    // workgroups per chain that give it
+    std::vector<int> cand;
+    for (int rows = 1; rows <= min_nt; ++rows) {
+        const int P = (min_nt + rows - 1) / rows;
+        if (cand.empty() || cand.back() != P) cand.push_back(P);
+    }
+    hipLaunchKernelGGL(k_zero_status_api, dim3(1), dim3(1), 0, c->stream, c->status_d);
+    SF_HIP(hipGetLastError());
+    hipEvent_t e0, e1;
+    SF_HIP(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return SF_ERR_HIP;
+    }
+    const int keep = c->maxP;
+    int best = keep, rc = SF_OK;
+    float best_ms = 0.0f;
+    std::vector<int> tried;
+    for (int P : cand) {
+        set_sweep_shape(c, P);
+        if (std::find(tried.begin(), tried.end(), c->maxP) != tried.end()) continue;   // clamped to a tried shape
+        tried.push_back(c->maxP);
+        if (hipMemcpyAsync(c->d_subs, c->subs.data(), c->subs.size() * sizeof(SubDesc), hipMemcpyHostToDevice,
+                           c->stream) != hipSuccess) { rc = SF_ERR_HIP; break; }
+        if ((rc = fill_i32(c, c->done_d, c->B, 0)) != SF_OK) break;
+        if ((rc = sfdd::launch_residual(c, U, c->r, 0, 0.0, 0, 0)) != SF_OK) break;
+        if ((rc = sfdd::launch_sweep(c, U, c->r, -1, nullptr, nullptr)) != SF_OK) break;   // warm-up
+        if (hipEventRecord(e0, c->stream) != hipSuccess) { rc = SF_ERR_HIP; break; }
+        for (int i = 0; i < trials && rc == SF_OK; ++i) rc = sfdd::launch_sweep(c, U, c->r, -1, nullptr, nullptr);
+        if (rc != SF_OK) break;
+        float ms = 0.0f;
+        if (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { rc = SF_ERR_HIP; break; }
+        const int code = pull_status(c);
+        if (code != SF_OK) { rc = code; break; }
+        if (tried.size() == 1 || ms < best_ms) {
+            best_ms = ms;
+            best = c->maxP;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    set_sweep_shape(c, rc == SF_OK ? best : keep);
+    if (hipMemcpy(c->d_subs, c->subs.data(), c->subs.size() * sizeof(SubDesc), hipMemcpyHostToDevice) != hipSuccess)
+        return SF_ERR_HIP;
+    if (band_tile) *band_tile = c->maxP;
+    return rc;
 }
 
 int sf_adjoint(sf_context* c, const double* U, const double* G, double* P, double* dI0, double* dI1, double* dalpha,

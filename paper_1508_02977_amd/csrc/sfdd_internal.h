@@ -61,6 +61,7 @@ struct sf_context {
     sfdd::SubDesc* d_subs;
     int sweep_grid;                 // 8 * ceil(nsub / 8) * groups * maxP workgroups (idle slots exit)
     int maxP;                       // sweep workgroups per chain
+    int sweep_capacity;             // co-resident sweep workgroups on the device
     int groups;                     // chains per subdomain: 2 = twisted factorisation, 1 = top to bottom
     int sweep_rows;                 // largest number of block rows a sweep workgroup owns
     int factor_pf;                  // workgroups per subdomain in the cooperative factor (0: one-WG factor)

@@ -13,10 +13,10 @@
 // tiles of block row I are the lower tiles (I, J<=I) and, transposed, the
 // tiles (J>I, I) of block column I, so each off-diagonal tile is read by two
 // ranks (the second read is served by L2: all ranks of a subdomain sit on one
-// XCD).  Ranks publish their finished rows and bump a per-subdomain counter;
-// the next line starts when all P rows sets are out.  No reductions across
-// ranks, so results do not depend on P.  All waits are bounded: a stalled
-// wait raises SF_ERR_DEVICE and every rank exits.
+// XCD).  Ranks publish their finished rows as tagged words; the next line
+// starts when all P row sets are seen.  No reductions across ranks: P changes
+// only the order of the partial sums inside a row.  All waits are bounded: a
+// stalled wait raises SF_ERR_DEVICE and every rank exits.
 #include <algorithm>
 
 #include "sfdd_internal.h"
