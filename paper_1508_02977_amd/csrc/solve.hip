@@ -233,11 +233,23 @@ __global__ void __launch_bounds__(64 * NWV) k_sweep(SweepArgs A) {
         const int x = d.cols ? d.bx0 : d.bx0 + s, y = d.cols ? d.by0 + s : d.by0;
         return ((int64_t)d.pair * 3 + c) * nn + (int64_t)y * A.W + x;
     };
-    // right-hand side of the rows a = tid + CW0 * j of this thread
+    // Rows of z that this thread forms.  Fast form: a tile wave forms exactly
+    // the rows it consumes (its column blocks wv + NWT i), so no workgroup
+    // barrier separates z from the products; general form: rows tid + CW0 j.
+    static_assert(RMAX != 2 || 64 * RPT == 16 * PF, "fast form: z rows of a wave = its column blocks");
+    auto zrow = [&](int j) -> int {
+        if constexpr (RMAX == 2) {
+            const int k = lane + 64 * j;
+            return (wv + NWT * (k >> 5)) * TS + (k & 31);
+        } else {
+            return tid + CW0 * j;
+        }
+    };
+    // right-hand side of this thread's rows
     const double* __restrict__ rsrc[RPT];
 #pragma unroll
     for (int j = 0; j < RPT; ++j) {
-        const int a = tid + CW0 * j;
+        const int a = zrow(j);
         rsrc[j] = mode == 1 ? A.b_local + a : A.r + (a < m ? gbase(a) : 0);
     }
     const int64_t rstep = mode == 1 ? m : gstep;
@@ -302,7 +314,7 @@ __global__ void __launch_bounds__(64 * NWV) k_sweep(SweepArgs A) {
         const bool hu = has_up(q, t), hd = has_dn(q, t);
 #pragma unroll
         for (int j = 0; j < RPT; ++j) {             // z terms first: needed earlier
-            const int a = tid + CW0 * j;
+            const int a = zrow(j);
             if (a < m) {
                 if (q <= L) pr[j] = rsrc[j][t * rstep];
                 if (hu) {
@@ -396,7 +408,7 @@ __global__ void __launch_bounds__(64 * NWV) k_sweep(SweepArgs A) {
         if (!ctl) {
 #pragma unroll
             for (int j = 0; j < RPT; ++j) {
-                const int a = tid + CW0 * j, zs = a / 3;
+                const int a = zrow(j), zs = a / 3;
                 if (a >= mp) break;
                 double v = 0.0;
                 if (a < m) {
@@ -426,7 +438,13 @@ __global__ void __launch_bounds__(64 * NWV) k_sweep(SweepArgs A) {
                 z[a] = v;
             }
         }
-        __syncthreads();
+        if constexpr (FAST) {
+            // each tile wave reads only its own rows of z
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        } else {
+            __syncthreads();
+        }
         if (!ctl) {
             // this rank's block rows
             if constexpr (FAST) {
