@@ -242,7 +242,7 @@ int sf_create(const sf_config* cfg, void* stream, sf_context** out) {
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, sfdd::sweep_kernel(), sfdd::sweep_threads(0), 0) !=
             hipSuccess || occ < 1)
         occ = 1;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ_b, sfdd::sweep_kernel_small(), 256, 0) ==
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ_b, sfdd::sweep_kernel_small(), sfdd::sweep_threads(1), 0) ==
             hipSuccess && occ_b >= 1)
         occ = std::min(occ, occ_b);
     const int capacity = ncu * occ;

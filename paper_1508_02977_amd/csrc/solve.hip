@@ -237,37 +237,52 @@ __global__ void __launch_bounds__(64 * NWV) k_sweep(SweepArgs A) {
     // the rows it consumes (its column blocks wv + NWT i), so no workgroup
     // barrier separates z from the products; general form: rows tid + CW0 j.
     static_assert(RMAX != 2 || 64 * RPT == 16 * PF, "fast form: z rows of a wave = its column blocks");
+    // (The thread index is passed through an empty asm statement where rows
+    // are formed inside the phase loop, so that the compiler recomputes the
+    // few integer operations of their addresses instead of keeping a set of
+    // 64-bit addresses live across the whole loop.)
+    constexpr bool OPAQUE = sizeof(TT) == 8;       // FP64 tiles leave few spare registers
     auto zrow = [&](int j) -> int {
+        int tx = tid;
+        if constexpr (OPAQUE) asm volatile("" : "+v"(tx));
         if constexpr (RMAX == 2) {
-            const int k = lane + 64 * j;
-            return (wv + NWT * (k >> 5)) * TS + (k & 31);
+            const int k = (tx & 63) + 64 * j;
+            return ((tx >> 6) + NWT * (k >> 5)) * TS + (k & 31);
         } else {
-            return tid + CW0 * j;
+            return tx + CW0 * j;
         }
     };
-    // right-hand side of this thread's rows
-    const double* __restrict__ rsrc[RPT];
-#pragma unroll
-    for (int j = 0; j < RPT; ++j) {
-        const int a = zrow(j);
-        rsrc[j] = mode == 1 ? A.b_local + a : A.r + (a < m ? gbase(a) : 0);
-    }
+    // right-hand side of row a of line t (FP32 tiles: base pointers kept per row)
     const int64_t rstep = mode == 1 ? m : gstep;
+    const double* __restrict__ rbase[OPAQUE ? 1 : RPT];
+    if constexpr (!OPAQUE) {
+#pragma unroll
+        for (int j = 0; j < RPT; ++j) {
+            const int a = zrow(j);
+            rbase[j] = mode == 1 ? A.b_local + a : A.r + (a < m ? gbase(a) : 0);
+        }
+    }
+    auto rsrc = [&](int j, int a, int t) -> const double* {
+        if constexpr (OPAQUE)
+            return mode == 1 ? A.b_local + a + (int64_t)t * rstep : A.r + gbase(a) + (int64_t)t * rstep;
+        else
+            return rbase[j] + (int64_t)t * rstep;
+    };
     // this thread's prefetched tiles (fixed for all lines): offsets inside a line
-    // Fast form (RMAX == 2, NT <= NWT PF / 2): slot p holds tile (row p % 2,
-    // column wv + NWT (p / 2)), so a wave's tiles of one row are fixed and the
-    // row partials stay in registers until one reduction per row.  General
+    // Fast form (RMAX == 2, NT <= NWT PF / 2): slot p holds tile (row p / (PF/2),
+    // column wv + NWT (p % (PF/2))), so a wave's tiles of one row are fixed and
+    // the row partials stay in registers until one reduction per row.  General
     // form: slot p holds the tile qt = wv + NWT p of the rank's row-major list.
     constexpr bool FAST = RMAX == 2;
     auto slot_ok = [&](int p) -> bool {
-        if constexpr (FAST) return (p & 1) < R && wv + NWT * (p >> 1) < NT;
+        if constexpr (FAST) return p / (PF / 2) < R && wv + NWT * (p % (PF / 2)) < NT;
         else return wv + NWT * p < ntw;
     };
     int32_t toff[PF];                              // < ntiles * TSZ elements
 #pragma unroll
     for (int p = 0; p < PF; ++p) {
         if constexpr (FAST) {
-            toff[p] = slot_ok(p) ? tile_lane_offset(own_row(p & 1, rank, P), wv + NWT * (p >> 1)) : 0;
+            toff[p] = slot_ok(p) ? tile_lane_offset(own_row(p / (PF / 2), rank, P), wv + NWT * (p % (PF / 2))) : 0;
         } else {
             const int qt = min(wv + NWT * p, ntw - 1);
             toff[p] = tile_lane_offset(own_row(qt / NT, rank, P), qt % NT);
@@ -316,7 +331,7 @@ __global__ void __launch_bounds__(64 * NWV) k_sweep(SweepArgs A) {
         for (int j = 0; j < RPT; ++j) {             // z terms first: needed earlier
             const int a = zrow(j);
             if (a < m) {
-                if (q <= L) pr[j] = rsrc[j][t * rstep];
+                if (q <= L) pr[j] = *rsrc(j, a, t);
                 if (hu) {
                     const double* cf = Bb + ((int64_t)t * m + a) * 6;
 #pragma unroll
@@ -448,40 +463,39 @@ __global__ void __launch_bounds__(64 * NWV) k_sweep(SweepArgs A) {
         if (!ctl) {
             // this rank's block rows
             if constexpr (FAST) {
-                // direct partials dp[i][k] of rows 8h+k and transposed partials
-                // tp[i][0..1] of columns 2c, 2c+1, summed over this wave's tiles
+                // per own row i: direct partials dp[k] of rows 8h+k and
+                // transposed partials tp0, tp1 of columns 2c, 2c+1, summed over
+                // this wave's tiles of the row, then one reduction per row
                 const int c = lane & 15, h = lane >> 4;
-                double dp[2][8], tp[2][2];
-#pragma unroll
-                for (int i = 0; i < 2; ++i) {
-                    tp[i][0] = tp[i][1] = 0.0;
-#pragma unroll
-                    for (int k = 0; k < 8; ++k) dp[i][k] = 0.0;
-                }
-#pragma unroll
-                for (int p = 0; p < PF; ++p) {
-                    if (!slot_ok(p)) continue;
-                    const int i = p & 1, I = own_row(i, rank, P), J = wv + NWT * (p >> 1);
-                    if (J >= I) {
-                        const double* zr = z + J * TS + 8 * h;
-#pragma unroll
-                        for (int k = 0; k < 8; ++k) {
-                            tp[i][0] = fma((double)pre[p][2 * k], zr[k], tp[i][0]);
-                            tp[i][1] = fma((double)pre[p][2 * k + 1], zr[k], tp[i][1]);
-                        }
-                    } else {
-                        const double z0 = z[J * TS + 2 * c], z1 = z[J * TS + 2 * c + 1];
-#pragma unroll
-                        for (int k = 0; k < 8; ++k)
-                            dp[i][k] = fma((double)pre[p][2 * k], z0, fma((double)pre[p][2 * k + 1], z1, dp[i][k]));
-                    }
-                }
                 const int b3 = (c >> 3) & 1, b2 = (c >> 2) & 1, b1 = (c >> 1) & 1;
+                constexpr int PH = PF / 2;
 #pragma unroll
                 for (int i = 0; i < 2; ++i) {
                     if (i >= R) break;
+                    const int I = own_row(i, rank, P);
+                    double d[8], s0 = 0.0, s1 = 0.0;
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) d[k] = 0.0;
+#pragma unroll
+                    for (int u = 0; u < PH; ++u) {
+                        const int p = i * PH + u;
+                        if (!slot_ok(p)) continue;
+                        const int J = wv + NWT * u;
+                        if (J >= I) {
+                            const double* zr = z + J * TS + 8 * h;
+#pragma unroll
+                            for (int k = 0; k < 8; ++k) {
+                                s0 = fma((double)pre[p][2 * k], zr[k], s0);
+                                s1 = fma((double)pre[p][2 * k + 1], zr[k], s1);
+                            }
+                        } else {
+                            const double z0 = z[J * TS + 2 * c], z1 = z[J * TS + 2 * c + 1];
+#pragma unroll
+                            for (int k = 0; k < 8; ++k)
+                                d[k] = fma((double)pre[p][2 * k], z0, fma((double)pre[p][2 * k + 1], z1, d[k]));
+                        }
+                    }
                     double* y = &yw[wv][i * TS];
-                    double* d = dp[i];
 #pragma unroll
                     for (int q = 0; q < 4; ++q) {
                         const double keep = b3 ? d[q + 4] : d[q], send = b3 ? d[q] : d[q + 4];
@@ -497,7 +511,6 @@ __global__ void __launch_bounds__(64 * NWV) k_sweep(SweepArgs A) {
                         d[0] = keep + __shfl_xor(send, 2, 64);
                     }
                     d[0] += __shfl_xor(d[0], 1, 64);
-                    double s0 = tp[i][0], s1 = tp[i][1];
                     s0 += __shfl_xor(s0, 16, 64);
                     s1 += __shfl_xor(s1, 16, 64);
                     s0 += __shfl_xor(s0, 32, 64);
@@ -589,20 +602,19 @@ __global__ void k_zero_u32(uint32_t* p, int n) {
 
 // Launch forms.  General: 4 waves (3 tile waves; one wave per SIMD, 512
 // registers each).  Fast (at most 2 block rows per rank, lines up to 384),
-// all of a phase's tiles in registers: FP64 tiles with 4 waves (8 tiles per
-// tile wave, partly in AGPRs), FP32 tiles with 8 waves (7 tile waves, 4
-// tiles each, within 256 VGPRs).
+// all of a phase's tiles in registers: 8 waves (7 tile waves, 4 tiles each,
+// within 256 VGPRs, two waves per SIMD), FP64 or FP32 tiles.
 constexpr int GEN_WAVES = 4;
 const void* sweep_kernel() { return (const void*)k_sweep<double, MAXR, 4, MAXMP, GEN_WAVES>; }
-const void* sweep_kernel_small() { return (const void*)k_sweep<double, 2, 8, 384, 4>; }
+const void* sweep_kernel_small() { return (const void*)k_sweep<double, 2, 4, 384, 8>; }
 
 static void sweep_form(const sf_context* c, bool fast, const void** kern, int* threads) {
     if (c->cfg.factor_precision == SF_FP32) {
         *kern = fast ? (const void*)k_sweep<float, 2, 4, 384, 8> : (const void*)k_sweep<float, MAXR, 4, MAXMP, GEN_WAVES>;
         *threads = fast ? 512 : 64 * GEN_WAVES;
     } else {
-        *kern = fast ? (const void*)k_sweep<double, 2, 8, 384, 4> : (const void*)k_sweep<double, MAXR, 4, MAXMP, GEN_WAVES>;
-        *threads = 64 * (fast ? 4 : GEN_WAVES);
+        *kern = fast ? (const void*)k_sweep<double, 2, 4, 384, 8> : (const void*)k_sweep<double, MAXR, 4, MAXMP, GEN_WAVES>;
+        *threads = 64 * (fast ? 8 : GEN_WAVES);
     }
 }
 int sweep_threads(int fast) { return fast ? 512 : 64 * GEN_WAVES; }
