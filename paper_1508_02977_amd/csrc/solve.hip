@@ -165,7 +165,9 @@ __global__ void __launch_bounds__(64 * NWV) k_sweep(SweepArgs A) {
     constexpr int NWT = NW - 1;                    // tile waves
     constexpr int CW0 = NWT * 64;                  // first thread of the control wave
     constexpr int NRC = (RMAX * TS + 63) / 64;     // own rows per control lane
-    constexpr int RPT = (LMAX + CW0 - 1) / CW0;    // line rows per tile-wave thread (mp <= LMAX)
+    // rows of z per tile-wave thread: general form, all rows over the tile
+    // threads; fast form, the 32 (PF / 2) rows of the wave's column blocks
+    constexpr int RPT = RMAX == 2 ? (16 * PF + 63) / 64 : (LMAX + CW0 - 1) / CW0;
     __shared__ double z[LMAX];
     __shared__ double vup[LMAX];                   // vector of the line above (t - 1)
     __shared__ double vdn[LMAX];                   // vector of the line below (t + 1)
@@ -236,7 +238,7 @@ __global__ void __launch_bounds__(64 * NWV) k_sweep(SweepArgs A) {
     // Rows of z that this thread forms.  Fast form: a tile wave forms exactly
     // the rows it consumes (its column blocks wv + NWT i), so no workgroup
     // barrier separates z from the products; general form: rows tid + CW0 j.
-    static_assert(RMAX != 2 || 64 * RPT == 16 * PF, "fast form: z rows of a wave = its column blocks");
+    static_assert(RMAX != 2 || 64 * RPT >= 16 * PF, "fast form: z rows of a wave = its column blocks");
     // (The thread index is passed through an empty asm statement where rows
     // are formed inside the phase loop, so that the compiler recomputes the
     // few integer operations of their addresses instead of keeping a set of
@@ -247,6 +249,7 @@ __global__ void __launch_bounds__(64 * NWV) k_sweep(SweepArgs A) {
         if constexpr (OPAQUE) asm volatile("" : "+v"(tx));
         if constexpr (RMAX == 2) {
             const int k = (tx & 63) + 64 * j;
+            if (k >= 16 * PF) return LMAX;                  // no row (a lane beyond the wave's blocks)
             return ((tx >> 6) + NWT * (k >> 5)) * TS + (k & 31);
         } else {
             return tx + CW0 * j;
