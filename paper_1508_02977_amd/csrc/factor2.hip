@@ -14,19 +14,20 @@
 //
 // Work split: rank r owns block rows r and NT-1-r (balanced: NT+1 lower tiles
 // per rank) and keeps its tiles in MFMA accumulators (v_mfma_f64_16x16x4f64,
-// one 16x16 block per accumulator) for the whole line.  One more workgroup
-// per chain, the pivot server, forms every Pi: the owner of block row k+1
-// updates its diagonal tile first in pivot step k and hands it over, so Pi_{k+1}
-// is ready by the time the ranks finish the rest of step k.  Pivot blocks and
-// Pi travel as tagged 64-bit words (32-bit tag, half of a double), so one
-// poll both synchronises and transfers them.  Lane layout of that
+// one 16x16 block per accumulator) for the whole line.  Lane layout of that
 // instruction (checked on gfx950): A[i][k] in lane i + 16k, B[k][j] in lane
-// j + 16k, accumulator element q of lane l is D[l/16 + 4q][l%16].  Each pivot step needs
-// block column k of the current matrix: its owners publish it to a global
-// exchange slot (relaxed device-scope stores), bump the subdomain counter,
-// and every rank reads it into LDS.  One exchange per pivot step, NT + 1 per
-// line.  The Schur update of the next line is built from the full symmetric
-// S_{t-1}^{-1} that the ranks leave in global memory at the end of a line.
+// j + 16k, accumulator element q of lane l is D[l/16 + 4q][l%16].
+//
+// Each pivot step needs block column k of the current matrix: its owners
+// publish it to a global exchange slot (relaxed device-scope stores) and bump
+// the chain's counter, and every rank reads it into LDS.  One more workgroup
+// per chain, the pivot server, forms every Pi: the owner of block row k+1
+// updates its diagonal tile first in pivot step k and hands it over, so
+// Pi_{k+1} is ready by the time the ranks finish the rest of step k.  Pivot
+// blocks and Pi travel as tagged 64-bit words (32-bit tag, half of a double),
+// so one poll both synchronises and transfers them.  The Schur update of the
+// next line is built from the full symmetric S_{t-1}^{-1} that the ranks leave
+// in global memory at the end of a line.
 #include <algorithm>
 #include <cmath>
 

@@ -7,7 +7,7 @@ namespace sfdd {
 constexpr int F2_WAVES = 4;         // waves per factor workgroup
 constexpr int F2_BLOCKS = 13;       // 16x16 accumulator blocks per wave
 
-constexpr int F2_COUNTERS = 3;      // per chain counters (one used: column parts published)
+constexpr int F2_COUNTERS = 1;      // per chain counters: column parts published
 
 // doubles per chain: full symmetric inverse (mp x mp), two exchange columns
 // of NT 32x32 tiles, two pivot-block and two pivot-inverse slots of tagged

@@ -81,7 +81,7 @@ struct sf_context {
     double *relres_d;               // [B]
     int32_t *sweeps_d;              // [B]
     int32_t *done_d;                // [B]
-    uint32_t *counters;             // [2 nsub][3] factor synchronisation, three per chain
+    uint32_t *counters;             // [2 nsub] factor synchronisation, one per chain
     uint64_t *etamax_bits;          // [B]
     int32_t *flags_d;               // [4] input validation flags
     // subdomain storage
