@@ -1,5 +1,6 @@
 """Pins of the oracle's presmoothing and split chooser (Sections 1 and 3.1)."""
 import math
+import os
 
 import numpy as np
 import pytest
@@ -59,14 +60,29 @@ def test_separable_pass_equals_direct_2d_convolution():
     assert np.abs(variants.presmooth(I, sigma) - ref).max() < 1e-15
 
 
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "split_ratio_48x48.txt")
+
+
+def load_split_golden():
+    rows = []
+    with open(GOLDEN) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                px, py, r = line.split()
+                rows.append((int(px), int(py), float(r)))
+    return rows
+
+
 def test_split_ratios_of_the_papers_worked_example():
-    # 48 x 48 pixels, twelve parts: 1 x 12 -> 1.846, 2 x 6 -> 3, 3 x 4 -> 3.428
-    assert round(variants.split_ratio(48, 48, 1, 12), 3) == 1.846
-    assert round(variants.split_ratio(48, 48, 12, 1), 3) == 1.846
-    assert variants.split_ratio(48, 48, 2, 6) == 3.0
-    assert round(variants.split_ratio(48, 48, 3, 4), 3) == 3.429     # 24/7 = 3.4286 (printed truncated: 3.428)
+    # every split of the printed figure, to the three decimals printed
+    rows = load_split_golden()
+    assert len(rows) == 6
+    for px, py, r in rows:
+        assert math.floor(variants.split_ratio(48, 48, px, py) * 1000) / 1000 == r, (px, py)
+    # the chosen split is the one with the largest printed ratio
+    best = max(r for _, _, r in rows)
     px, py, r = variants.choose_split(48, 48, 12)
-    assert {px, py} == {3, 4} and abs(r - 24 / 7) < 1e-15
+    assert (px, py, best) in [(a, b, c) for a, b, c in rows] and abs(r - 24 / 7) < 1e-15
 
 
 def test_split_prefers_parts_across_the_longer_side():
