@@ -44,6 +44,7 @@ constexpr int LDP = 34;               // LDS row pitch (doubles): conflict-free 
 constexpr int LTILE = TS * LDP;       // doubles per LDS tile
 constexpr int F2_MAXBLK = 13;         // accumulator blocks per wave: 4 * (NT + 1) / 4
 static_assert(F2_NW == F2_WAVES && F2_MAXBLK == F2_BLOCKS, "factor workspace layout");
+static_assert(F2_NW * 12 * 256 <= F2_MAXNT * TS * 34, "final-write staging fits the exchange column's LDS");
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
@@ -773,16 +774,21 @@ __global__ void __launch_bounds__(F2_THREADS) k_factor2(FactorArgs A) {
             }
             if (kn >= NT) {
                 // ---------- line done: blocks hold -S_t^{-1} ----------------------
-                // (through this wave's scratch, so that the store code is not
-                // unrolled over the accumulators)
+                // The blocks go through LDS (the exchange column is free once
+                // every wave is past its last update), so that the store code is
+                // a loop rather than unrolled over the accumulators and each
+                // block's values are a short LDS read away.
+                constexpr int NSTG = 12;                 // staged blocks per wave (LDS budget)
+                __syncthreads();
+                double* stg = colk + wv * NSTG * 256;
 #pragma unroll
-                for (int b = 0; b < F2_MAXBLK; ++b)
+                for (int b = 0; b < NSTG; ++b)
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) bscr[(b * 4 + q) * 64 + lane] = acc[b][q];
-#pragma unroll 1
-                for (int b = 0; b < F2_MAXBLK; ++b) {
+                    for (int q = 0; q < 4; ++q) stg[(b * 4 + q) * 64 + lane] = acc[b][q];
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                auto store_block = [&](int b, const double (&vals)[4]) {
                     const int blk = wv + F2_NW * b;
-                    if (blk >= nblk) break;
                     int I, J;
                     f2_tile_of(blk >> 2, rowA, rowB, I, J);
                     const int qi = (blk >> 1) & 1, qj = blk & 1;
@@ -790,11 +796,11 @@ __global__ void __launch_bounds__(F2_THREADS) k_factor2(FactorArgs A) {
                     const int64_t toff = ((int64_t)t * d.ntiles + q0) * TSZ;
                     double* tl = Tout + toff;
                     float* tf = reinterpret_cast<float*>(Tout) + toff;
-                    #pragma unroll
+#pragma unroll
                     for (int q = 0; q < 4; ++q) {
                         const int r = 16 * qi + cr + 4 * q, c = 16 * qj + cc;
                         if (I == J && r < c) continue;           // diagonal tiles: mirror the lower half
-                        const double v = -bscr[(b * 4 + q) * 64 + lane];
+                        const double v = -vals[q];
                         if (A.fp32) {
                             tf[r * TS + c] = (float)v;
                             if (I == J) tf[c * TS + r] = (float)v;
@@ -808,6 +814,22 @@ __global__ void __launch_bounds__(F2_THREADS) k_factor2(FactorArgs A) {
                             xstore(Sown + (int64_t)gc * mp + ga, v);
                         }
                     }
+                };
+                static_assert(F2_MAXBLK == NSTG + 1, "one block beyond the staged ones");
+#pragma unroll 1
+                for (int b = 0; b < F2_MAXBLK; ++b) {
+                    if (wv + F2_NW * b >= nblk) break;
+                    if (b == NSTG) {                     // the last block reuses the first slot
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) stg[q * 64 + lane] = acc[NSTG][q];
+                        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                    }
+                    const int sb = b < NSTG ? b : 0;
+                    double vals[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) vals[q] = stg[(sb * 4 + q) * 64 + lane];
+                    store_block(b, vals);
                 }
                 f2_signal(cnt);
             }
