@@ -42,6 +42,15 @@ constexpr int F2_NW = F2_THREADS / 64;
 constexpr int F2_MAXNT = 12;          // line matrices up to 384 x 384
 constexpr int LDP = 34;               // LDS row pitch (doubles): conflict-free 16x4 / 4x16 fragments
 constexpr int LTILE = TS * LDP;       // doubles per LDS tile
+
+// The ranks keep the exchange column in LDS as 32x32 tiles of pitch 32 with
+// the 16-byte chunks of row r permuted by r mod 16 (chunk ch at position
+// ch ^ (r & 15)): a 64-lane load then lands 1 KB contiguously (direct
+// global-to-LDS loads), and the 16x4 operand fragments of the MFMA reads
+// fall on distinct banks.
+__device__ __forceinline__ int colk_at(int J, int r, int c) {
+    return J * TSZ + r * TS + ((((c >> 1) ^ (r & 15))) << 1) + (c & 1);
+}
 constexpr int F2_MAXBLK = 13;         // accumulator blocks per wave: 4 * (NT + 1) / 4
 static_assert(F2_NW == F2_WAVES && F2_MAXBLK == F2_BLOCKS, "factor workspace layout");
 static_assert(F2_NW * 12 * 256 <= F2_MAXNT * TS * 34, "final-write staging fits the exchange column's LDS");
@@ -675,23 +684,24 @@ __global__ void __launch_bounds__(F2_THREADS) k_factor2(FactorArgs A) {
             if (!f2_wait(cnt, Pf * phase, A, sub, &sh_ok)) return;
             const double* xb = xch + (int64_t)((phase - 1) & 1) * NT * TSZ;
             const uint64_t* pb = pslot + (npiv & 1) * 2 * TSZ;
-            // the column in two batches of loads (register budget), while the
-            // pivot server is still forming Pi_k
+            // the column straight into LDS (device-scope 16-byte loads, no
+            // registers), while the pivot server is still forming Pi_k:
+            // instruction q fills LDS chunks 64 q .. 64 q + 63 of the permuted
+            // layout, lane l fetching the chunk that belongs at position 64 q + l
+            {
+                const int ln = tido & 63, nq = NT * (TSZ / 128);
+                const int wvu = __builtin_amdgcn_readfirstlane(wv);
 #pragma unroll
-            for (int half = 0; half < 2; ++half) {
-                constexpr int NL = F2_MAXNT * TSZ / F2_THREADS / 2;
-                double tmp[NL];
-#pragma unroll
-                for (int u = 0; u < NL; ++u) {
-                    const int i = tido + F2_THREADS * (u + NL * half);
-                    tmp[u] = i < NT * TSZ ? xload(xb + i) : 0.0;
+                for (int u = 0; u < F2_MAXNT * (TSZ / 128) / F2_NW; ++u) {
+                    const int q = wvu + F2_NW * u;
+                    if (q >= nq) break;
+                    const int J = q / (TSZ / 128), p = (q % (TSZ / 128)) * 64 + ln;
+                    const int r = p >> 4, ch = (p & 15) ^ (r & 15);
+                    __builtin_amdgcn_global_load_lds(xb + J * TSZ + r * TS + 2 * ch,
+                                                     (__attribute__((address_space(3))) void*)(colk + q * 128), 16, 0,
+                                                     16 /* sc1: device scope */);
                 }
-#pragma unroll
-                for (int u = 0; u < NL; ++u) {
-                    const int i = tido + F2_THREADS * (u + NL * half);
-                    const int J = i / TSZ, r = (i / TS) % TS, c = i % TS;
-                    if (i < NT * TSZ) colk[J * LTILE + r * LDP + c] = tmp[u];
-                }
+                __builtin_amdgcn_s_waitcnt(0);
             }
             if (!f2_tpoll(pb, A.epoch + npiv, piv, A.status, A.status, A.spin_limit, sub, tido)) return;
             __builtin_amdgcn_sched_barrier(0);
@@ -706,7 +716,7 @@ __global__ void __launch_bounds__(F2_THREADS) k_factor2(FactorArgs A) {
                     d4 x = {0.0, 0.0, 0.0, 0.0};
                     #pragma unroll
                     for (int ks = 0; ks < TS / 4; ++ks) {
-                        const double a = colk[I * LTILE + (16 * qi + fr) * LDP + 4 * ks + fk];
+                        const double a = colk[colk_at(I, 16 * qi + fr, 4 * ks + fk)];
                         const double b = piv[(4 * ks + fk) * LDP + 16 * qj + fr];
                         x = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, x, 0, 0, 0);
                     }
@@ -740,7 +750,7 @@ __global__ void __launch_bounds__(F2_THREADS) k_factor2(FactorArgs A) {
                     #pragma unroll
                     for (int ks = 0; ks < TS / 4; ++ks) {
                         const double a = -xr[rr * LTILE + (16 * qi + fr) * LDP + 4 * ks + fk];
-                        const double bb = colk[J * LTILE + (16 * qj + fr) * LDP + 4 * ks + fk];
+                        const double bb = colk[colk_at(J, 16 * qj + fr, 4 * ks + fk)];
                         v = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb, v, 0, 0, 0);
                     }
                     acc[b] = v;
@@ -752,7 +762,7 @@ __global__ void __launch_bounds__(F2_THREADS) k_factor2(FactorArgs A) {
                     #pragma unroll
                     for (int ks = 0; ks < TS / 4; ++ks) {
                         const double a = piv[(16 * qi + fr) * LDP + 4 * ks + fk];
-                        const double bb = colk[J * LTILE + (16 * qj + fr) * LDP + 4 * ks + fk];
+                        const double bb = colk[colk_at(J, 16 * qj + fr, 4 * ks + fk)];
                         v = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb, v, 0, 0, 0);
                     }
                     acc[b] = v;
