@@ -591,20 +591,33 @@ __global__ void __launch_bounds__(F2_THREADS) k_factor2(FactorArgs A) {
                 }
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                // Z[i][jc] = sum over the coupled nodes of column c0 + jc
-                for (int e = lane; e < WN * 16; e += 64) {
-                    const int i = e / 16, jc = e % 16, a2 = c0 + jc;
-                    double zv = 0.0;
-                    if (i < nr && a2 < m) {
-                        const int nlo = a2 / 3 - 1 + dn, nhi = a2 / 3 + dn;
-                        const double* c2 = cf + a2 * 6;
+                // Z[i][jc] = sum over the coupled nodes of column c0 + jc; a lane
+                // keeps one column jc = lane % 16 (its six coupling coefficients
+                // loaded once) and runs over rows i = lane / 16 + 4 u
+                {
+                    const int jc = lane & 15, a2 = c0 + jc;
+                    const bool live = a2 < m;
+                    const int nlo = a2 / 3 - 1 + dn, nhi = a2 / 3 + dn;
+                    double c2[6];
 #pragma unroll
-                        for (int g = 0; g < 3; ++g) {
-                            if (nlo >= 0) zv = fma(win[i * WN + 3 * nlo + g - wc0], c2[g], zv);
-                            if (nhi < ms) zv = fma(win[i * WN + 3 * nhi + g - wc0], c2[3 + g], zv);
+                    for (int g = 0; g < 6; ++g) c2[g] = live ? cf[a2 * 6 + g] : 0.0;
+                    const bool ulo = live && nlo >= 0, uhi = live && nhi < ms;
+                    const int olo = 3 * nlo - wc0, ohi = 3 * nhi - wc0;
+#pragma unroll
+                    for (int u = 0; u < (WN * 16 + 63) / 64; ++u) {
+                        const int i = (lane >> 4) + 4 * u;
+                        if (i >= WN) break;
+                        double zv = 0.0;
+                        if (i < nr) {
+                            const double* wr = win + i * WN;
+#pragma unroll
+                            for (int g = 0; g < 3; ++g) {
+                                if (ulo) zv = fma(wr[olo + g], c2[g], zv);
+                                if (uhi) zv = fma(wr[ohi + g], c2[3 + g], zv);
+                            }
                         }
+                        zb[i * 16 + jc] = zv;
                     }
-                    zb[e] = zv;
                 }
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
