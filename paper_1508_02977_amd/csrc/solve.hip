@@ -73,6 +73,62 @@ __device__ __forceinline__ void load_tile(const float* __restrict__ T, float tv[
     }
 }
 
+// Lane exchanges of the row reductions, kept in the VALU (no LDS crossbar round
+// trip).  Within each 16-lane row, DPP gives partners 15 - c (row mirror),
+// c ^ 7 inside each half row (half mirror), c ^ 2 and c ^ 1 (quad permutes).
+// These pair every lane with one lane of the opposite bit 3, 2, 1, 0 in turn,
+// and the four partner maps generate all 16 lanes, so a transpose-reduce over
+// them sums each kept row over the whole row group, as xor partners would.
+constexpr int DPP_MIRROR = 0x140, DPP_HALF_MIRROR = 0x141, DPP_SWAP2 = 0x4E, DPP_SWAP1 = 0xB1;
+template <int CTRL>
+__device__ __forceinline__ double dpp_partner(double x) {
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+// x plus x of lane ^ 16 (SW = 16) or lane ^ 32 (SW = 32): the permlane swap
+// leaves the two halves of every lane pair in the two registers, whose sum is
+// the same in both lanes.
+template <int SW>
+__device__ __forceinline__ double sum_partner(double x) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+    const unsigned lo = (unsigned)b, hi = (unsigned)(b >> 32);
+    unsigned l0, l1, h0, h1;
+    if constexpr (SW == 16) {
+        const auto l = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+        const auto h = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+        l0 = l[0]; l1 = l[1]; h0 = h[0]; h1 = h[1];
+    } else {
+        static_assert(SW == 32, "lane distance 16 or 32");
+        const auto l = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+        const auto h = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+        l0 = l[0]; l1 = l[1]; h0 = h[0]; h1 = h[1];
+    }
+    return __longlong_as_double((long long)(((unsigned long long)h0 << 32) | l0)) +
+           __longlong_as_double((long long)(((unsigned long long)h1 << 32) | l1));
+}
+// Transpose-reduce of 8 row partials p[8] over the 16 lanes of a row group:
+// lane c ends with row 4 b3 + 2 b2 + b1 (bits of c) in p[0].
+__device__ __forceinline__ void row_group_reduce(double p[8], int c) {
+    const int b3 = (c >> 3) & 1, b2 = (c >> 2) & 1, b1 = (c >> 1) & 1;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const double keep = b3 ? p[q + 4] : p[q], send = b3 ? p[q] : p[q + 4];
+        p[q] = keep + dpp_partner<DPP_MIRROR>(send);
+    }
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const double keep = b2 ? p[q + 2] : p[q], send = b2 ? p[q] : p[q + 2];
+        p[q] = keep + dpp_partner<DPP_HALF_MIRROR>(send);
+    }
+    {
+        const double keep = b1 ? p[1] : p[0], send = b1 ? p[0] : p[1];
+        p[0] = keep + dpp_partner<DPP_SWAP2>(send);
+    }
+    p[0] += dpp_partner<DPP_SWAP1>(p[0]);
+}
+
 // y_I += (tile) z_J for one tile of the block row, into the wave's row buffer y[32].
 template <typename TT>
 __device__ __forceinline__ void tile_apply(const TT tv[16], int I, int J, const double* z, double* y) {
@@ -88,10 +144,8 @@ __device__ __forceinline__ void tile_apply(const TT tv[16], int I, int J, const 
             s0 = fma((double)tv[2 * i], zr[i], s0);
             s1 = fma((double)tv[2 * i + 1], zr[i], s1);
         }
-        s0 += __shfl_xor(s0, 16, 64);
-        s1 += __shfl_xor(s1, 16, 64);
-        s0 += __shfl_xor(s0, 32, 64);
-        s1 += __shfl_xor(s1, 32, 64);
+        s0 = sum_partner<32>(sum_partner<16>(s0));
+        s1 = sum_partner<32>(sum_partner<16>(s1));
         if (h == 0) {
             y[2 * c] += s0;
             y[2 * c + 1] += s1;
@@ -104,23 +158,8 @@ __device__ __forceinline__ void tile_apply(const TT tv[16], int I, int J, const 
         double p[8];
 #pragma unroll
         for (int i = 0; i < 8; ++i) p[i] = fma((double)tv[2 * i], z0, (double)tv[2 * i + 1] * z1);
-        const int b3 = (c >> 3) & 1, b2 = (c >> 2) & 1, b1 = (c >> 1) & 1;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const double keep = b3 ? p[q + 4] : p[q], send = b3 ? p[q] : p[q + 4];
-            p[q] = keep + __shfl_xor(send, 8, 64);
-        }
-#pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            const double keep = b2 ? p[q + 2] : p[q], send = b2 ? p[q] : p[q + 2];
-            p[q] = keep + __shfl_xor(send, 4, 64);
-        }
-        {
-            const double keep = b1 ? p[1] : p[0], send = b1 ? p[0] : p[1];
-            p[0] = keep + __shfl_xor(send, 2, 64);
-        }
-        p[0] += __shfl_xor(p[0], 1, 64);
-        if ((c & 1) == 0) y[8 * h + 4 * b3 + 2 * b2 + b1] += p[0];
+        row_group_reduce(p, c);
+        if ((c & 1) == 0) y[8 * h + (c >> 1)] += p[0];
     }
 }
 
@@ -470,7 +509,6 @@ __global__ void __launch_bounds__(64 * NWV) k_sweep(SweepArgs A) {
                 // transposed partials tp0, tp1 of columns 2c, 2c+1, summed over
                 // this wave's tiles of the row, then one reduction per row
                 const int c = lane & 15, h = lane >> 4;
-                const int b3 = (c >> 3) & 1, b2 = (c >> 2) & 1, b1 = (c >> 1) & 1;
                 constexpr int PH = PF / 2;
 #pragma unroll
                 for (int i = 0; i < 2; ++i) {
@@ -499,26 +537,10 @@ __global__ void __launch_bounds__(64 * NWV) k_sweep(SweepArgs A) {
                         }
                     }
                     double* y = &yw[wv][i * TS];
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const double keep = b3 ? d[q + 4] : d[q], send = b3 ? d[q] : d[q + 4];
-                        d[q] = keep + __shfl_xor(send, 8, 64);
-                    }
-#pragma unroll
-                    for (int q = 0; q < 2; ++q) {
-                        const double keep = b2 ? d[q + 2] : d[q], send = b2 ? d[q] : d[q + 2];
-                        d[q] = keep + __shfl_xor(send, 4, 64);
-                    }
-                    {
-                        const double keep = b1 ? d[1] : d[0], send = b1 ? d[0] : d[1];
-                        d[0] = keep + __shfl_xor(send, 2, 64);
-                    }
-                    d[0] += __shfl_xor(d[0], 1, 64);
-                    s0 += __shfl_xor(s0, 16, 64);
-                    s1 += __shfl_xor(s1, 16, 64);
-                    s0 += __shfl_xor(s0, 32, 64);
-                    s1 += __shfl_xor(s1, 32, 64);
-                    if ((c & 1) == 0) y[8 * h + 4 * b3 + 2 * b2 + b1] = d[0];   // yw is zero here
+                    row_group_reduce(d, c);
+                    s0 = sum_partner<32>(sum_partner<16>(s0));
+                    s1 = sum_partner<32>(sum_partner<16>(s1));
+                    if ((c & 1) == 0) y[8 * h + (c >> 1)] = d[0];   // yw is zero here
                     if (h == 0) {
                         y[2 * c] += s0;
                         y[2 * c + 1] += s1;
