@@ -22,6 +22,11 @@ FLAGS = [
     "-shared",
     # keep hipcc from forming packed FP32 ops (toolchain notes)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # MFMA accumulators in ordinary VGPRs: the factor keeps 13 accumulator
+    # chains live and interleaves them; with the accumulator-register form the
+    # compiler copied every block in and out around its MFMAs (and, with the
+    # interleaved order, runs out of aligned registers)
+    "-mllvm", "-amdgpu-mfma-vgpr-form=1",
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
 ]
 

@@ -56,6 +56,7 @@ static_assert(F2_NW == F2_WAVES && F2_MAXBLK == F2_BLOCKS, "factor workspace lay
 static_assert(F2_NW * 12 * 256 <= F2_MAXNT * TS * 34, "final-write staging fits the exchange column's LDS");
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef double d2 __attribute__((ext_vector_type(2)));
 
 struct FactorArgs {
     const SubDesc* subs;
@@ -398,9 +399,9 @@ __device__ void f2_pivot_inverse(const double* Sk, double* piv, double* xr, cons
 
 __global__ void __launch_bounds__(F2_THREADS) k_factor2(FactorArgs A) {
     // LDS: exchange column (NT tiles), pivot inverse, scaled rows X_I (2 tiles)
-    __shared__ double colk[F2_MAXNT * LTILE];
+    __shared__ __attribute__((aligned(16))) double colk[F2_MAXNT * LTILE];
     __shared__ double piv[LTILE];
-    __shared__ double xr[2 * LTILE];
+    __shared__ __attribute__((aligned(16))) double xr[2 * LTILE];
     __shared__ double adiag[F2_MAXNT * TS];
     __shared__ double Cl[F2_MAXNT * TS * 6];             // couplings to the next line, [m][6]
     __shared__ int sh_ok;
@@ -759,13 +760,25 @@ __global__ void __launch_bounds__(F2_THREADS) k_factor2(FactorArgs A) {
                 const int qi = (blk >> 1) & 1, qj = blk & 1;
                 const int rr = (I == rowA) ? 0 : 1;
                 if (I != k && J != k) {
+                    // S_IJ -= X_I S_kJ.  In product slice ks, lane group fk takes
+                    // k = 8 fk + ks (the 32 values of k in any order give the same
+                    // sum up to rounding), so that a lane's operands of two slices
+                    // are one 16-byte LDS read; all 8 reads are issued before the
+                    // 8 products, so only the first product waits on LDS.
+                    d2 av[4], bv[4];
+                    #pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        av[u] = *reinterpret_cast<const d2*>(&xr[rr * LTILE + (16 * qi + fr) * LDP + 8 * fk + 2 * u]);
+                        bv[u] = *reinterpret_cast<const d2*>(&colk[colk_at(J, 16 * qj + fr, 8 * fk + 2 * u)]);
+                    }
                     d4 v = acc[b];
                     #pragma unroll
-                    for (int ks = 0; ks < TS / 4; ++ks) {
-                        const double a = -xr[rr * LTILE + (16 * qi + fr) * LDP + 4 * ks + fk];
-                        const double bb = colk[colk_at(J, 16 * qj + fr, 4 * ks + fk)];
-                        v = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb, v, 0, 0, 0);
+                    for (int u = 0; u < 4; ++u) {
+                        v = __builtin_amdgcn_mfma_f64_16x16x4f64(-av[u][0], bv[u][0], v, 0, 0, 0);
+                        v = __builtin_amdgcn_mfma_f64_16x16x4f64(-av[u][1], bv[u][1], v, 0, 0, 0);
                     }
+                    __builtin_amdgcn_sched_group_barrier(0x100, 8, 0);   // the 8 LDS reads
+                    __builtin_amdgcn_sched_group_barrier(0x008, 8, 0);   // then the 8 products
                     acc[b] = v;
                 } else if (I != k) {        // J == k: S_Ik <- X_I
                     #pragma unroll
