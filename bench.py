@@ -179,9 +179,10 @@ def main():
     I1 = torch.tensor(pair.I1[None], dtype=torch.float64, device=dev)
     A0 = torch.tensor(alpha0[None], dtype=torch.float64, device=dev)
 
-    def run_form(precision, batch=1):
+    def run_form(precision, batch=1, graph=False):
         """Warm up, then time `steps` whole pipeline steps with the given
-        storage of the inverse Schur tiles, on `batch` pairs at once."""
+        storage of the inverse Schur tiles, on `batch` pairs at once (solves
+        replayed from captured HIP graphs if `graph`)."""
         if batch == 1:
             I0b, I1b, A0b = I0, I1, A0
         else:
@@ -198,7 +199,7 @@ def main():
             Al.copy_(A0b)
             U.zero_()
             return api.run_pipeline(ctx, I0b, I1b, Al, U, rtol=RTOL, max_sweeps=MAX_SWEEPS, passes=PASSES,
-                                    kappa=KAPPA, eta_thr=ETA_THR, alpha_th=ALPHA_TH)
+                                    kappa=KAPPA, eta_thr=ETA_THR, alpha_th=ALPHA_TH, graph=graph)
 
         for _ in range(args.warmup):
             step()
@@ -298,6 +299,17 @@ def main():
             "final_relres": [list(r) for r in zip(*bt["last"].relres)],
             "sweep_avg_launch_ms": bt["avg_sweep_ms"],
             "phase_ms_per_step": {k: v[0] / args.steps for k, v in bt["prof"].items()},
+        }
+    if not args.plain_only:
+        # the plain form with every 4 solve iterations replayed from one captured
+        # HIP graph: the same kernels, so the same iterate bit for bit
+        gr = run_form(api.SF_FP64, graph=True)
+        out["graph_form"] = {
+            "form": "plain FP64, solve iterations replayed from captured HIP graphs (chunks of 4)",
+            "value": 3 * W * H / (gr["ms_step"] * 1e-3), "unit": "unknowns/s", "ms_per_step": gr["ms_step"],
+            "speedup_vs_plain": ms_step / gr["ms_step"],
+            "sweeps_per_solve": [s[0] for s in gr["last"].sweeps],
+            "iterate_equals_plain": bool(torch.equal(gr["U"], plain["U"])),
         }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(pair, alpha0, sum(sweeps), len(sweeps), PASSES)

@@ -115,6 +115,20 @@ int sf_factor_subdomains(sf_context* ctx);
 int sf_schwarz_solve(sf_context* ctx, double* U, double rtol, int32_t max_sweeps,
                      int32_t* sweeps, double* relres);
 
+/* sf_schwarz_solve with the launches of every 4 iterations (residual and
+ * convergence test, sweep) replayed from one captured HIP graph: the same
+ * kernels in the same order, so U, sweeps and relres equal those of
+ * sf_schwarz_solve bit for bit.  The graph runs on a private stream of the
+ * context (created on the first call: default priority, non-blocking) that
+ * waits for the work queued on the context's stream, which in turn waits
+ * for the graph's; the iteration index and the sweep's tag base live on the
+ * device for the replays.  Iterations beyond the last whole chunk of 4 run
+ * as ordinary launches.  Converged pairs make later replays' kernels exit at
+ * once.  Arguments, outputs and return codes as sf_schwarz_solve; calls on
+ * one context must not overlap.                                            */
+int sf_schwarz_solve_graph(sf_context* ctx, double* U, double rtol, int32_t max_sweeps,
+                           int32_t* sweeps, double* relres);
+
 /* Autotuning of the sweep's launch shape: with current factors, time
  * `trials` RAS sweeps for every number of workgroups per chain that changes
  * the block rows each one owns (clamped to what fits co-resident), keep the

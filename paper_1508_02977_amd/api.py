@@ -62,6 +62,7 @@ _SIGS = {
     "sf_assemble": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "sf_factor_subdomains": (c_int32, [c_void_p]),
     "sf_schwarz_solve": (c_int32, [c_void_p, c_void_p, c_double, c_int32, c_void_p, c_void_p]),
+    "sf_schwarz_solve_graph": (c_int32, [c_void_p, c_void_p, c_double, c_int32, c_void_p, c_void_p]),
     "sf_autotune": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p]),
     "sf_adjoint": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_double,
                              c_int32, c_void_p, c_void_p]),
@@ -215,6 +216,17 @@ def sf_schwarz_solve(ctx: Context, U, rtol: float, max_sweeps: int):
     return code, list(sw), list(rr)
 
 
+def sf_schwarz_solve_graph(ctx: Context, U, rtol: float, max_sweeps: int):
+    """As :func:`sf_schwarz_solve`, with every 4 iterations replayed from one
+    captured HIP graph (identical results)."""
+    sw = (c_int32 * ctx.B)()
+    rr = (c_double * ctx.B)()
+    code = lib().sf_schwarz_solve_graph(ctx.handle, _dev(U, ctx.field_shape(), "U"), float(rtol),
+                                        int(max_sweeps), ctypes.cast(sw, c_void_p), ctypes.cast(rr, c_void_p))
+    _check(code, "sf_schwarz_solve_graph", ctx, allow=(SF_NOT_CONVERGED,))
+    return code, list(sw), list(rr)
+
+
 def sf_autotune(ctx: Context, U, trials: int = 3) -> int:
     """Time the sweep's launch shapes on the current factors and keep the
     fastest; returns the chosen workgroups per chain.  ``U`` is overwritten."""
@@ -345,22 +357,24 @@ class PipelineResult:
 
 
 def run_pipeline(ctx: Context, I0, I1, alpha, U, rtol=1e-8, max_sweeps=1000, passes=0, kappa=1.0,
-                 eta_thr=0.1, alpha_th=1e-3, sweeps_per_solve=None) -> PipelineResult:
+                 eta_thr=0.1, alpha_th=1e-3, sweeps_per_solve=None, graph=False) -> PipelineResult:
     """assemble -> factor -> solve -> (update_alpha -> factor -> solve) x passes.
 
     ``alpha`` is updated in place and ``U`` holds the final iterate (each solve
     warm-starts from the previous one).  ``sweeps_per_solve`` forces exact
-    sweep counts (rtol 0), for comparisons at equal sweep counts.
+    sweep counts (rtol 0), for comparisons at equal sweep counts.  ``graph``
+    solves with :func:`sf_schwarz_solve_graph` (identical results).
     """
+    solve = sf_schwarz_solve_graph if graph else sf_schwarz_solve
     sf_assemble(ctx, I0, I1, alpha)
     sweeps, rels, etas = [], [], []
     status = SF_OK
     for it in range(passes + 1):
         sf_factor_subdomains(ctx)
         if sweeps_per_solve is not None:
-            code, sw, rr = sf_schwarz_solve(ctx, U, 0.0, sweeps_per_solve[it])
+            code, sw, rr = solve(ctx, U, 0.0, sweeps_per_solve[it])
         else:
-            code, sw, rr = sf_schwarz_solve(ctx, U, rtol, max_sweeps)
+            code, sw, rr = solve(ctx, U, rtol, max_sweeps)
             status = max(status, code)
         sweeps.append(sw)
         rels.append(rr)

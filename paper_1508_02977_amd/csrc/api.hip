@@ -46,6 +46,17 @@ __global__ void k_zero_status_api(sfdd::DevStatus* st) {
     st->row = -1;
 }
 
+// Device counters of a graph-replayed Schwarz loop: iteration index and sweep
+// tag base, set once, then advanced by the graph after every sweep.
+__global__ void k_graph_init(int32_t* k, uint32_t* epoch, uint32_t e0) {
+    *k = 0;
+    *epoch = e0;
+}
+__global__ void k_graph_advance(int32_t* k, uint32_t* epoch, uint32_t inc) {
+    *k += 1;
+    *epoch += inc;
+}
+
 int fill_i32(sf_context* c, int32_t* p, int n, int32_t v) {
     hipLaunchKernelGGL(k_fill_i32, dim3((n + 255) / 256), dim3(256), 0, c->stream, p, n, v);
     return hipGetLastError() == hipSuccess ? SF_OK : SF_ERR_HIP;
@@ -183,6 +194,11 @@ void sf_destroy(sf_context* c) {
         if (p) (void)hipFree(p);
     if (c->host_stage) (void)hipHostFree(c->host_stage);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+    if (c->gk_d) (void)hipFree(c->gk_d);
+    if (c->gepoch_d) (void)hipFree(c->gepoch_d);
+    for (hipEvent_t e : c->gev)
+        if (e) (void)hipEventDestroy(e);
+    if (c->gstream) (void)hipStreamDestroy(c->gstream);
     delete c;
 }
 
@@ -433,16 +449,23 @@ int sf_factor_subdomains(sf_context* c) {
 
 // RAS iteration on A U = rhs from the U given, stopping per pair at
 // ||rhs - A U|| <= rtol ||rhs|| (rhs_n2 = ||rhs||^2 on the device).
-static int schwarz_loop(sf_context* c, double* U, const double* rhs, const double* rhs_n2, double rtol,
-                        int32_t max_sweeps, int32_t* sweeps, double* relres) {
+// Prologue: pairs with rhs = 0 get U = 0; all pairs active; status cleared.
+static int loop_prologue(sf_context* c, double* U, const double* rhs_n2) {
     SF_TRY(sfdd::launch_zero_where_rhs_zero(c, U, rhs_n2));
     SF_TRY(fill_i32(c, c->done_d, c->B, 0));
     hipLaunchKernelGGL(k_zero_status_api, dim3(1), dim3(1), 0, c->stream, c->status_d);
     SF_HIP(hipGetLastError());
+    return SF_OK;
+}
+
+// Iterations k0 .. max_sweeps, one launch each (residual + convergence test,
+// then a sweep); the host looks at the done flags every 4 sweeps.
+static int loop_iterations(sf_context* c, double* U, const double* rhs, const double* rhs_n2, double rtol,
+                           int32_t max_sweeps, int k0) {
     int32_t* hd = (int32_t*)stage_a(c);
     const int check_every = 4;
     sfdd::DevStatus* hst = (sfdd::DevStatus*)c->host_stage;
-    for (int k = 0; k <= max_sweeps; ++k) {
+    for (int k = k0; k <= max_sweeps; ++k) {
         SF_TRY(sfdd::prof_begin(c, sfdd::PROF_RESIDUAL));
         SF_TRY(sfdd::launch_residual(c, U, c->r, 1, rtol, k, max_sweeps, rhs, rhs_n2));
         SF_TRY(sfdd::prof_end(c));
@@ -461,7 +484,11 @@ static int schwarz_loop(sf_context* c, double* U, const double* rhs, const doubl
             if (all) break;
         }
     }
-    // results
+    return SF_OK;
+}
+
+// Per-pair results of the loop and its status.
+static int loop_finish(sf_context* c, double rtol, int32_t* sweeps, double* relres) {
     double* hrel = (double*)stage_b(c);
     int32_t* hsw = (int32_t*)stage_c(c);
     SF_HIP(hipMemcpyAsync(hrel, c->relres_d, c->B * sizeof(double), hipMemcpyDeviceToHost, c->stream));
@@ -478,6 +505,108 @@ static int schwarz_loop(sf_context* c, double* U, const double* rhs, const doubl
     const int code = pull_status(c);
     if (code != SF_OK) return code;
     return rc;
+}
+
+static int schwarz_loop(sf_context* c, double* U, const double* rhs, const double* rhs_n2, double rtol,
+                        int32_t max_sweeps, int32_t* sweeps, double* relres) {
+    SF_TRY(loop_prologue(c, U, rhs_n2));
+    SF_TRY(loop_iterations(c, U, rhs, rhs_n2, rtol, max_sweeps, 0));
+    return loop_finish(c, rtol, sweeps, relres);
+}
+
+// Graph-replayed iterations on c->stream (the private stream): one chunk of
+// GRAPH_CHUNK iterations (residual + convergence test, sweep, advance of the
+// device counters) and the copies of the done flags and status is captured
+// once and replayed while whole chunks fit in max_sweeps and some pair is
+// active.  *k_next: the first iteration not run (max_sweeps + 1 when every
+// pair finished or a device wait was abandoned).
+constexpr int GRAPH_CHUNK = 4;
+static int graph_iterations(sf_context* c, double* U, double rtol, int32_t max_sweeps, int* k_next) {
+    *k_next = 0;
+    if (max_sweeps < GRAPH_CHUNK) return SF_OK;
+    const uint32_t e0 = c->sweep_epoch, inc = sfdd::sweep_epoch_step(c);
+    hipLaunchKernelGGL(k_graph_init, dim3(1), dim3(1), 0, c->stream, c->gk_d, c->gepoch_d, e0);
+    SF_HIP(hipGetLastError());
+    int32_t* hd = (int32_t*)stage_a(c);
+    sfdd::DevStatus* hst = (sfdd::DevStatus*)c->host_stage;
+    hipGraph_t g = nullptr;
+    hipGraphExec_t ge = nullptr;
+    SF_HIP(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    c->graph_capture = 1;
+    int rc = SF_OK;
+    for (int i = 0; i < GRAPH_CHUNK && rc == SF_OK; ++i) {
+        rc = sfdd::launch_residual(c, U, c->r, 1, rtol, 0, max_sweeps, c->F, c->Fn2);
+        if (rc == SF_OK) rc = sfdd::launch_sweep(c, U, c->r, -1, nullptr, nullptr);
+        if (rc == SF_OK) {
+            hipLaunchKernelGGL(k_graph_advance, dim3(1), dim3(1), 0, c->stream, c->gk_d, c->gepoch_d, inc);
+            if (hipGetLastError() != hipSuccess) rc = SF_ERR_HIP;
+        }
+    }
+    if (rc == SF_OK &&
+        hipMemcpyAsync(hd, c->done_d, c->B * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream) != hipSuccess)
+        rc = SF_ERR_HIP;
+    if (rc == SF_OK &&
+        hipMemcpyAsync(hst, c->status_d, sizeof(sfdd::DevStatus), hipMemcpyDeviceToHost, c->stream) != hipSuccess)
+        rc = SF_ERR_HIP;
+    c->graph_capture = 0;
+    if (hipStreamEndCapture(c->stream, &g) != hipSuccess && rc == SF_OK) rc = SF_ERR_HIP;
+    if (rc == SF_OK && hipGraphInstantiate(&ge, g, nullptr, nullptr, 0) != hipSuccess) rc = SF_ERR_HIP;
+    int k = 0, replays = 0;
+    while (rc == SF_OK && k + GRAPH_CHUNK <= max_sweeps) {
+        if (hipGraphLaunch(ge, c->stream) != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess) {
+            rc = SF_ERR_HIP;
+            break;
+        }
+        ++replays;
+        k += GRAPH_CHUNK;
+        bool all = true;
+        for (int b = 0; b < c->B; ++b) all = all && hd[b];
+        if (hst->code != SF_OK || all) {
+            k = max_sweeps + 1;
+            break;
+        }
+    }
+    // the replays used tag bases e0 .. e0 + (GRAPH_CHUNK replays - 1) inc
+    c->sweep_epoch = std::max(c->sweep_epoch, e0 + (uint32_t)(GRAPH_CHUNK * replays) * inc);
+    if (ge) (void)hipGraphExecDestroy(ge);
+    if (g) (void)hipGraphDestroy(g);
+    *k_next = k;
+    return rc;
+}
+
+int sf_schwarz_solve_graph(sf_context* c, double* U, double rtol, int32_t max_sweeps, int32_t* sweeps,
+                           double* relres) {
+    if (!c || !U || max_sweeps < 0 || !(rtol >= 0.0)) return SF_ERR_INVALID;
+    if (c->state != ST_FACTORED) return SF_ERR_STATE;
+    if (!c->gstream) {
+        if (hipStreamCreateWithFlags(&c->gstream, hipStreamNonBlocking) != hipSuccess) {
+            c->gstream = nullptr;
+            return SF_ERR_HIP;
+        }
+        for (hipEvent_t& e : c->gev)
+            if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+                e = nullptr;
+                return SF_ERR_HIP;
+            }
+        int rc = dalloc(&c->gk_d, 1);
+        rc |= dalloc(&c->gepoch_d, 1);
+        if (rc != SF_OK) return SF_ERR_OOM;
+    }
+    SF_TRY(loop_prologue(c, U, c->Fn2));
+    // the private stream continues after the work queued on the context's stream
+    SF_HIP(hipEventRecord(c->gev[0], c->stream));
+    SF_HIP(hipStreamWaitEvent(c->gstream, c->gev[0], 0));
+    hipStream_t user = c->stream;
+    c->stream = c->gstream;
+    int k = 0;
+    int rc = graph_iterations(c, U, rtol, max_sweeps, &k);
+    if (rc == SF_OK && k <= max_sweeps) rc = loop_iterations(c, U, c->F, c->Fn2, rtol, max_sweeps, k);
+    c->stream = user;
+    // and the context's stream continues after the private one
+    if (hipEventRecord(c->gev[1], c->gstream) != hipSuccess || hipStreamWaitEvent(user, c->gev[1], 0) != hipSuccess)
+        return SF_ERR_HIP;
+    if (rc != SF_OK) return rc;
+    return loop_finish(c, rtol, sweeps, relres);
 }
 
 int sf_schwarz_solve(sf_context* c, double* U, double rtol, int32_t max_sweeps, int32_t* sweeps, double* relres) {

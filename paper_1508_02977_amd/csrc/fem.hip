@@ -150,10 +150,12 @@ __global__ void k_residual(const double* __restrict__ f0, const double* __restri
 // relres <= rtol, on a non-finite norm, at max_sweeps, or at once if F = 0.
 __global__ void k_converge(const double* __restrict__ partials, int npart, const double* __restrict__ Fn2,
                            double* __restrict__ relres, int32_t* __restrict__ sweeps,
-                           int32_t* __restrict__ done, double rtol, int sweep, int max_sweeps) {
+                           int32_t* __restrict__ done, double rtol, int sweep, int max_sweeps,
+                           const int32_t* __restrict__ sweep_dev) {
     __shared__ double sh[NODE_THREADS / 64];
     const int pair = blockIdx.x;
     if (done[pair]) return;                      // uniform over the block
+    if (sweep_dev) sweep = *sweep_dev;           // graph replay: the index lives on the device
     double v = 0.0;
     for (int i = threadIdx.x; i < npart; i += blockDim.x) v += partials[(int64_t)pair * npart + i];
     const double s = block_sum(v, sh);
@@ -526,7 +528,8 @@ int launch_residual(sf_context* c, const double* U, double* r, int fuse_converge
     SF_LAUNCH_CHECK();
     if (fuse_converge) {
         hipLaunchKernelGGL(k_converge, dim3(c->B), dim3(NODE_THREADS), 0, c->stream, c->partials, c->npart,
-                           rhs_n2, c->relres_d, c->sweeps_d, c->done_d, rtol, sweep, max_sweeps);
+                           rhs_n2, c->relres_d, c->sweeps_d, c->done_d, rtol, sweep, max_sweeps,
+                           c->graph_capture ? (const int32_t*)c->gk_d : (const int32_t*)nullptr);
     } else {
         hipLaunchKernelGGL(k_finalize_norm, dim3(c->B), dim3(64), 0, c->stream, c->partials, c->npart,
                            c->relres_d);

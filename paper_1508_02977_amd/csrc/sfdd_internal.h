@@ -92,6 +92,14 @@ struct sf_context {
     sfdd::DevStatus status_h;       // last error detail
     // host staging (pinned)
     void *host_stage;
+    // graph-replayed Schwarz loop (sf_schwarz_solve_graph): a private stream,
+    // and the iteration index and sweep tag base kept on the device so that a
+    // replayed graph reads fresh values
+    hipStream_t gstream;            // created on first use: default priority, non-blocking
+    hipEvent_t gev[2];
+    int32_t *gk_d;                  // iteration index read by the convergence test
+    uint32_t *gepoch_d;             // tag base read by the sweep
+    int graph_capture;              // 1 while the chunk graph is being captured
     // optional per-kernel timing (sf_profile): event pairs around launches
     int profiling;
     std::vector<hipEvent_t> ev_pool;
@@ -121,6 +129,7 @@ int launch_line_coeffs(sf_context* c);
 const void* factor2_kernel();
 int launch_sweep(sf_context* c, double* U, const double* r, int single_sub, const double* b_local,
                  double* x_local);
+uint32_t sweep_epoch_step(const sf_context* c);   // tag base advance of one sweep launch
 const void* sweep_kernel();
 const void* sweep_kernel_small();
 int sweep_threads(int fast);

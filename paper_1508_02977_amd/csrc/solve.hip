@@ -39,6 +39,7 @@ struct SweepArgs {
     int W, H, mode;
     int groups;             // 1: plain substitution; 2: twisted (both ends towards line kmid)
     uint32_t epoch;         // tag base of this launch (published words carry epoch + phase)
+    const uint32_t* epoch_dev;   // if set, the tag base is read here (graph replays)
     long long spin_limit;
 };
 
@@ -253,7 +254,7 @@ __global__ void __launch_bounds__(64 * NWV) k_sweep(SweepArgs A) {
     uint64_t* __restrict__ mypub = pub + (int64_t)grp * 6 * mp;
     DevStatus* st = A.status;
     const long long spin = A.spin_limit;
-    const uint32_t epoch = A.epoch;
+    const uint32_t epoch = A.epoch_dev ? *A.epoch_dev : A.epoch;
     auto tag_of = [&](int g, int q) -> uint32_t { return epoch + 2u * (uint32_t)q + (uint32_t)g; };
     auto slot_of = [&](int g, int q) -> const uint64_t* {
         const int Lg = g == 0 ? km : nt - 1 - km;
@@ -644,6 +645,12 @@ static void sweep_form(const sf_context* c, bool fast, const void** kern, int* t
 }
 int sweep_threads(int fast) { return fast ? 512 : 64 * GEN_WAVES; }
 
+uint32_t sweep_epoch_step(const sf_context* c) {
+    int maxph = 0;
+    for (const auto& d : c->subs) maxph = std::max(maxph, 2 * d.nt);
+    return 2u * (uint32_t)maxph + 4;
+}
+
 int launch_sweep(sf_context* c, double* U, const double* r, int single_sub, const double* b_local, double* x_local) {
     SweepArgs a;
     a.subs = c->d_subs;
@@ -662,11 +669,12 @@ int launch_sweep(sf_context* c, double* U, const double* r, int single_sub, cons
     a.groups = c->groups;
     a.spin_limit = 1ll << 20;
     // tags must differ from every tag left in the exchange buffers by earlier
-    // launches: advance by more than the tags of one launch (2 per phase)
+    // launches: advance by more than the tags of one launch (2 per phase).
+    // While a graph is captured the kernel reads the tag base from the device
+    // counter that the graph advances after every sweep.
     a.epoch = c->sweep_epoch;
-    int maxph = 0;
-    for (const auto& d : c->subs) maxph = std::max(maxph, 2 * d.nt);
-    c->sweep_epoch += 2u * (uint32_t)maxph + 4;
+    a.epoch_dev = c->graph_capture ? c->gepoch_d : nullptr;
+    c->sweep_epoch += sweep_epoch_step(c);
     const int ranks = c->groups * c->maxP;
     const int grid = single_sub >= 0 ? 8 * ranks : c->sweep_grid;
     int maxmp = 0;
@@ -676,7 +684,9 @@ int launch_sweep(sf_context* c, double* U, const double* r, int single_sub, cons
     int threads;
     sweep_form(c, fast, &kern, &threads);
     void* args[] = {&a};
-    if (ranks > 1) {
+    // A captured launch is an ordinary kernel node: the grid fits the
+    // co-resident capacity measured at creation, and every wait is bounded.
+    if (ranks > 1 && !c->graph_capture) {
         if (hipLaunchCooperativeKernel(kern, dim3(grid), dim3(threads), args, 0, c->stream) != hipSuccess)
             return SF_ERR_HIP;
     } else {
