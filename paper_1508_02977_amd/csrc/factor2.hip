@@ -289,6 +289,76 @@ __device__ __forceinline__ void f2_publish_diag(const d4 (&acc)[F2_MAXBLK], uint
     }
 }
 
+// Cross-lane moves of the pivot sweep, all in the VALU.  A 16x16 block sits
+// in a wave as element q of lane (ci, ri) = row ri + 4q, column ci
+// (lane = ci + 16 ri).  Broadcast of lane row R (lanes 16R..16R+15) to all
+// four: permlane16_swap(x, x) yields rows (0,0,2,2) and (1,1,3,3),
+// permlane32_swap(x, x) the lower and the upper half twice (checked on
+// gfx950).
+template <int R>
+__device__ __forceinline__ double f2_bcast_row(double x) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+    unsigned lo = (unsigned)b, hi = (unsigned)(b >> 32);
+    const auto l1 = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+    const auto h1 = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+    lo = (R & 1) ? l1[1] : l1[0];
+    hi = (R & 1) ? h1[1] : h1[0];
+    const auto l2 = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+    const auto h2 = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+    lo = (R & 2) ? l2[1] : l2[0];
+    hi = (R & 2) ? h2[1] : h2[0];
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+// lane L of every 16-lane row to the whole row (DPP row_newbcast)
+template <int L>
+__device__ __forceinline__ double f2_row_lane(double x) {
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, 0x150 + L, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x150 + L, 0xF, 0xF, false);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+__device__ __forceinline__ double f2_lane(double x, int l) {
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readlane((int)b, l), hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+// Gauss-Jordan step on pivot P of the 16x16 block v (see f2_pivot_inverse):
+// row P from its lane row, column P from lane P of every row, the pivot by
+// readlane.  The pivot test is recorded in bad (first failing pivot).
+template <int P>
+__device__ __forceinline__ void f2_gj_step(double (&v)[4], const double (&adg)[16], int ci, int ri, int& bad) {
+    constexpr int Q = P >> 2, R = P & 3;
+    const double rowp = f2_bcast_row<R>(v[Q]);               // M[P][ci]
+    double colp[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) colp[q] = f2_row_lane<P>(v[q]);   // M[ri + 4q][P]
+    const double pp = f2_lane(v[Q], P + 16 * R);             // M[P][P]
+    const bool okp = pp > 1e-13 * adg[P] && isfinite(pp);
+    bad = (bad < 0 && !okp) ? P : bad;
+    double ip = __builtin_amdgcn_rcp(pp);
+    ip = fma(fma(-pp, ip, 1.0), ip, ip);
+    ip = fma(fma(-pp, ip, 1.0), ip, ip);
+    const bool jp = ci == P;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const bool iq = ri + 4 * q == P;
+        const double upd = v[q] - colp[q] * rowp * ip;
+        const double side = jp ? colp[q] * ip : upd;
+        v[q] = iq ? (jp ? -ip : rowp * ip) : side;
+    }
+}
+template <int P>
+struct F2Sweep {
+    __device__ static __forceinline__ void run(double (&v)[4], const double (&adg)[16], int ci, int ri, int& bad) {
+        f2_gj_step<P>(v, adg, ci, ri, bad);
+        F2Sweep<P + 1>::run(v, adg, ci, ri, bad);
+    }
+};
+template <>
+struct F2Sweep<16> {
+    __device__ static __forceinline__ void run(double (&)[4], const double (&)[16], int, int, int&) {}
+};
+
 __device__ void f2_pivot_inverse(const double* Sk, double* piv, double* xr, const double* adiag_k, int lane,
                                  DevStatus* status, int sub, int64_t row0) {
     constexpr int PB = 17;                        // pitch of the 16x16 scratch blocks
@@ -296,7 +366,6 @@ __device__ void f2_pivot_inverse(const double* Sk, double* piv, double* xr, cons
     double* bB = bA + 16 * PB;                    // B, then -C'^-1 X
     double* bX = bB + 16 * PB;                    // X = B A^-1
     double* bC = bX + 16 * PB;                    // C'^-1
-    double* prow = bC + 16 * PB;                  // pivot row
     const int ci = lane & 15, ri = lane >> 4;     // element q of a lane: row ri + 4q, column ci
     d4 Av, Bv, Cv;
 #pragma unroll
@@ -306,41 +375,20 @@ __device__ void f2_pivot_inverse(const double* Sk, double* piv, double* xr, cons
         Bv[q] = 0.5 * (Sk[(16 + i) * LDP + j] + Sk[j * LDP + 16 + i]);
         Cv[q] = 0.5 * (Sk[(16 + i) * LDP + 16 + j] + Sk[(16 + j) * LDP + 16 + i]);
     }
-    // v (symmetric 16x16) <- -v^{-1}.  The pivot test is recorded per step and
-    // reported once after the sweep (first failing pivot), and 1/pp is the
-    // hardware reciprocal refined by two Newton steps r <- r + r (1 - pp r),
-    // which keeps every step of this latency-bound chain short.
+    // v (16x16) <- -v^{-1} by Gauss-Jordan without pivoting.  The pivot test
+    // is recorded per step and reported once after the sweep (first failing
+    // pivot), and 1/pp is the hardware reciprocal refined by two Newton steps
+    // r <- r + r (1 - pp r), which keeps every step of this latency-bound chain
+    // short; rows, columns and the pivot move between lanes without LDS.
     auto sweep16 = [&](d4& v, int poff) {
         double adg[16];
 #pragma unroll
         for (int p = 0; p < 16; ++p) adg[p] = adiag_k[poff + p];
+        double w[4] = {v[0], v[1], v[2], v[3]};
         int bad = -1;
+        F2Sweep<0>::run(w, adg, ci, ri, bad);
 #pragma unroll
-        for (int p = 0; p < 16; ++p) {
-            if (ri == (p & 3)) prow[ci] = v[p >> 2];             // row p = column p
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            const double pp = prow[p];
-            const double rowp = prow[ci];
-            double colp[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) colp[q] = prow[ri + 4 * q];
-            const bool okp = pp > 1e-13 * adg[p] && isfinite(pp);
-            bad = (bad < 0 && !okp) ? p : bad;
-            double ip = __builtin_amdgcn_rcp(pp);
-            ip = fma(fma(-pp, ip, 1.0), ip, ip);
-            ip = fma(fma(-pp, ip, 1.0), ip, ip);
-            const bool jp = ci == p;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const bool iq = ri + 4 * q == p;
-                const double upd = v[q] - colp[q] * rowp * ip;
-                const double side = jp ? colp[q] * ip : upd;
-                v[q] = iq ? (jp ? -ip : rowp * ip) : side;
-            }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        }
+        for (int q = 0; q < 4; ++q) v[q] = w[q];
         if (lane == 0 && bad >= 0 && atomicCAS(&status->code, 0, SF_NOT_SPD) == 0) {
             status->sub = sub;
             status->row = row0 + poff + bad;
