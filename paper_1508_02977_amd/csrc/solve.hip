@@ -367,7 +367,7 @@ __global__ void __launch_bounds__(64 * NWV) k_sweep(SweepArgs A) {
     auto has_dn = [&](int q, int t) -> bool {
         return (q < L) ? (grp == 1 && t < nt - 1) : (q == L ? t < nt - 1 : grp == 0);
     };
-    auto prefetch = [&](int q) {                    // tile waves
+    auto prefetch = [&](int q, bool tiles) {        // tile waves
         const int t = line_of(q);
         const bool hu = has_up(q, t), hd = has_dn(q, t);
 #pragma unroll
@@ -384,6 +384,7 @@ __global__ void __launch_bounds__(64 * NWV) k_sweep(SweepArgs A) {
                 }
             }
         }
+        if (!tiles) return;
         const TT* Tl = Tb + (int64_t)t * tstride;
 #pragma unroll
         for (int p = 0; p < PF; ++p)
@@ -428,7 +429,7 @@ __global__ void __launch_bounds__(64 * NWV) k_sweep(SweepArgs A) {
     for (int i = 0; i < NRC; ++i) pw[i] = 0.0;
 
     for (int i = tid; i < NWT * RMAX * TS; i += NTHR) (&yw[0][0])[i] = 0.0;
-    if (!ctl) prefetch(0);
+    if (!ctl) prefetch(0, true);
     // Phase structure (B = workgroup barrier):
     //   control wave: [gather(q)] B z B  .  B [finish, publish(q)]
     //   tile waves:              B z B [compute(q)] B [prefetch(q+1)]
@@ -536,6 +537,9 @@ __global__ void __launch_bounds__(64 * NWV) k_sweep(SweepArgs A) {
                             for (int k = 0; k < 8; ++k)
                                 d[k] = fma((double)pre[p][2 * k], z0, fma((double)pre[p][2 * k + 1], z1, d[k]));
                         }
+                        // the slot is free: its tile of the next line streams in
+                        // under the rest of this phase
+                        if (q + 1 < nphase) load_tile(Tb + (int64_t)line_of(q + 1) * tstride + toff[p], pre[p]);
                     }
                     double* y = &yw[wv][i * TS];
                     row_group_reduce(d, c);
@@ -563,7 +567,8 @@ __global__ void __launch_bounds__(64 * NWV) k_sweep(SweepArgs A) {
         }
         __syncthreads();
         if (!ctl) {
-            if (q + 1 < nphase) prefetch(q + 1);
+            // the fast form has already reloaded its tile slots for the next line
+            if (q + 1 < nphase) prefetch(q + 1, !FAST);
         } else {
             // finish and publish this rank's rows; keep them; prefetch w
             const uint64_t tag = (uint64_t)tag_of(grp, q) << 32;
