@@ -317,6 +317,7 @@ __global__ void __launch_bounds__(64 * NWV) k_sweep(SweepArgs A) {
     // the row partials stay in registers until one reduction per row.  General
     // form: slot p holds the tile qt = wv + NWT p of the rank's row-major list.
     constexpr bool FAST = RMAX == 2;
+    constexpr bool RELOAD = FAST && sizeof(TT) == 8;   // tile slots reloaded right after their products
     auto slot_ok = [&](int p) -> bool {
         if constexpr (FAST) return p / (PF / 2) < R && wv + NWT * (p % (PF / 2)) < NT;
         else return wv + NWT * p < ntw;
@@ -537,9 +538,11 @@ __global__ void __launch_bounds__(64 * NWV) k_sweep(SweepArgs A) {
                             for (int k = 0; k < 8; ++k)
                                 d[k] = fma((double)pre[p][2 * k], z0, fma((double)pre[p][2 * k + 1], z1, d[k]));
                         }
-                        // the slot is free: its tile of the next line streams in
-                        // under the rest of this phase
-                        if (q + 1 < nphase) load_tile(Tb + (int64_t)line_of(q + 1) * tstride + toff[p], pre[p]);
+                        // FP64 tiles: the slot is free, so its tile of the next
+                        // line streams in under the rest of this phase (with FP32
+                        // tiles the stream is short enough to follow the products)
+                        if constexpr (RELOAD)
+                            if (q + 1 < nphase) load_tile(Tb + (int64_t)line_of(q + 1) * tstride + toff[p], pre[p]);
                     }
                     double* y = &yw[wv][i * TS];
                     row_group_reduce(d, c);
@@ -567,8 +570,8 @@ __global__ void __launch_bounds__(64 * NWV) k_sweep(SweepArgs A) {
         }
         __syncthreads();
         if (!ctl) {
-            // the fast form has already reloaded its tile slots for the next line
-            if (q + 1 < nphase) prefetch(q + 1, !FAST);
+            // (with RELOAD the tile slots have already been reloaded for the next line)
+            if (q + 1 < nphase) prefetch(q + 1, !RELOAD);
         } else {
             // finish and publish this rank's rows; keep them; prefetch w
             const uint64_t tag = (uint64_t)tag_of(grp, q) << 32;
