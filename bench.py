@@ -154,8 +154,8 @@ def main():
                     help="only run a plain 256 MiB -> 256 MiB copy kernel (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
-                                   "(the sharded design is described in DESIGN.md)"}))
+        print(json.dumps({"error": "the solver runs on one GPU: --gpus must be 1 "
+                                   "(sharding subdomains over GPUs is designed, not built)"}))
         sys.exit(2)
 
     import numpy as np
