@@ -610,10 +610,17 @@ __global__ void __launch_bounds__(F2_THREADS) k_factor2(FactorArgs A) {
                 win_rows(r0, dn, wr0, nr);
                 win_rows(c0, dn, wc0, nc);
                 const double* S = dn ? Sdn : Sup;
+                // every lane loads, with indices clamped into the window (which
+                // lies inside the mp x mp inverse: wr0, wc0 <= the block's first
+                // row, wr0 + nr, wc0 + nc <= m); the entries outside the window
+                // are zeroed where the window is stored.  Branch-free loads whose
+                // values are not touched before that keep the compiler's wait
+                // counts exact, so the next item's loads stay in flight.
+                const int imax = max(nr - 1, 0), jmax = max(nc - 1, 0);
 #pragma unroll
                 for (int u = 0; u < NWL; ++u) {
                     const int e = lane + 64 * u, i = e / WN, j = e % WN;
-                    w[u] = (i < nr && j < nc) ? xload(S + (int64_t)(wr0 + i) * mp + wc0 + j) : 0.0;
+                    w[u] = xload(S + (int64_t)(wr0 + min(i, imax)) * mp + wc0 + min(j, jmax));
                 }
             };
             d4 v = {0.0, 0.0, 0.0, 0.0};
@@ -635,8 +642,8 @@ __global__ void __launch_bounds__(F2_THREADS) k_factor2(FactorArgs A) {
                 if (nterm == 1 || dn == 0) a_init(r0, c0);         // first term of the block
 #pragma unroll
                 for (int u = 0; u < NWL; ++u) {
-                    const int e = lane + 64 * u;
-                    if (e < WN * WN) win[e] = w[u];
+                    const int e = lane + 64 * u, i = e / WN, j = e % WN;
+                    if (e < WN * WN) win[e] = (i < nr && j < nc) ? w[u] : 0.0;
                 }
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -706,13 +713,18 @@ __global__ void __launch_bounds__(F2_THREADS) k_factor2(FactorArgs A) {
                     for (int q = 0; q < 4; ++q) bscr[(b * 4 + q) * 64 + lane] = v[q];
                 }
             } else {
+                // the next item's window is in flight while an item is
+                // processed; issues are unconditional (an index past the last
+                // item reloads its window, unused) so that the only waits are
+                // for the window about to be stored
                 double wa[NWL], wb[NWL];
-                if (nitem > 0) issue(0, wa);
+                auto iss = [&](int it, double (&w)[NWL]) { issue(min(it, nitem - 1), w); };
+                if (nitem > 0) iss(0, wa);
 #pragma unroll 1
                 for (int it = 0; it < nitem; it += 2) {
-                    if (it + 1 < nitem) issue(it + 1, wb);
+                    iss(it + 1, wb);
                     process(it, wa);
-                    if (it + 2 < nitem) issue(it + 2, wa);
+                    iss(it + 2, wa);
                     if (it + 1 < nitem) process(it + 1, wb);
                 }
             }
