@@ -189,6 +189,13 @@ int sf_residual(sf_context* ctx, const double* U, double* r, double* rnorm2);
 /* eta_K of sf_update_alpha without changing alpha; eta [B][H-1][W-1][2].   */
 int sf_indicator(sf_context* ctx, const double* U, double* eta);
 
+/* Host-only: device memory (bytes) that sf_create would allocate for cfg
+ * (factors, workspace and field arrays, not counting allocation rounding or
+ * the small graph-replay buffers); *bytes is HOST.  It grows linearly with
+ * cfg->batch, so a driver can split many pairs into waves that fit the
+ * device (a batch of tens of full-HD pairs needs several times its HBM).   */
+int sf_memory_bytes(const sf_config* cfg, int64_t* bytes);
+
 /* Host-only geometry plan (no device needed): returns the number of
  * subdomains of `cfg` (or a negative error) and, if geom != NULL, fills
  * geom[10*i .. 10*i+9] (HOST) with pair, box x0, x1, y0, y1, owned x0, x1,

@@ -73,6 +73,7 @@ _SIGS = {
     "sf_residual": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "sf_indicator": (c_int32, [c_void_p, c_void_p, c_void_p]),
     "sf_plan": (c_int32, [ctypes.POINTER(sf_config), c_void_p]),
+    "sf_memory_bytes": (c_int32, [ctypes.POINTER(sf_config), ctypes.POINTER(ctypes.c_int64)]),
     "sf_num_subdomains": (c_int32, [c_void_p]),
     "sf_subdomain_geometry": (c_int32, [c_void_p, c_int32, c_void_p]),
     "sf_subdomain_solve": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p]),
@@ -301,6 +302,15 @@ def sf_plan(width, height, batch=1, parts_x=1, parts_y=1, overlap=0, lam=1.0):
     return [_geom(list(g[10 * i:10 * i + 10])) for i in range(n)]
 
 
+def sf_memory_bytes(width, height, batch=1, parts_x=1, parts_y=1, overlap=0, lam=1.0, sigma=0.0,
+                    factor_precision=SF_FP64) -> int:
+    """Host-only: device bytes a context of this configuration allocates."""
+    cfg = make_config(width, height, batch, parts_x, parts_y, overlap, lam, sigma, factor_precision)
+    out = ctypes.c_int64()
+    _check(lib().sf_memory_bytes(ctypes.byref(cfg), ctypes.byref(out)), "sf_memory_bytes")
+    return out.value
+
+
 def _geom(g):
     out = dict(pair=g[0], box=(g[1], g[2], g[3], g[4]), own=(g[5], g[6], g[7], g[8]), cols=bool(g[9]))
     if len(g) > 10:
@@ -381,6 +391,41 @@ def run_pipeline(ctx: Context, I0, I1, alpha, U, rtol=1e-8, max_sweeps=1000, pas
         if it < passes:
             etas.append(sf_update_alpha(ctx, U, alpha, kappa, eta_thr, alpha_th))
     return PipelineResult(sweeps, rels, etas, status)
+
+
+def run_pipeline_waves(I0, I1, alpha, U, parts_x, parts_y, overlap, lam=1.0, budget_bytes=None, band_tile=0,
+                       factor_precision=SF_FP64, **pipeline_kw):
+    """:func:`run_pipeline` over N pairs (I0, I1 [N,H,W], alpha [N,H-1,W-1,2]
+    updated in place, U [N,3,H,W] written) in waves of as many pairs as a
+    context can hold within ``budget_bytes`` of device memory (default: 90%
+    of the free memory).  One context serves all full waves and one more the
+    last, smaller wave.  Returns (wave size, [PipelineResult per wave])."""
+    import torch
+    N, H, W = I0.shape
+    if budget_bytes is None:
+        budget_bytes = int(0.9 * torch.cuda.mem_get_info(I0.device)[0])
+
+    def need(b):
+        return sf_memory_bytes(W, H, b, parts_x, parts_y, overlap, lam, 0.0, factor_precision)
+
+    per_pair = need(2) - need(1)
+    wave = min(N, max(0, (budget_bytes - (need(1) - per_pair)) // per_pair))
+    if wave < 1:
+        raise SfError(SF_ERR_OOM, f"run_pipeline_waves: one pair needs {need(1)} bytes, budget {budget_bytes}")
+    results, ctxs = [], {}
+    try:
+        for s0 in range(0, N, wave):
+            s1 = min(N, s0 + wave)
+            b = s1 - s0
+            if b not in ctxs:
+                ctxs[b] = sf_create(W, H, b, parts_x, parts_y, overlap, lam=lam, band_tile=band_tile,
+                                    factor_precision=factor_precision)
+            U[s0:s1].zero_()
+            results.append(run_pipeline(ctxs[b], I0[s0:s1], I1[s0:s1], alpha[s0:s1], U[s0:s1], **pipeline_kw))
+    finally:
+        for c in ctxs.values():
+            c.close()
+    return wave, results
 
 
 # ---- autograd ----------------------------------------------------------------

@@ -204,6 +204,43 @@ void sf_destroy(sf_context* c) {
 
 // Sweep workgroups per chain (P, clamped to the line matrices' block rows and
 // to co-residency) and the launch shape that follows; host side only.
+// Storage offsets of every subdomain (factors and workspace, in doubles);
+// host only.  The totals are the two large device arrays of a context.
+static void storage_offsets(std::vector<SubDesc>& subs, int precision, int64_t* factor_doubles,
+                            int64_t* work_doubles) {
+    int64_t foff = 0, woff = 0;
+    for (auto& d : subs) {
+        d.foff = foff;
+        // tiles in doubles, or in floats packed two per double
+        foff += (int64_t)d.nt * d.ntiles * sfdd::TSZ / (precision == SF_FP32 ? 2 : 1);
+        d.boff = foff;
+        foff += (int64_t)d.nt * d.m * 6;
+        d.aoff = foff;
+        foff += (int64_t)d.nt * d.ms * 18;
+        d.woff = woff;
+        woff += (int64_t)d.nt * d.mp;
+        d.poff = woff;
+        woff += (int64_t)12 * d.mp;
+        d.soff = woff;   // factor workspace (one-WG factor: 3 mp^2; cooperative: two chains)
+        woff += std::max<int64_t>((int64_t)3 * d.mp * d.mp, 2 * sfdd::f2_chain_doubles(d.mp, d.NT));
+    }
+    *factor_doubles = foff;
+    *work_doubles = woff;
+}
+
+// Device bytes of the field arrays of a context (everything but factors and
+// workspace), matching the allocations of sf_create.
+static int64_t field_bytes(const sf_config& k, int64_t nsub) {
+    const int64_t nn = (int64_t)k.width * k.height, ne = (int64_t)(k.width - 1) * (k.height - 1) * 2;
+    const int64_t B = k.batch, npart = (nn + 255) / 256;
+    int64_t d = 2 * nn * B + 2 * ne * B + 6 * nn * B;          // f0, ft, alpha, eta, F, r
+    d += 2 * B + npart * B + B;                                  // Fn2, Gn2, partials, relres
+    int64_t bytes = d * 8 + (int64_t)sizeof(SubDesc) * nsub;
+    bytes += 4 * (2 * B) + 8 * B + 4 * (2 * sfdd::F2_COUNTERS * nsub) + 16 + sizeof(sfdd::DevStatus);
+    if (k.sigma > 0.0) bytes += 8 * (2 * (int64_t)std::ceil(3.0 * k.sigma) + 1);   // blur weights
+    return bytes;
+}
+
 static void set_sweep_shape(sf_context* c, int P) {
     int min_nt = 1 << 30, maxnt = 0;
     for (const auto& d : c->subs) {
@@ -302,25 +339,8 @@ int sf_create(const sf_config* cfg, void* stream, sf_context** out) {
     set_sweep_shape(c, P);
 
     // ---- storage offsets -----------------------------------------------------
-    int64_t foff = 0, woff = 0;
-    for (auto& d : c->subs) {
-        d.kmid = G == 2 ? (d.nt - 1) / 2 : d.nt - 1;
-        d.foff = foff;
-        // tiles in doubles, or in floats packed two per double
-        foff += (int64_t)d.nt * d.ntiles * sfdd::TSZ / (k.factor_precision == SF_FP32 ? 2 : 1);
-        d.boff = foff;
-        foff += (int64_t)d.nt * d.m * 6;
-        d.aoff = foff;
-        foff += (int64_t)d.nt * d.ms * 18;
-        d.woff = woff;
-        woff += (int64_t)d.nt * d.mp;
-        d.poff = woff;
-        woff += (int64_t)12 * d.mp;
-        d.soff = woff;   // factor workspace (one-WG factor: 3 mp^2; cooperative: two chains)
-        woff += std::max<int64_t>((int64_t)3 * d.mp * d.mp, 2 * sfdd::f2_chain_doubles(d.mp, d.NT));
-    }
-    c->factor_doubles = foff;
-    c->work_doubles = woff;
+    for (auto& d : c->subs) d.kmid = G == 2 ? (d.nt - 1) / 2 : d.nt - 1;
+    storage_offsets(c->subs, k.factor_precision, &c->factor_doubles, &c->work_doubles);
 
     const int64_t nn = (int64_t)c->W * c->H, ne = (int64_t)(c->W - 1) * (c->H - 1) * 2;
     c->npart = (int)((nn + 255) / 256);
@@ -776,6 +796,19 @@ int sf_profile(sf_context* c, int32_t enable, double* ms, int64_t* launches) {
             c->prof_n[i] = 0;
         }
     }
+    return SF_OK;
+}
+
+int sf_memory_bytes(const sf_config* cfg, int64_t* bytes) {
+    if (!cfg || !bytes) return SF_ERR_INVALID;
+    SF_TRY(check_config(*cfg));
+    std::vector<SubDesc> subs = plan_subdomains(*cfg);
+    int maxmp = 0;
+    for (const auto& d : subs) maxmp = std::max(maxmp, d.mp);
+    if (maxmp > 512) return SF_ERR_INVALID;
+    int64_t fd = 0, wd = 0;
+    storage_offsets(subs, cfg->factor_precision, &fd, &wd);
+    *bytes = 8 * (fd + wd) + field_bytes(*cfg, (int64_t)subs.size());
     return SF_OK;
 }
 

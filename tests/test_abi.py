@@ -93,3 +93,30 @@ def test_sigma_bounds():
     assert api.lib().sf_plan(cfg_ok, None) == 4
     assert api.lib().sf_plan(cfg_bad, None) == api.SF_ERR_INVALID
     assert api.lib().sf_plan(api.make_config(32, 32, 1, 2, 2, 4, sigma=-1.0), None) == api.SF_ERR_INVALID
+
+
+@pytest.mark.parametrize("W,H,px,py,d", [(64, 64, 2, 2, 4), (640, 480, 4, 4, 8), (1920, 1080, 12, 7, 8)])
+def test_memory_bytes_linear_in_batch_and_tile_storage(W, H, px, py, d):
+    _ensure_built()
+    b1, b2, b5 = (api.sf_memory_bytes(W, H, b, px, py, d) for b in (1, 2, 5))
+    # every pair repeats the same subdomains and fields: exactly affine in the batch
+    assert b5 - b1 == 4 * (b2 - b1) and b2 > b1 > 0
+    # FP32 tiles halve exactly the inverse Schur tiles: per subdomain, lines x
+    # lower tiles of the padded line matrix (32x32 tiles), from the geometry alone
+    tile_bytes = 0
+    for g in api.sf_plan(W, H, 1, px, py, d):
+        x0, x1, y0, y1 = g["box"]
+        ms, nt = (y1 - y0, x1 - x0) if g["cols"] else (x1 - x0, y1 - y0)
+        NT = -(-3 * ms // 32)
+        tile_bytes += nt * NT * (NT + 1) // 2 * 32 * 32 * 8
+    f32 = api.sf_memory_bytes(W, H, 1, px, py, d, factor_precision=api.SF_FP32)
+    assert b1 - f32 == tile_bytes // 2
+    assert b1 > tile_bytes
+
+
+def test_memory_bytes_invalid():
+    _ensure_built()
+    with pytest.raises(api.SfError):
+        api.sf_memory_bytes(0, 10)
+    with pytest.raises(api.SfError):
+        api.sf_memory_bytes(180, 171)          # lines of 171 nodes: above the largest line matrix
