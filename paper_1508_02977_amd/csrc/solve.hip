@@ -189,11 +189,13 @@ __device__ __forceinline__ int own_row(int i, int rank, int P) {
 // matrix and the right-hand side terms; the last wave ("control wave") does
 // the latency-critical traffic: it gathers the rows the phase needs, finishes
 // and publishes this rank's rows.  Global loads of a wave complete in order,
-// so keeping the tile prefetch (issued by the tile waves right after their
-// compute, one phase ahead) off the control wave lets the next phase's data
-// stream in while the control wave synchronises.  All addressing is set up in
-// registers; nothing inside the phase loop loads an address from memory (such
-// a load would drain the prefetch queue).
+// so keeping the tile loads of the next line (issued by the tile waves one
+// phase ahead) off the control wave keeps its polls short.  With FP64 tiles
+// each slot is reloaded right after its products, so the stream runs under
+// the compute and is mostly done when the control wave polls; with FP32 tiles
+// (half the bytes) the loads follow the products.  All addressing is set up
+// in registers; nothing inside the phase loop loads an address from memory
+// (such a load would drain the load queue).
 // Workgroup g is dispatched to XCD g % 8; the ranks of subdomain i are the
 // workgroups g with g % 8 == i % 8, so the tiles that two ranks of one
 // subdomain both read are shared through one L2.  Correctness does not depend
@@ -434,6 +436,7 @@ __global__ void __launch_bounds__(64 * NWV) k_sweep(SweepArgs A) {
     // Phase structure (B = workgroup barrier):
     //   control wave: [gather(q)] B z B  .  B [finish, publish(q)]
     //   tile waves:              B z B [compute(q)] B [prefetch(q+1)]
+    //   (FP64 tiles: the tiles of q+1 are loaded inside compute(q), slot by slot)
     // Rows are exchanged as tagged 64-bit words (32-bit tag, 32-bit half of a
     // double): a reader polls the words it needs until both halves carry the
     // tag of the wanted phase, so one memory round trip both synchronises and
