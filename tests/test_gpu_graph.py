@@ -4,8 +4,9 @@ The replayed chunk holds the same kernels in the same order as the ordinary
 loop, so the iterate, the sweep counts and the residuals must equal those of
 sf_schwarz_solve bit for bit: on small and ragged geometries, a batch with a
 pair that has nothing to solve, a max_sweeps that leaves a partial chunk,
-solves repeated with other work on the device in between, and the timed
-640x480 workload.  One case is also held to the oracle's iterate.
+solves repeated with other work on the device in between, the FP32-tile
+sweep form, and the timed 640x480 workload.  One case is also held to the
+oracle's iterate.
 """
 import numpy as np
 import pytest
@@ -127,5 +128,17 @@ def test_graph_full_size_workload(gpu):
     api.sf_assemble(ctx, dev(p.I0[None]), dev(p.I1[None]), dev(synth.constant_alpha(W, H)[None]))
     api.sf_factor_subdomains(ctx)
     (Ue, re), (Ug, rg) = both(ctx, 1e-8, 2000)
+    assert re[0] == api.SF_OK and rg == re and torch.equal(Ug, Ue)
+    ctx.close()
+
+
+def test_graph_solve_with_fp32_tiles_equals_ordinary_solve(gpu):
+    # the FP32-tile sweep is another kernel form: replayed it must also match
+    W, H, px, py, d = 72, 56, 3, 3, 8
+    p = synth.make_pair("plain640", 3, W=W, H=H)
+    ctx = api.sf_create(W, H, 1, px, py, d, factor_precision=api.SF_FP32)
+    api.sf_assemble(ctx, dev(p.I0[None]), dev(p.I1[None]), dev(synth.random_alpha(W, H, 3)[None]))
+    api.sf_factor_subdomains(ctx)
+    (Ue, re), (Ug, rg) = both(ctx, 1e-9, 500)
     assert re[0] == api.SF_OK and rg == re and torch.equal(Ug, Ue)
     ctx.close()
