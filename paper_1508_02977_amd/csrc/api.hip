@@ -185,6 +185,20 @@ const char* sf_status_string(int s) {
     }
 }
 
+// The graph path's stream, events and device counters (all or none exist).
+static void release_graph_resources(sf_context* c) {
+    if (c->gk_d) (void)hipFree(c->gk_d);
+    if (c->gepoch_d) (void)hipFree(c->gepoch_d);
+    for (hipEvent_t& e : c->gev) {
+        if (e) (void)hipEventDestroy(e);
+        e = nullptr;
+    }
+    if (c->gstream) (void)hipStreamDestroy(c->gstream);
+    c->gk_d = nullptr;
+    c->gepoch_d = nullptr;
+    c->gstream = nullptr;
+}
+
 void sf_destroy(sf_context* c) {
     if (!c) return;
     void* ptrs[] = {c->d_subs, c->f0, c->ft, c->alpha, c->F, c->r, c->eta, c->Fn2, c->Gn2,
@@ -194,11 +208,7 @@ void sf_destroy(sf_context* c) {
         if (p) (void)hipFree(p);
     if (c->host_stage) (void)hipHostFree(c->host_stage);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
-    if (c->gk_d) (void)hipFree(c->gk_d);
-    if (c->gepoch_d) (void)hipFree(c->gepoch_d);
-    for (hipEvent_t e : c->gev)
-        if (e) (void)hipEventDestroy(e);
-    if (c->gstream) (void)hipStreamDestroy(c->gstream);
+    release_graph_resources(c);
     delete c;
 }
 
@@ -599,18 +609,25 @@ int sf_schwarz_solve_graph(sf_context* c, double* U, double rtol, int32_t max_sw
     if (!c || !U || max_sweeps < 0 || !(rtol >= 0.0)) return SF_ERR_INVALID;
     if (c->state != ST_FACTORED) return SF_ERR_STATE;
     if (!c->gstream) {
+        // created together on first use; a failure leaves none of them, so a
+        // later call never runs with a missing counter
+        int rc = SF_OK;
         if (hipStreamCreateWithFlags(&c->gstream, hipStreamNonBlocking) != hipSuccess) {
             c->gstream = nullptr;
-            return SF_ERR_HIP;
+            rc = SF_ERR_HIP;
         }
         for (hipEvent_t& e : c->gev)
-            if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+            if (rc == SF_OK && hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
                 e = nullptr;
-                return SF_ERR_HIP;
+                rc = SF_ERR_HIP;
             }
-        int rc = dalloc(&c->gk_d, 1);
-        rc |= dalloc(&c->gepoch_d, 1);
-        if (rc != SF_OK) return SF_ERR_OOM;
+        if (rc == SF_OK) rc = dalloc(&c->gk_d, 1);
+        if (rc == SF_OK) rc = dalloc(&c->gepoch_d, 1);
+        if (rc != SF_OK) {
+            (void)hipGetLastError();
+            release_graph_resources(c);
+            return rc;
+        }
     }
     SF_TRY(loop_prologue(c, U, c->Fn2));
     // the private stream continues after the work queued on the context's stream
