@@ -701,7 +701,11 @@ int sf_autotune(sf_context* c, double* U, int32_t trials, int32_t* band_tile) {
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     set_sweep_shape(c, rc == SF_OK ? best : keep);
-    if (hipMemcpy(c->d_subs, c->subs.data(), c->subs.size() * sizeof(SubDesc), hipMemcpyHostToDevice) != hipSuccess)
+    // on the context's stream, after any sweep still queued there (an early
+    // break leaves some), so no sweep reads the descriptors while they change
+    if (hipMemcpyAsync(c->d_subs, c->subs.data(), c->subs.size() * sizeof(SubDesc), hipMemcpyHostToDevice,
+                       c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess)
         return SF_ERR_HIP;
     if (band_tile) *band_tile = c->maxP;
     return rc;
