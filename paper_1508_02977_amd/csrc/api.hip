@@ -393,20 +393,23 @@ int sf_create(const sf_config* cfg, void* stream, sf_context** out) {
         sf_destroy(c);
         return SF_ERR_OOM;
     }
-    if (hipMemcpy(c->d_subs, c->subs.data(), c->subs.size() * sizeof(SubDesc), hipMemcpyHostToDevice) !=
-        hipSuccess) {
+    // uploads and clears go on the context's stream, so the synchronisation
+    // below covers them also when that stream does not wait for the null stream
+    if (hipMemcpyAsync(c->d_subs, c->subs.data(), c->subs.size() * sizeof(SubDesc), hipMemcpyHostToDevice,
+                       c->stream) != hipSuccess) {
         sf_destroy(c);
         return SF_ERR_HIP;
     }
     // sweep exchange buffers start with tag 0, which no launch ever waits for
-    if (hipMemset(c->work, 0, (size_t)c->work_doubles * sizeof(double)) != hipSuccess) {
+    if (hipMemsetAsync(c->work, 0, (size_t)c->work_doubles * sizeof(double), c->stream) != hipSuccess) {
         sf_destroy(c);
         return SF_ERR_HIP;
     }
     c->sweep_epoch = 1;
     c->factor_epoch = 1;
     if (!bw.empty() &&
-        hipMemcpy(c->blur_w, bw.data(), bw.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
+        hipMemcpyAsync(c->blur_w, bw.data(), bw.size() * sizeof(double), hipMemcpyHostToDevice, c->stream) !=
+            hipSuccess) {
         sf_destroy(c);
         return SF_ERR_HIP;
     }
