@@ -20,14 +20,15 @@ def dev(a):
     return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
 
 
-def test_memory_estimate_covers_the_allocation(gpu):
+@pytest.mark.parametrize("precision", [api.SF_FP64, api.SF_FP32])
+def test_memory_estimate_covers_the_allocation(gpu, precision):
     W, H, px, py, d = 640, 480, 4, 4, 8
-    est = api.sf_memory_bytes(W, H, 1, px, py, d)
+    est = api.sf_memory_bytes(W, H, 1, px, py, d, factor_precision=precision)
     # a first context takes the runtime's one-time costs (code objects, queues)
-    first = api.sf_create(W, H, 1, px, py, d)
+    first = api.sf_create(W, H, 1, px, py, d, factor_precision=precision)
     torch.cuda.synchronize()
     free0 = torch.cuda.mem_get_info()[0]
-    ctx = api.sf_create(W, H, 1, px, py, d)
+    ctx = api.sf_create(W, H, 1, px, py, d, factor_precision=precision)
     torch.cuda.synchronize()
     used = free0 - torch.cuda.mem_get_info()[0]
     ctx.close()
