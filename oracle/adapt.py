@@ -29,10 +29,12 @@ Readings (binding for the oracle and the library alike):
 * ||eta||_inf is the maximum over all elements of the frame pair; if it is 0,
   alpha is left unchanged.
 
-The element residual is pinned against the moment-formula expansion in the
-tests; the
-adapted alpha values themselves have no printed reference ("parity unpinned"
-beyond the invariants the tests check).
+The element residual is pinned against the moment-formula expansion and, with
+its weights h_K, |grad f| and alpha_K^{-1/2}, against closed forms on linear
+frames (constant shift with zero, constant-flow and constant-illumination
+fields, where the flux jumps vanish); the jump term against closed forms of
+linear flows and alpha interfaces.  The adapted alpha values on textured pairs
+have no printed reference ("parity unpinned" beyond those invariants).
 """
 from __future__ import annotations
 

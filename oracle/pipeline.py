@@ -6,6 +6,10 @@ The adaptive loop of Section 2.3 on the fixed pixel mesh (no remeshing):
 solve, compute eta, decrease alpha, reassemble with the new alpha, refactor,
 solve again warm-started from the previous iterate; ``passes`` alpha updates
 give ``passes + 1`` solves.
+
+Pinned by: no passes = one RAS solve; with kappa = 0 the warm start continues
+the same iteration; with exact (1x1 split) solves the final iterate solves the
+system reassembled with the twice-updated alpha.
 """
 from __future__ import annotations
 

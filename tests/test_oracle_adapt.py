@@ -134,3 +134,69 @@ def test_metrics_closed_forms():
     assert metrics.aae(u, ue) == pytest.approx(60.0)
     assert metrics.ee(u, ue) == pytest.approx(np.sqrt(2.0))
     assert metrics.aae(ue, ue) == pytest.approx(0.0, abs=1e-6)
+
+
+# ---- closed forms of the element-residual term (Section 2.3, eq. (errind)) ----
+# These fix every factor of alpha_K^{-1/2} h_K ||R_K||_{L2(K)}: with a linear
+# first frame every element has the same gradient g = (p, q), and with a flow
+# field whose gradient vanishes there is no flux jump, so eta_K is the residual
+# term alone.  The vertices of the two triangles of cell (x, y) are written out
+# here from the mesh definition (T0: (x,y), (x+1,y), (x+1,y+1); T1: (x,y),
+# (x+1,y+1), (x,y+1)), and int_K v^2 of a linear v with vertex values v_i is
+# |K|/6 (sum v_i^2 + sum_{i<j} v_i v_j).
+
+def _linear_frames(W, H, a, p, q, c):
+    X, Y = np.meshgrid(np.arange(W, dtype=np.float64), np.arange(H, dtype=np.float64))
+    I0 = a + p * X + q * Y
+    return I0, I0 + c
+
+
+def _tri_vertex_values(v):
+    """Vertex values [H-1, W-1, 2, 3] of a nodal field v [H, W] on T0 / T1."""
+    v00, v10, v11, v01 = v[:-1, :-1], v[:-1, 1:], v[1:, 1:], v[1:, :-1]
+    t0 = np.stack([v00, v10, v11], axis=-1)
+    t1 = np.stack([v00, v11, v01], axis=-1)
+    return np.stack([t0, t1], axis=2)
+
+
+def test_residual_term_closed_form_shift_no_flow():
+    # U = 0: s = 0, f_t = c on every node, int_K f_t^2 = c^2 / 2, so
+    # eta_K = sqrt(2) sqrt(p^2 + q^2) (c^2 / 2)^{1/2} / sqrt(alpha_K)
+    #       = |c| sqrt(p^2 + q^2) / sqrt(alpha_K).
+    W, H = 9, 7
+    p, q, c = 0.031, -0.017, 0.2
+    I0, I1 = _linear_frames(W, H, 0.4, p, q, c)
+    al = synth.random_alpha(W, H, 11)
+    eta = adapt.indicator(I0, I1, al, 1.0, np.zeros(3 * W * H))
+    expect = abs(c) * np.hypot(p, q) / np.sqrt(al)
+    assert np.allclose(eta, expect, rtol=1e-12, atol=0.0)
+
+
+def test_residual_term_closed_form_constant_flow():
+    # U = (u, v, 0) constant: s + f_t = p u + q v + c on every node.
+    W, H = 8, 6
+    p, q, c, u, v = 0.05, 0.02, -0.03, 0.7, -0.4
+    I0, I1 = _linear_frames(W, H, 0.3, p, q, c)
+    al = synth.random_alpha(W, H, 12)
+    U = np.zeros((H, W, 3))
+    U[:, :, 0], U[:, :, 1] = u, v
+    eta = adapt.indicator(I0, I1, al, 1.0, U.ravel())
+    expect = abs(p * u + q * v + c) * np.hypot(p, q) / np.sqrt(al)
+    assert np.allclose(eta, expect, rtol=1e-12, atol=0.0)
+
+
+def test_residual_term_closed_form_illumination_only():
+    # U = (0, 0, mu): s + f_t = c - mu f is linear on K with vertex values
+    # c - mu f_i, so ||R_K||^2 = |g|^2 |K|/6 (sum v_i^2 + sum_{i<j} v_i v_j).
+    W, H = 8, 7
+    p, q, c, mu = 0.04, -0.03, 0.05, 0.3
+    I0, I1 = _linear_frames(W, H, 0.6, p, q, c)
+    al = synth.random_alpha(W, H, 13)
+    U = np.zeros((H, W, 3))
+    U[:, :, 2] = mu
+    eta = adapt.indicator(I0, I1, al, 1.0, U.ravel())
+    vv = _tri_vertex_values(c - mu * I0)                      # [H-1, W-1, 2, 3]
+    pair_sum = vv[..., 0] * vv[..., 1] + vv[..., 0] * vv[..., 2] + vv[..., 1] * vv[..., 2]
+    int_v2 = 0.5 / 6.0 * (np.sum(vv * vv, axis=-1) + pair_sum)
+    expect = np.sqrt(2.0) * np.hypot(p, q) * np.sqrt(int_v2) / np.sqrt(al)
+    assert np.allclose(eta, expect, rtol=1e-12, atol=0.0)

@@ -3,7 +3,7 @@ import numpy as np
 import pytest
 import scipy.sparse as sp
 
-from oracle import fem, schwarz
+from oracle import adapt, fem, schwarz
 from paper_1508_02977_amd import synth
 
 
@@ -145,3 +145,59 @@ def test_subdomain_matrices_spd_even_if_global_singular():
     for s in schwarz.decompose(W, H, 2, 2, 4):
         evs = np.linalg.eigvalsh(schwarz.local_matrix(A, s).toarray())
         assert evs.min() > 0.0
+
+
+# ---- the adaptive driver (Section 2.3 loop): pins of pipeline.solve_pair -----
+
+def test_solve_pair_without_passes_is_one_ras_solve():
+    from oracle import pipeline
+    W, H = 14, 12
+    p = synth.make_pair("plain64", 21, W=W, H=H, noise=0.01)
+    al = synth.random_alpha(W, H, 5)
+    res = pipeline.solve_pair(p.I0, p.I1, al, 1.0, 2, 2, 2, rtol=1e-9, max_sweeps=500)
+    A, F = fem.assemble(p.I0, p.I1, al, 1.0)
+    facs = schwarz.factor_subdomains(A, schwarz.decompose(W, H, 2, 2, 2))
+    ref = schwarz.ras_solve(A, F, facs, rtol=1e-9, max_sweeps=500)
+    assert res.sweeps == [ref.sweeps] and np.array_equal(res.U, ref.U)
+    assert np.array_equal(res.alpha, al) and res.eta_max == []
+
+
+def test_solve_pair_warm_start_continues_the_iteration():
+    # kappa = 0 leaves alpha unchanged, so the reassembled system is the same
+    # and the warm-started second solve continues the first one's iteration:
+    # 3 + 4 sweeps equal 7 sweeps of one solve, bit for bit.
+    from oracle import pipeline
+    W, H = 13, 11
+    p = synth.make_pair("plain64", 22, W=W, H=H, noise=0.01)
+    al = synth.random_alpha(W, H, 6)
+    res = pipeline.solve_pair(p.I0, p.I1, al, 1.0, 2, 2, 3, rtol=0.0, max_sweeps=0, passes=1,
+                              kappa=0.0, sweeps_per_solve=[3, 4])
+    A, F = fem.assemble(p.I0, p.I1, al, 1.0)
+    facs = schwarz.factor_subdomains(A, schwarz.decompose(W, H, 2, 2, 3))
+    ref = schwarz.ras_solve(A, F, facs, rtol=0.0, max_sweeps=7)
+    assert np.array_equal(res.U, ref.U) and np.array_equal(res.alpha, al)
+
+
+def test_solve_pair_reassembles_with_the_updated_alpha():
+    # A 1x1 split solves exactly in one sweep, so with one sweep per solve each
+    # solve returns the solution of the system assembled with the current
+    # alpha: after two updates U solves A(alpha_2) U = F, and alpha_2 is the
+    # decrease rule applied to the indicators of the two earlier exact solutions.
+    from oracle import pipeline
+    W, H = 10, 9
+    p = synth.make_pair("plain64", 23, W=W, H=H, noise=0.01)
+    al0 = synth.constant_alpha(W, H, 0.1)
+    kw = dict(kappa=1.0, eta_thr=0.1, alpha_th=1e-3)
+    res = pipeline.solve_pair(p.I0, p.I1, al0, 1.0, 1, 1, 0, rtol=0.0, max_sweeps=1, passes=2, **kw)
+    al = al0
+    for _ in range(2):
+        A, F = fem.assemble(p.I0, p.I1, al, 1.0)
+        U = schwarz.dense_solve(A, F)
+        eta = adapt.indicator(p.I0, p.I1, al, 1.0, U)
+        al, _ = adapt.update_alpha(al, eta, kw["kappa"], kw["eta_thr"], kw["alpha_th"])
+    A2, F2 = fem.assemble(p.I0, p.I1, al, 1.0)
+    U2 = schwarz.dense_solve(A2, F2)
+    assert not np.allclose(al, al0)
+    assert np.allclose(res.alpha, al, rtol=1e-10, atol=0.0)
+    assert np.linalg.norm(res.U - U2) <= 1e-10 * np.linalg.norm(U2)
+    assert res.sweeps == [1, 1, 1]
