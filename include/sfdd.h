@@ -178,6 +178,11 @@ int sf_error_detail(const sf_context* ctx, int32_t* pair, int32_t* subdomain, in
 /* Static text for a status code. */
 const char* sf_status_string(int status);
 
+/* Static text: SHA-256 (hex) of the sources the library was built from (the
+ * names and bytes of csrc/ and include/ files, sorted), so that a caller can
+ * refuse a library built from other sources than it expects.               */
+const char* sf_build_digest(void);
+
 /* ---- diagnostics (same math, exposed for verification) ------------------ */
 
 /* Copy F [B][3][H][W] (valid after sf_assemble) into `F`.                   */

@@ -79,6 +79,7 @@ _SIGS = {
     "sf_subdomain_solve": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p]),
     "sf_profile": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p]),
     "sf_choose_split": (c_int32, [c_int32, c_int32, c_int32, c_void_p, c_void_p, c_void_p]),
+    "sf_build_digest": (ctypes.c_char_p, []),
 }
 
 _lib = None
@@ -96,7 +97,14 @@ def lib() -> ctypes.CDLL:
             fn = getattr(L, name)
             fn.restype = res
             fn.argtypes = args
+        from . import build
+        built, now = L.sf_build_digest().decode(), build.source_digest()
+        if built != now:
+            raise ImportError(f"{LIB_PATH} was built from other sources than the tree holds (library {built[:12]}, "
+                              f"sources {now[:12]}); rebuild with `python -m paper_1508_02977_amd.build`")
         _lib = L
+        import atexit
+        atexit.register(_close_all)
     return _lib
 
 
@@ -131,6 +139,21 @@ def _check(code: int, where: str, ctx=None, allow=()):
     if ctx is not None and code in (SF_NOT_SPD, SF_ERR_DEVICE):
         detail = sf_error_detail(ctx)
     raise SfError(code, where, detail)
+
+
+_LIVE = []   # weak references to open contexts, closed at interpreter exit
+
+
+def _close_all():
+    """Destroy every context still open, while the HIP runtime is alive."""
+    for ref in list(_LIVE):
+        c = ref()
+        if c is not None:
+            try:
+                c.close()
+            except Exception:
+                pass
+    _LIVE.clear()
 
 
 @dataclasses.dataclass
@@ -189,7 +212,10 @@ def sf_create(width, height, batch=1, parts_x=1, parts_y=1, overlap=0, lam=1.0, 
         stream = torch.cuda.current_stream()
     h = c_void_p()
     _check(lib().sf_create(ctypes.byref(cfg), c_void_p(stream.cuda_stream), ctypes.byref(h)), "sf_create")
-    return Context(h, cfg)
+    ctx = Context(h, cfg)
+    import weakref
+    _LIVE.append(weakref.ref(ctx))
+    return ctx
 
 
 def sf_destroy(ctx: Context) -> None:

@@ -2,10 +2,14 @@
 
 All sources under ``csrc/`` are compiled by one ``hipcc`` invocation into a
 shared library next to this file; the Python binding loads it from there.
+The library carries a digest of the sources it was built from
+(``sf_build_digest``), and the binding refuses a library whose digest differs
+from that of the sources in the tree.
 """
 from __future__ import annotations
 
 import glob
+import hashlib
 import os
 import shutil
 import subprocess
@@ -32,6 +36,24 @@ FLAGS = [
 ]
 
 
+def sources() -> list[str]:
+    """Every file the library is built from (sorted, repository-relative)."""
+    pats = (os.path.join(HERE, "csrc", "*.hip"), os.path.join(HERE, "csrc", "*.h"),
+            os.path.join(ROOT, "include", "*.h"))
+    return sorted(os.path.relpath(f, ROOT) for pat in pats for f in glob.glob(pat))
+
+
+def source_digest() -> str:
+    """SHA-256 over the names and bytes of :func:`sources`."""
+    h = hashlib.sha256()
+    for rel in sources():
+        h.update(rel.encode() + b"\0")
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+        h.update(b"\0")
+    return h.hexdigest()
+
+
 def hipcc() -> str:
     for cand in (os.environ.get("HIPCC"), "/opt/rocm/bin/hipcc", shutil.which("hipcc")):
         if cand and os.path.exists(cand):
@@ -42,8 +64,8 @@ def hipcc() -> str:
 def build(verbose: bool = False) -> str:
     srcs = sorted(glob.glob(os.path.join(HERE, "csrc", "*.hip")))
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), *FLAGS, "-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc"),
-           "-o", tmp, *srcs]
+    cmd = [hipcc(), *FLAGS, f'-DSFDD_SOURCE_DIGEST="{source_digest()}"', "-I", os.path.join(ROOT, "include"),
+           "-I", os.path.join(HERE, "csrc"), "-o", tmp, *srcs]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)

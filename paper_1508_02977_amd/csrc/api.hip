@@ -168,7 +168,13 @@ int prof_harvest(sf_context* c) {
 
 }  // namespace sfdd
 
+#ifndef SFDD_SOURCE_DIGEST
+#define SFDD_SOURCE_DIGEST "unknown"
+#endif
+
 extern "C" {
+
+const char* sf_build_digest(void) { return SFDD_SOURCE_DIGEST; }
 
 const char* sf_status_string(int s) {
     switch (s) {

@@ -20,35 +20,6 @@
 
 namespace sfdd {
 
-// 3x3 block A[(x,y), (x+dx, y+dy)] of the global matrix, row field c,
-// column field d, for (dx, dy) in {(0,0), (1,0), (0,1), (1,1)}.
-__device__ void stencil_block(const double* __restrict__ f0, const double* __restrict__ al, int W, int H,
-                              int x, int y, int dx, int dy, double lam, double blk[9]) {
-    for (int i = 0; i < 9; ++i) blk[i] = 0.0;
-    double b[9];
-    auto add = [&](int cx, int cy, int t, int i, int j) {
-        if (cx < 0 || cy < 0 || cx >= W - 1 || cy >= H - 1) return;
-        Elem e = load_elem(f0, al, W, H, cx, cy, t);
-        elem_block(e, t, i, j, lam, b);
-        for (int k = 0; k < 9; ++k) blk[k] += b[k];
-    };
-    if (dx == 0 && dy == 0) {
-        for (int k = 0; k < 6; ++k) {
-            const Around a = around(k);
-            add(x + a.dcx, y + a.dcy, a.t, a.v, a.v);
-        }
-    } else if (dx == 1 && dy == 0) {          // edge (x,y)-(x+1,y)
-        add(x, y, 0, 0, 1);
-        add(x, y - 1, 1, 2, 1);
-    } else if (dx == 0 && dy == 1) {          // edge (x,y)-(x,y+1)
-        add(x, y, 1, 0, 2);
-        add(x - 1, y, 0, 1, 2);
-    } else {                                  // diagonal edge (x,y)-(x+1,y+1)
-        add(x, y, 0, 0, 2);
-        add(x, y, 1, 0, 1);
-    }
-}
-
 // Lane-blocked 32x32x32 tile product for one wave:
 //   acc[r][c] += sum_k opA(4br+r, k) * opB(k, 4bc+c),  br = lane/8, bc = lane%8
 // opA(i,k) = TA ? A[k*lda+i] : A[i*lda+k];  opB(k,j) = TB ? B[j*ldb+k] : B[k*ldb+j].

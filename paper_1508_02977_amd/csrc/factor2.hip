@@ -76,33 +76,6 @@ struct FactorArgs {
     uint32_t epoch;           // tag base of this launch (pivot-block and Pi words carry epoch + pivot)
 };
 
-__device__ void f2_stencil_block(const double* __restrict__ f0, const double* __restrict__ al, int W, int H,
-                                 int x, int y, int dx, int dy, double lam, double blk[9]) {
-    for (int i = 0; i < 9; ++i) blk[i] = 0.0;
-    double b[9];
-    auto add = [&](int cx, int cy, int t, int i, int j) {
-        if (cx < 0 || cy < 0 || cx >= W - 1 || cy >= H - 1) return;
-        Elem e = load_elem(f0, al, W, H, cx, cy, t);
-        elem_block(e, t, i, j, lam, b);
-        for (int k = 0; k < 9; ++k) blk[k] += b[k];
-    };
-    if (dx == 0 && dy == 0) {
-        for (int k = 0; k < 6; ++k) {
-            const Around a = around(k);
-            add(x + a.dcx, y + a.dcy, a.t, a.v, a.v);
-        }
-    } else if (dx == 1 && dy == 0) {
-        add(x, y, 0, 0, 1);
-        add(x, y - 1, 1, 2, 1);
-    } else if (dx == 0 && dy == 1) {
-        add(x, y, 1, 0, 2);
-        add(x - 1, y, 0, 1, 2);
-    } else {
-        add(x, y, 0, 0, 2);
-        add(x, y, 1, 0, 1);
-    }
-}
-
 // Line coefficients of every subdomain, computed once before the
 // factorisation: per line t and node s the 3x3 blocks A[(t,s),(t,s)] and
 // A[(t,s),(t,s+1)] (row-major, 18 doubles at aoff + (t*ms + s)*18) and the
@@ -121,11 +94,11 @@ __global__ void k_line_coeffs(const SubDesc* __restrict__ subs, const double* __
     int x, y;
     local_to_global(d, t, s, x, y);
     double blk[9];
-    f2_stencil_block(f0, al, W, H, x, y, 0, 0, lam, blk);
+    stencil_block(f0, al, W, H, x, y, 0, 0, lam, blk);
     for (int k = 0; k < 9; ++k) Ab[k] = blk[k];
     if (s + 1 < d.ms) {
-        if (d.cols) f2_stencil_block(f0, al, W, H, x, y, 0, 1, lam, blk);
-        else        f2_stencil_block(f0, al, W, H, x, y, 1, 0, lam, blk);
+        if (d.cols) stencil_block(f0, al, W, H, x, y, 0, 1, lam, blk);
+        else        stencil_block(f0, al, W, H, x, y, 1, 0, lam, blk);
     } else {
         for (int k = 0; k < 9; ++k) blk[k] = 0.0;
     }
@@ -134,12 +107,12 @@ __global__ void k_line_coeffs(const SubDesc* __restrict__ subs, const double* __
         int px, py;
         local_to_global(d, t - 1, s, px, py);
         double bs[9], bd[9];
-        if (d.cols) f2_stencil_block(f0, al, W, H, px, py, 1, 0, lam, bs);
-        else        f2_stencil_block(f0, al, W, H, px, py, 0, 1, lam, bs);
+        if (d.cols) stencil_block(f0, al, W, H, px, py, 1, 0, lam, bs);
+        else        stencil_block(f0, al, W, H, px, py, 0, 1, lam, bs);
         if (s > 0) {
             int qx, qy;
             local_to_global(d, t - 1, s - 1, qx, qy);
-            f2_stencil_block(f0, al, W, H, qx, qy, 1, 1, lam, bd);
+            stencil_block(f0, al, W, H, qx, qy, 1, 1, lam, bd);
         } else {
             for (int k = 0; k < 9; ++k) bd[k] = 0.0;
         }

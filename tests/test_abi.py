@@ -120,3 +120,12 @@ def test_memory_bytes_invalid():
         api.sf_memory_bytes(0, 10)
     with pytest.raises(api.SfError):
         api.sf_memory_bytes(180, 171)          # lines of 171 nodes: above the largest line matrix
+
+
+def test_library_built_from_the_current_sources():
+    # the binding refuses a library whose embedded source digest differs from
+    # the sources in the tree; the loaded one must match
+    _ensure_built()
+    from paper_1508_02977_amd import build
+    assert api.lib().sf_build_digest().decode() == build.source_digest()
+    assert len(build.sources()) >= 8 and any(s.endswith("sfdd.h") for s in build.sources())

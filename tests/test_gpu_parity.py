@@ -47,6 +47,16 @@ def rel(a, b):
     return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / max(np.linalg.norm(np.ravel(b)), 1e-300))
 
 
+def emax(a, b):
+    """Largest element-wise difference of field planes [..., 3, H, W] (or any
+    array), each field relative to its own largest magnitude."""
+    a, b = np.asarray(a), np.asarray(b)
+    if a.ndim >= 3 and a.shape[-3] == 3:
+        return max(float(np.abs(a[..., c, :, :] - b[..., c, :, :]).max() / max(np.abs(b[..., c, :, :]).max(), 1e-300))
+                   for c in range(3))
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
 def setup(case, alpha=None, band_tile=0, lam=1.0):
     p = synth.make_pair(case["kind"], case["seed"], W=case["W"], H=case["H"])
     W, H = case["W"], case["H"]
@@ -105,9 +115,7 @@ def test_ras_iterates_match_oracle(gpu, name):
     facs = schwarz.factor_subdomains(A, schwarz.decompose(case["W"], case["H"], case["px"], case["py"], case["d"]))
     res = schwarz.ras_solve(A, F, facs, rtol=0.0, max_sweeps=nsw)
     Uo = planes(res.U, case["W"], case["H"])
-    assert rel(host(U)[0], Uo) <= 1e-10
-    for c in range(3):
-        assert rel(host(U)[0, c], Uo[c]) <= 1e-10
+    assert emax(host(U)[0], Uo) <= 1e-10
     assert rr[0] == pytest.approx(res.relres, rel=1e-8)
 
 
@@ -126,7 +134,7 @@ def test_workgroups_per_subdomain_variants(gpu, name, band_tile):
     A, F = fem.assemble(p.I0, p.I1, al, 1.0)
     facs = schwarz.factor_subdomains(A, schwarz.decompose(case["W"], case["H"], case["px"], case["py"], case["d"]))
     res = schwarz.ras_solve(A, F, facs, rtol=0.0, max_sweeps=12)
-    assert rel(host(U)[0], planes(res.U, case["W"], case["H"])) <= 1e-10
+    assert emax(host(U)[0], planes(res.U, case["W"], case["H"])) <= 1e-10
 
 
 def test_solve_to_tolerance_and_determinism(gpu):
@@ -144,7 +152,7 @@ def test_solve_to_tolerance_and_determinism(gpu):
     res = schwarz.ras_solve(A, F, facs, rtol=1e-8, max_sweeps=500)
     assert abs(res.sweeps - sw[0]) <= 1
     res = schwarz.ras_solve(A, F, facs, rtol=0.0, max_sweeps=sw[0])
-    assert rel(host(U)[0], planes(res.U, case["W"], case["H"])) <= 1e-10
+    assert emax(host(U)[0], planes(res.U, case["W"], case["H"])) <= 1e-10
     # the oracle's own residual of the GPU iterate
     Ug = interleave(host(U)[0])
     assert np.linalg.norm(F - A @ Ug) / np.linalg.norm(F) <= 1.0000001e-8
@@ -202,8 +210,8 @@ def test_adaptive_pipeline_matches_oracle(gpu):
     counts = [s[0] for s in res.sweeps]
     ores = pipeline.solve_pair(p.I0, p.I1, al0, 1.0, case["px"], case["py"], case["d"], 0.0, 0, passes=2,
                                sweeps_per_solve=counts)
-    assert rel(host(Al)[0], ores.alpha) <= 1e-10
-    assert rel(host(U)[0], planes(ores.U, W, H)) <= 1e-10
+    assert emax(host(Al)[0], ores.alpha) <= 1e-10
+    assert emax(host(U)[0], planes(ores.U, W, H)) <= 1e-10
     assert all(r <= 1e-8 for r in (rr[0] for rr in res.relres))
 
 

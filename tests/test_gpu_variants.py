@@ -48,10 +48,11 @@ def test_presmoothed_rhs_iterates_and_indicator(gpu, case):
     facs = schwarz.factor_subdomains(A, schwarz.decompose(W, H, case["px"], case["py"], case["d"]))
     Uo = schwarz.ras_solve(A, F, facs, rtol=0.0, max_sweeps=20).U
     Ug = np.ascontiguousarray(U[0].cpu().numpy().transpose(1, 2, 0)).reshape(-1)
-    assert rel(Ug, Uo) <= 1e-10
+    d = np.abs(Ug - Uo).reshape(-1, 3).max(axis=0) / np.abs(Uo).reshape(-1, 3).max(axis=0)
+    assert d.max() <= 1e-10                      # per field, element by element
     # indicator on the smoothed frames
     eta = torch.empty((1, H - 1, W - 1, 2), dtype=torch.float64, device="cuda")
     api.sf_indicator(ctx, U, eta)
     eo = adapt.indicator(f0, f1, al, 1.0, Ug)
-    assert rel(eta[0].cpu().numpy(), eo) <= 1e-10
+    assert np.abs(eta[0].cpu().numpy() - eo).max() <= 1e-10 * eo.max()
     ctx.close()
