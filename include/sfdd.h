@@ -191,6 +191,19 @@ int sf_rhs(sf_context* ctx, double* F);
 /* r = F - A U for U [B][3][H][W]; rnorm2 [B] HOST (||r||^2) or NULL.       */
 int sf_residual(sf_context* ctx, const double* U, double* r, double* rnorm2);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * r = F - A U and ||r||^2 as sf_residual (same kernels, equal bit for bit),
+ * with the block partials and norms held in a static device array of the
+ * library (SF_NOALLOC_SCRATCH_BYTES per device, kept until the process
+ * ends) instead of context storage; the call allocates nothing.  The array
+ * holds B * ceil(W H / 256) + B doubles of this context; larger contexts get
+ * SF_ERR_INVALID.  rnorm2 [B] is HOST or NULL (NULL: no synchronisation).
+ * All contexts on one device share the array: calls that overlap on one
+ * device (other threads or streams) race.                                  */
+#define SF_NOALLOC_SCRATCH_BYTES (1 << 20)
+int sf_residual_noalloc(sf_context* ctx, const double* U, double* r, double* rnorm2);
+
 /* eta_K of sf_update_alpha without changing alpha; eta [B][H-1][W-1][2].   */
 int sf_indicator(sf_context* ctx, const double* U, double* eta);
 

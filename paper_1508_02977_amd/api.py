@@ -30,6 +30,7 @@ SF_NONFINITE = 3
 SF_FP64 = 0
 SF_FP32 = 1
 SF_SIGMA_MAX = 16.0
+SF_NOALLOC_SCRATCH_BYTES = 1 << 20
 
 c_int32 = ctypes.c_int32
 c_double = ctypes.c_double
@@ -71,6 +72,7 @@ _SIGS = {
     "sf_status_string": (ctypes.c_char_p, [c_int32]),
     "sf_rhs": (c_int32, [c_void_p, c_void_p]),
     "sf_residual": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
+    "sf_residual_noalloc": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "sf_indicator": (c_int32, [c_void_p, c_void_p, c_void_p]),
     "sf_plan": (c_int32, [ctypes.POINTER(sf_config), c_void_p]),
     "sf_memory_bytes": (c_int32, [ctypes.POINTER(sf_config), ctypes.POINTER(ctypes.c_int64)]),
@@ -311,6 +313,16 @@ def sf_residual(ctx: Context, U, r):
     _check(lib().sf_residual(ctx.handle, _dev(U, ctx.field_shape(), "U"), _dev(r, ctx.field_shape(), "r"),
                              ctypes.cast(n2, c_void_p)), "sf_residual")
     return list(n2)
+
+
+def sf_residual_noalloc(ctx: Context, U, r, norms=True):
+    """As :func:`sf_residual`, with the reduction scratch in the library's
+    static device array (the call allocates nothing); ``norms=False`` passes
+    NULL (no synchronisation) and returns None."""
+    n2 = (c_double * ctx.B)()
+    _check(lib().sf_residual_noalloc(ctx.handle, _dev(U, ctx.field_shape(), "U"), _dev(r, ctx.field_shape(), "r"),
+                                     ctypes.cast(n2, c_void_p) if norms else c_void_p()), "sf_residual_noalloc")
+    return list(n2) if norms else None
 
 
 def sf_indicator(ctx: Context, U, eta) -> None:

@@ -291,6 +291,12 @@ int sf_create(const sf_config* cfg, void* stream, sf_context** out) {
     c->H = k.height;
     c->B = k.batch;
     if (hipGetDevice(&c->device) != hipSuccess) { sf_destroy(c); return SF_ERR_HIP; }
+    // the allocation-free entry point's static array: its address on this
+    // device (looked up once per device, with the device current)
+    {
+        const int rc = sfdd::scratch_resolve(c->device, &c->scratch);
+        if (rc != SF_OK) { sf_destroy(c); return rc; }
+    }
 
     // ---- geometry (Section 3.1) --------------------------------------------
     c->subs = plan_subdomains(k);
@@ -773,6 +779,23 @@ int sf_residual(sf_context* c, const double* U, double* r, double* rnorm2) {
     if (rnorm2) {
         double* h = (double*)stage_a(c);
         SF_HIP(hipMemcpyAsync(h, c->relres_d, c->B * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        SF_HIP(hipStreamSynchronize(c->stream));
+        for (int b = 0; b < c->B; ++b) rnorm2[b] = h[b];
+    }
+    return SF_OK;
+}
+
+int sf_residual_noalloc(sf_context* c, const double* U, double* r, double* rnorm2) {
+    if (!c || !U || !r) return SF_ERR_INVALID;
+    if (c->state < ST_ASSEMBLED) return SF_ERR_STATE;
+    if (!c->scratch) return SF_ERR_STATE;
+    if (sfdd::scratch_residual_doubles(c) * (int64_t)sizeof(double) > (int64_t)SF_NOALLOC_SCRATCH_BYTES)
+        return SF_ERR_INVALID;   // B * ceil(W H / 256) + B doubles exceed the static array
+    SF_TRY(sfdd::launch_residual_scratch(c, U, r, c->scratch));
+    if (rnorm2) {
+        double* h = (double*)stage_a(c);
+        SF_HIP(hipMemcpyAsync(h, c->scratch + (int64_t)c->B * c->npart, c->B * sizeof(double),
+                              hipMemcpyDeviceToHost, c->stream));
         SF_HIP(hipStreamSynchronize(c->stream));
         for (int b = 0; b < c->B; ++b) rnorm2[b] = h[b];
     }

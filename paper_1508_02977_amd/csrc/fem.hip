@@ -3,6 +3,7 @@
 // per element); every reduction is a fixed-order two-stage sum, so results
 // are bitwise reproducible run to run.
 #include <cmath>
+#include <mutex>
 
 #include "element.h"
 #include "sfdd_internal.h"
@@ -534,6 +535,59 @@ int launch_residual(sf_context* c, const double* U, double* r, int fuse_converge
         hipLaunchKernelGGL(k_finalize_norm, dim3(c->B), dim3(64), 0, c->stream, c->partials, c->npart,
                            c->relres_d);
     }
+    SF_LAUNCH_CHECK();
+    return SF_OK;
+}
+
+// ---- allocation-free residual (sf_residual_noalloc) ------------------------
+//
+// The block partials and the per-pair norms of the residual live in one
+// file-scope device array instead of the context's arrays.  Every context on
+// a device shares that device's copy, which keeps the last call's contents;
+// nothing in it needs clearing (every block writes its partial, the finish
+// kernel every norm).  Calls that overlap on one device race.
+static __device__ __align__(256) double scratch[SF_NOALLOC_SCRATCH_BYTES / sizeof(double)];
+
+namespace {
+constexpr int SCRATCH_MAX_DEVICES = 64;
+std::mutex scratch_mu;
+double* scratch_addr[SCRATCH_MAX_DEVICES] = {};
+}  // namespace
+
+// Device address of `scratch` on `device` (which must be current), looked up
+// once per device.  The array's name in host code is a host-side stand-in,
+// not a device address, so kernels and copies take this pointer.
+int scratch_resolve(int device, double** out) {
+    *out = nullptr;
+    if (device < 0 || device >= SCRATCH_MAX_DEVICES) return SF_ERR_INVALID;
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_addr[device]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return SF_ERR_HIP;
+        }
+        scratch_addr[device] = (double*)p;
+    }
+    *out = scratch_addr[device];
+    return SF_OK;
+}
+
+// Doubles of scratch the residual of a context needs: B blocks' partials of
+// npart blocks each, then the B norms.
+int64_t scratch_residual_doubles(const sf_context* c) { return (int64_t)c->B * c->npart + c->B; }
+
+// r = F - A U with ||r||^2 per pair at scr + B npart; the same kernels, launch
+// shape and reduction order as launch_residual, so r and the norms are equal
+// bit for bit.
+int launch_residual_scratch(sf_context* c, const double* U, double* r, double* scr) {
+    const int64_t nn = (int64_t)c->W * c->H;
+    dim3 grid((unsigned)((nn + NODE_THREADS - 1) / NODE_THREADS), c->B);
+    hipLaunchKernelGGL(k_residual, grid, dim3(NODE_THREADS), 0, c->stream, c->f0, c->alpha, c->F, U, r, scr,
+                       c->npart, c->W, c->H, c->cfg.lambda, (const int32_t*)nullptr);
+    SF_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_finalize_norm, dim3(c->B), dim3(64), 0, c->stream, scr, c->npart,
+                       scr + (int64_t)c->B * c->npart);
     SF_LAUNCH_CHECK();
     return SF_OK;
 }

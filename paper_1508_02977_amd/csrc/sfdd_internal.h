@@ -92,6 +92,8 @@ struct sf_context {
     sfdd::DevStatus status_h;       // last error detail
     // host staging (pinned)
     void *host_stage;
+    // device address of the allocation-free entry point's static scratch array
+    double *scratch;
     // graph-replayed Schwarz loop (sf_schwarz_solve_graph): a private stream,
     // and the iteration index and sweep tag base kept on the device so that a
     // replayed graph reads fresh values
@@ -121,6 +123,9 @@ int launch_zero_where_rhs_zero(sf_context* c, double* U, const double* rhs_n2);
 int launch_adjoint_gradients(sf_context* c, const double* U, const double* P, double* dI0, double* dI1,
                              double* dal);
 int launch_indicator(sf_context* c, const double* U, double* eta, int reset_max);
+int scratch_resolve(int device, double** out);
+int64_t scratch_residual_doubles(const sf_context* c);
+int launch_residual_scratch(sf_context* c, const double* U, double* r, double* scr);
 int launch_alpha_update(sf_context* c, const double* eta, double* alpha_out, double kappa,
                         double eta_thr, double alpha_th);
 int launch_factor(sf_context* c);
