@@ -122,13 +122,21 @@ def indicator(I0, I1, alpha, lam, U) -> np.ndarray:
     I0 = np.asarray(I0, dtype=np.float64)
     H, W = I0.shape
     ed = fem.element_data(I0, I1, W, H)
-    tri, xy, G, g = (ed[k] for k in ("tri", "xy", "G", "g"))
+    tri, g = ed["tri"], ed["g"]
     Uv = np.asarray(U, dtype=np.float64).reshape(-1, 3)[tri]     # [E, 3 vertices, 3 fields]
     al = np.asarray(alpha, dtype=np.float64).reshape(-1)
     quad = _residual_integral(ed, Uv)
     diam = np.sqrt(2.0)
     res_norm = np.sqrt(np.sum(g * g, axis=1) * quad)
-    eta = diam * res_norm / np.sqrt(al)
+    eta = diam * res_norm / np.sqrt(al) + jump_terms(ed, Uv, al)
+    return eta.reshape(H - 1, W - 1, 2)
+
+
+def jump_terms(ed: dict, Uv: np.ndarray, al: np.ndarray) -> np.ndarray:
+    """The edge part of eta_K: 1/2 sum_e alpha_e^{-1/2} h_e^{1/2} ||J_e||_{L2(e)},
+    J_e the jump of alpha grad u_c . n_e, c = 1, 2 (flattened element order)."""
+    tri, xy, G = ed["tri"], ed["xy"], ed["G"]
+    eta = np.zeros(tri.shape[0])
     # flux jumps of alpha grad u_c, c = 1, 2
     grad_u = np.einsum("eik,eic->eck", G, Uv[:, :, :2])          # [E, 2 fields, 2]
     flux = al[:, None, None] * grad_u
@@ -142,7 +150,7 @@ def indicator(I0, I1, alpha, lam, U) -> np.ndarray:
         a_e = al.copy()
         a_e[inner] = np.maximum(al[inner], al[nb[inner]])
         eta += 0.5 * length[:, k] * np.linalg.norm(jump, axis=1) / np.sqrt(a_e)
-    return eta.reshape(H - 1, W - 1, 2)
+    return eta
 
 
 def update_alpha(alpha, eta, kappa: float, eta_thr: float, alpha_th: float):

@@ -157,6 +157,12 @@ def assemble(I0: np.ndarray, I1: np.ndarray, alpha: np.ndarray, lam: float):
     H, W = I0.shape
     ed = element_data(I0, I1, W, H)
     Ae, Fe = element_matrices(ed, alpha, lam)
+    return assemble_elements(ed, Ae, Fe, W, H)
+
+
+def assemble_elements(ed: dict, Ae: np.ndarray, Fe: np.ndarray, W: int, H: int):
+    """Global CSR matrix and right-hand side from the local 9x9 matrices and
+    9-vectors of every element (symmetric blocks mirrored)."""
     Ae = 0.5 * (Ae + Ae.transpose(0, 2, 1))
     gidx = (3 * ed["tri"][:, :, None] + np.arange(3)[None, None, :]).reshape(-1, 9)
     rows = np.repeat(gidx, 9, axis=1).ravel()
