@@ -26,6 +26,8 @@ illumination"):
                  area/perimeter choice of the image split (Section 3.1).
 * ``adjoint``  - gradients of a loss of the solution with respect to the
                  frames and alpha by the adjoint of the discrete system.
+* ``clg``      - the data term smoothed by K_rho (functionals (BW) and (BW2)
+                 with rho > 0) and its error indicator.
 
 Functions whose result the paper does not fix by any printed value or closed
 form are marked "parity unpinned" in their docstrings.

@@ -446,10 +446,17 @@ def run_pipeline_waves(I0, I1, alpha, U, parts_x, parts_y, overlap, lam=1.0, bud
     def need(b):
         return sf_memory_bytes(W, H, b, parts_x, parts_y, overlap, lam, 0.0, factor_precision)
 
-    per_pair = need(2) - need(1)
-    wave = min(N, max(0, (budget_bytes - (need(1) - per_pair)) // per_pair))
-    if wave < 1:
+    # the largest batch that fits (need grows with the batch: bisection)
+    if need(1) > budget_bytes:
         raise SfError(SF_ERR_OOM, f"run_pipeline_waves: one pair needs {need(1)} bytes, budget {budget_bytes}")
+    lo, hi = 1, N
+    while lo < hi:
+        mid = (lo + hi + 1) // 2
+        if need(mid) <= budget_bytes:
+            lo = mid
+        else:
+            hi = mid - 1
+    wave = lo
     results, ctxs = [], {}
     try:
         for s0 in range(0, N, wave):

@@ -12,6 +12,7 @@ using sfdd::SubDesc;
 namespace {
 
 constexpr int ST_CREATED = 0, ST_ASSEMBLED = 1, ST_FACTORED = 2;
+constexpr int MAX_LINE = 768;        // largest padded line matrix (3 x the shorter box side, rounded up to 32)
 
 template <class T>
 int dalloc(T** p, size_t count) {
@@ -224,7 +225,7 @@ void sf_destroy(sf_context* c) {
 // host only.  The totals are the two large device arrays of a context.
 static void storage_offsets(std::vector<SubDesc>& subs, int precision, int64_t* factor_doubles,
                             int64_t* work_doubles) {
-    int64_t foff = 0, woff = 0;
+    int64_t foff = 0, woff = 0, ws = 0;
     for (auto& d : subs) {
         d.foff = foff;
         // tiles in doubles, or in floats packed two per double
@@ -237,9 +238,15 @@ static void storage_offsets(std::vector<SubDesc>& subs, int precision, int64_t* 
         woff += (int64_t)d.nt * d.mp;
         d.poff = woff;
         woff += (int64_t)12 * d.mp;
-        d.soff = woff;   // factor workspace (one-WG factor: 3 mp^2; cooperative: two chains)
-        woff += std::max<int64_t>((int64_t)3 * d.mp * d.mp, 2 * sfdd::f2_chain_doubles(d.mp, d.NT));
+        // factor workspace (one-workgroup factor: 3 mp^2; cooperative: two chains)
+        ws = std::max<int64_t>(ws, std::max<int64_t>((int64_t)3 * d.mp * d.mp, 2 * sfdd::f2_chain_doubles(d.mp, d.NT)));
     }
+    // The factor runs in chunks of at most FACTOR_WS_SLOTS consecutive
+    // subdomains, one chunk after another on the stream, so subdomain i uses
+    // workspace slot i mod FACTOR_WS_SLOTS (distinct within any chunk).
+    const int nslot = std::min<int>((int)subs.size(), sfdd::FACTOR_WS_SLOTS);
+    for (size_t i = 0; i < subs.size(); ++i) subs[i].soff = woff + (int64_t)(i % sfdd::FACTOR_WS_SLOTS) * ws;
+    woff += (int64_t)nslot * ws;
     *factor_doubles = foff;
     *work_doubles = woff;
 }
@@ -257,17 +264,31 @@ static int64_t field_bytes(const sf_config& k, int64_t nsub) {
     return bytes;
 }
 
+// Lanes and chunk of a launch whose subdomains need `per` co-resident
+// workgroups each: 8 lanes (a subdomain's workgroups g all have g % 8 equal,
+// so they run on one XCD) when 8 subdomains fit, else the largest power of
+// two that fits; chunk = the most subdomains, a multiple of the lanes, that
+// fit (0 if one does not), at most `cap_chunk` and no more than needed.
+static void chunk_shape(int capacity, int per, int nsub, int cap_chunk, int* lanes, int* chunk) {
+    int L = 8;
+    while (L > 1 && (int64_t)L * per > capacity) L /= 2;
+    *lanes = L;
+    if (per < 1 || per > capacity) { *chunk = 0; return; }
+    const int ch = std::min(L * (capacity / (L * per)), L * (cap_chunk / L));
+    *chunk = std::min(ch, L * ((nsub + L - 1) / L));
+}
+
+// Sweep workgroups per chain P and the launch shape that follows (chunks of
+// subdomains whose G P ranks each fit co-resident); host side only.
 static void set_sweep_shape(sf_context* c, int P) {
-    int min_nt = 1 << 30, maxnt = 0;
-    for (const auto& d : c->subs) {
-        min_nt = std::min(min_nt, d.NT);
-        maxnt = std::max(maxnt, d.NT);
-    }
-    const int nsx = (c->nsub + 7) / 8, G = c->groups;
-    P = std::min(std::min(P, min_nt), 255);
-    if ((int64_t)P * 8 * nsx * G > c->sweep_capacity) P = std::max(1, c->sweep_capacity / (8 * nsx * G));
+    int maxnt = 0;
+    for (const auto& d : c->subs) maxnt = std::max(maxnt, d.NT);
+    const int G = c->groups;
+    // ranks beyond a subdomain's block rows have nothing to do
+    P = std::max(1, std::min(std::min(P, maxnt), 255));
+    if (G * P > c->sweep_capacity) P = std::max(1, c->sweep_capacity / G);
     c->maxP = P;
-    c->sweep_grid = 8 * nsx * G * P;
+    chunk_shape(c->sweep_capacity, G * P, c->nsub, 1 << 30, &c->sweep_lanes, &c->sweep_chunk);
     c->sweep_rows = 0;
     for (int r = 0; r < P; ++r) {
         int R = 0;
@@ -300,63 +321,71 @@ int sf_create(const sf_config* cfg, void* stream, sf_context** out) {
 
     // ---- geometry (Section 3.1) --------------------------------------------
     c->subs = plan_subdomains(k);
-    int maxmp = 0, min_nt = 1 << 30;
+    int maxmp = 0, maxnt = 0;
     for (const auto& d : c->subs) {
         maxmp = std::max(maxmp, d.mp);
-        min_nt = std::min(min_nt, d.NT);
+        maxnt = std::max(maxnt, d.NT);
     }
-    if (maxmp > 512) { sf_destroy(c); return SF_ERR_INVALID; }   // line matrices up to 512 x 512
+    if (maxmp > MAX_LINE) { sf_destroy(c); return SF_ERR_INVALID; }   // line matrices up to 768 x 768
     c->nsub = (int)c->subs.size();
 
     // ---- launch shapes ---------------------------------------------------------
-    int ncu = 0, occ = 0, occ_b = 0;
+    int ncu = 0;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess) {
         sf_destroy(c);
         return SF_ERR_HIP;
     }
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, sfdd::sweep_kernel(), sfdd::sweep_threads(0), 0) !=
-            hipSuccess || occ < 1)
-        occ = 1;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ_b, sfdd::sweep_kernel_small(), sfdd::sweep_threads(1), 0) ==
-            hipSuccess && occ_b >= 1)
-        occ = std::min(occ, occ_b);
+    // co-resident sweep workgroups: the least of the forms this precision uses
+    int occ = 1 << 30;
+    const int fp32 = k.factor_precision == SF_FP32;
+    for (int form : {sfdd::SWEEP_GENERAL, sfdd::SWEEP_FAST2, sfdd::SWEEP_FAST1}) {
+        int o = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, sfdd::sweep_kernel(form, fp32), sfdd::sweep_threads(form),
+                                                         0) != hipSuccess || o < 1)
+            o = 1;
+        occ = std::min(occ, o);
+    }
     const int capacity = ncu * occ;
-    // workgroup slots: 8 XCD lanes x ceil(nsub / 8) subdomains per lane x groups x P ranks
-    const int nsx = (c->nsub + 7) / 8;
+    c->sweep_capacity = capacity;
 
-    // cooperative factor: ceil(NT/2) workgroups per chain, line matrices up to
-    // 384; two chains (twisted factorisation) when both chains of every
-    // subdomain fit co-resident in the sweep and 8 subdomains in the factor
-    int maxnt = 0;
-    for (const auto& d : c->subs) maxnt = std::max(maxnt, d.NT);
+    // cooperative factor: f2_ranks(NT) workgroups and a pivot server per
+    // chain, line matrices up to 768; two chains per subdomain (twisted
+    // factorisation) when 8 subdomains fit one launch with both chains in the
+    // factor and with the fast sweep's ranks, else one chain
     int occ2 = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ2, sfdd::factor2_kernel(), sfdd::F2_WAVES * 64, 0) !=
         hipSuccess)
         occ2 = 0;
-    const int Pf = (maxnt + 1) / 2;
+    const int fcap = ncu * occ2;
+    int Pf = 0;
+    for (const auto& d : c->subs) Pf = std::max(Pf, sfdd::f2_ranks(d.NT));
+    const int Pfast = maxnt <= 14 ? (maxnt + 1) / 2 : maxnt;   // fast sweep: 2 block rows per rank, or 1
     c->groups = 1;
-    // (Pf ranks and one pivot server per chain)
-    if (maxnt <= 12 && occ2 >= 1 && 8 * (Pf + 1) <= ncu * occ2) {
+    if (maxnt <= sfdd::F2_MAX_NT && occ2 >= 1 && Pf + 1 <= fcap) {
         c->factor_pf = Pf;
-        if (16 * (Pf + 1) <= ncu * occ2 && 16 * nsx <= capacity) c->groups = 2;
-        // subdomains per launch: a multiple of 8 whose slots fit co-resident
-        c->factor_chunk = 8 * ((ncu * occ2) / (8 * c->groups * (Pf + 1)));
+        if (8 * 2 * (Pf + 1) <= fcap && 8 * 2 * Pfast <= capacity) c->groups = 2;
+        chunk_shape(fcap, c->groups * (Pf + 1), c->nsub, sfdd::FACTOR_WS_SLOTS, &c->factor_lanes, &c->factor_chunk);
     } else {
+        // one workgroup per subdomain (line matrices up to 512)
+        if (maxmp > 512) { sf_destroy(c); return SF_ERR_INVALID; }
         c->factor_pf = 0;
-        c->factor_chunk = 0;
+        c->factor_lanes = 1;
+        c->factor_chunk = std::min(c->nsub, sfdd::FACTOR_WS_SLOTS);
     }
     const int G = c->groups;
 
-    // sweep workgroups per chain: at most one per 32-row block row of the line
-    // matrices, and the fewest that give the largest per-rank share
-    c->sweep_capacity = capacity;
+    // sweep workgroups per chain: the most with which every subdomain fits one
+    // launch, balanced over the block rows, while that keeps a fast form;
+    // otherwise the fast forms' count, in chunks of subdomains
     int P;
     if (k.band_tile > 0) {
         P = k.band_tile;
     } else {
-        P = std::max(1, std::min(capacity / (8 * nsx * G), min_nt));
-        const int rows = (min_nt + P - 1) / P;
-        P = (min_nt + rows - 1) / rows;
+        const int nsx = (c->nsub + 7) / 8;
+        P = std::max(1, std::min(capacity / (8 * nsx * G), maxnt));
+        const int rows = (maxnt + P - 1) / P;
+        if (rows > 2 || (rows == 2 && maxnt > 14)) P = Pfast;
+        else P = (maxnt + rows - 1) / rows;
     }
     set_sweep_shape(c, P);
 
@@ -439,13 +468,16 @@ int sf_create(const sf_config* cfg, void* stream, sf_context** out) {
 int sf_assemble(sf_context* c, const double* I0, const double* I1, const double* alpha) {
     if (!c || !I0 || !I1 || !alpha) return SF_ERR_INVALID;
     c->state = ST_CREATED;
+    SF_TRY(sfdd::prof_begin(c, sfdd::PROF_OTHER));
     SF_TRY(fill_i32(c, c->flags_d, 4, 0));
     SF_TRY(sfdd::launch_validate(c, I0, I1, alpha));
     int32_t* hf = (int32_t*)((char*)c->host_stage + STAGE_FLAGS);
     SF_HIP(hipMemcpyAsync(hf, c->flags_d, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
     SF_HIP(hipStreamSynchronize(c->stream));
-    if (hf[0]) return SF_NONFINITE;
-    if (hf[1]) return SF_ERR_INVALID;
+    if (hf[0] || hf[1]) {
+        SF_TRY(sfdd::prof_end(c));
+        return hf[0] ? SF_NONFINITE : SF_ERR_INVALID;
+    }
     if (c->blur_r > 0) {
         // smoothed frames in the residual array (free until the first solve)
         const int64_t n = (int64_t)c->W * c->H * c->B;
@@ -458,6 +490,7 @@ int sf_assemble(sf_context* c, const double* I0, const double* I1, const double*
     } else {
         SF_TRY(sfdd::launch_assemble(c, I0, I1, alpha));
     }
+    SF_TRY(sfdd::prof_end(c));
     c->state = ST_ASSEMBLED;
     return SF_OK;
 }
@@ -496,11 +529,12 @@ int sf_factor_subdomains(sf_context* c) {
 // ||rhs - A U|| <= rtol ||rhs|| (rhs_n2 = ||rhs||^2 on the device).
 // Prologue: pairs with rhs = 0 get U = 0; all pairs active; status cleared.
 static int loop_prologue(sf_context* c, double* U, const double* rhs_n2) {
+    SF_TRY(sfdd::prof_begin(c, sfdd::PROF_OTHER));
     SF_TRY(sfdd::launch_zero_where_rhs_zero(c, U, rhs_n2));
     SF_TRY(fill_i32(c, c->done_d, c->B, 0));
     hipLaunchKernelGGL(k_zero_status_api, dim3(1), dim3(1), 0, c->stream, c->status_d);
     SF_HIP(hipGetLastError());
-    return SF_OK;
+    return sfdd::prof_end(c);
 }
 
 // Iterations k0 .. max_sweeps, one launch each (residual + convergence test,
@@ -670,13 +704,13 @@ int sf_schwarz_solve(sf_context* c, double* U, double rtol, int32_t max_sweeps, 
 int sf_autotune(sf_context* c, double* U, int32_t trials, int32_t* band_tile) {
     if (!c || !U || trials < 1) return SF_ERR_INVALID;
     if (c->state != ST_FACTORED) return SF_ERR_STATE;
-    int min_nt = 1 << 30;
-    for (const auto& d : c->subs) min_nt = std::min(min_nt, d.NT);
+    int maxnt = 0;
+    for (const auto& d : c->subs) maxnt = std::max(maxnt, d.NT);
     // candidates: for every number of block rows per workgroup, the fewest
     // workgroups per chain that give it
     std::vector<int> cand;
-    for (int rows = 1; rows <= min_nt; ++rows) {
-        const int P = (min_nt + rows - 1) / rows;
+    for (int rows = 1; rows <= maxnt; ++rows) {
+        const int P = (maxnt + rows - 1) / rows;
         if (cand.empty() || cand.back() != P) cand.push_back(P);
     }
     hipLaunchKernelGGL(k_zero_status_api, dim3(1), dim3(1), 0, c->stream, c->status_d);
@@ -734,8 +768,11 @@ int sf_adjoint(sf_context* c, const double* U, const double* G, double* P, doubl
     SF_TRY(sfdd::launch_norm2(c, G, c->Gn2));
     const int rc = schwarz_loop(c, P, G, c->Gn2, rtol, max_sweeps, sweeps, relres);
     if (rc != SF_OK && rc != SF_NOT_CONVERGED) return rc;
+    SF_TRY(sfdd::prof_begin(c, sfdd::PROF_OTHER));
     SF_TRY(sfdd::launch_adjoint_gradients(c, U, P, dI0, dI1, dalpha));
+    SF_TRY(sfdd::prof_end(c));
     SF_HIP(hipStreamSynchronize(c->stream));
+    SF_TRY(sfdd::prof_harvest(c));
     return rc;
 }
 
@@ -743,8 +780,10 @@ int sf_update_alpha(sf_context* c, const double* U, double* alpha, double kappa,
                     double* eta_max) {
     if (!c || !U || !alpha || !(kappa >= 0.0) || !std::isfinite(eta_thr) || !(alpha_th > 0.0)) return SF_ERR_INVALID;
     if (c->state < ST_ASSEMBLED) return SF_ERR_STATE;
+    SF_TRY(sfdd::prof_begin(c, sfdd::PROF_OTHER));
     SF_TRY(sfdd::launch_indicator(c, U, c->eta, 1));
     SF_TRY(sfdd::launch_alpha_update(c, c->eta, alpha, kappa, eta_thr, alpha_th));
+    SF_TRY(sfdd::prof_end(c));
     c->state = ST_ASSEMBLED;   // factors are stale, F is unchanged
     if (eta_max) {
         uint64_t* hb = (uint64_t*)stage_a(c);
@@ -858,7 +897,7 @@ int sf_memory_bytes(const sf_config* cfg, int64_t* bytes) {
     std::vector<SubDesc> subs = plan_subdomains(*cfg);
     int maxmp = 0;
     for (const auto& d : subs) maxmp = std::max(maxmp, d.mp);
-    if (maxmp > 512) return SF_ERR_INVALID;
+    if (maxmp > MAX_LINE) return SF_ERR_INVALID;
     int64_t fd = 0, wd = 0;
     storage_offsets(subs, cfg->factor_precision, &fd, &wd);
     *bytes = 8 * (fd + wd) + field_bytes(*cfg, (int64_t)subs.size());

@@ -15,6 +15,8 @@
 // per-subdomain workspace (L2-resident at the sizes used here).
 #include <cmath>
 
+#include <algorithm>
+
 #include "element.h"
 #include "sfdd_internal.h"
 
@@ -90,8 +92,8 @@ __device__ void set_status(DevStatus* st, int code, int sub, int64_t row) {
 __global__ void __launch_bounds__(FACTOR_THREADS)
 k_factor(const SubDesc* __restrict__ subs, const double* __restrict__ f0_all, const double* __restrict__ al_all,
          double* __restrict__ factors, double* __restrict__ work, DevStatus* __restrict__ status,
-         int W, int H, double lam, int fp32) {
-    const int sub = blockIdx.x;
+         int W, int H, double lam, int fp32, int sub0) {
+    const int sub = sub0 + blockIdx.x;
     const SubDesc d = subs[sub];
     const int tid = threadIdx.x, wv = tid >> 6, nw = FACTOR_THREADS / 64;
     const int m = d.m, mp = d.mp, NT = d.NT, ms = d.ms;
@@ -316,10 +318,14 @@ __global__ void k_zero_status(DevStatus* st) {
 int launch_factor(sf_context* c) {
     hipLaunchKernelGGL(k_zero_status, dim3(1), dim3(1), 0, c->stream, c->status_d);
     if (hipGetLastError() != hipSuccess) return SF_ERR_HIP;
-    hipLaunchKernelGGL(k_factor, dim3(c->nsub), dim3(FACTOR_THREADS), 0, c->stream, c->d_subs, c->f0, c->alpha,
-                       c->factors, c->work, c->status_d, c->W, c->H, c->cfg.lambda,
-                       c->cfg.factor_precision == SF_FP32 ? 1 : 0);
-    if (hipGetLastError() != hipSuccess) return SF_ERR_HIP;
+    // chunks of subdomains that share the factor workspace slots, in order
+    for (int s0 = 0; s0 < c->nsub; s0 += c->factor_chunk) {
+        const int n = std::min(c->factor_chunk, c->nsub - s0);
+        hipLaunchKernelGGL(k_factor, dim3(n), dim3(FACTOR_THREADS), 0, c->stream, c->d_subs, c->f0, c->alpha,
+                           c->factors, c->work, c->status_d, c->W, c->H, c->cfg.lambda,
+                           c->cfg.factor_precision == SF_FP32 ? 1 : 0, s0);
+        if (hipGetLastError() != hipSuccess) return SF_ERR_HIP;
+    }
     return SF_OK;
 }
 

@@ -39,29 +39,63 @@ namespace sfdd {
 
 constexpr int F2_THREADS = 256;      // one wave per SIMD: 512 registers per wave
 constexpr int F2_NW = F2_THREADS / 64;
-constexpr int F2_MAXNT = 12;          // line matrices up to 384 x 384
+constexpr int F2_MAXNT = 24;          // line matrices up to 768 x 768
 constexpr int LDP = 34;               // LDS row pitch (doubles): conflict-free 16x4 / 4x16 fragments
 constexpr int LTILE = TS * LDP;       // doubles per LDS tile
+// LDS tiles of the exchange column a rank keeps: every block column when one
+// rank owns a row pair (NT <= 12); with split pairs the columns of the rank's
+// parity (at most 12) and its two rows (slots 12, 13)
+constexpr int F2_SLOTS = 14;
+constexpr int F2_XSLOT_A = 12, F2_XSLOT_B = 13;
 
 // The ranks keep the exchange column in LDS as 32x32 tiles of pitch 32 with
 // the 16-byte chunks of row r permuted by r mod 16 (chunk ch at position
 // ch ^ (r & 15)): a 64-lane load then lands 1 KB contiguously (direct
 // global-to-LDS loads), and the 16x4 operand fragments of the MFMA reads
 // fall on distinct banks.
-__device__ __forceinline__ int colk_at(int J, int r, int c) {
-    return J * TSZ + r * TS + ((((c >> 1) ^ (r & 15))) << 1) + (c & 1);
+__device__ __forceinline__ int colk_at(int slot, int r, int c) {
+    return slot * TSZ + r * TS + ((((c >> 1) ^ (r & 15))) << 1) + (c & 1);
 }
-constexpr int F2_MAXBLK = 13;         // accumulator blocks per wave: 4 * (NT + 1) / 4
+constexpr int F2_MAXBLK = 13;         // accumulator blocks per wave: 4 * 13 tiles / 4 waves
 static_assert(F2_NW == F2_WAVES && F2_MAXBLK == F2_BLOCKS, "factor workspace layout");
-static_assert(F2_NW * 12 * 256 <= F2_MAXNT * TS * 34, "final-write staging fits the exchange column's LDS");
+static_assert(F2_NW * 12 * 256 <= F2_SLOTS * TSZ, "final-write staging fits the exchange column's LDS");
+static_assert(2 * F2_SPLIT_NT == F2_MAXNT && F2_XSLOT_B < F2_SLOTS, "split ranks: parity slots, then the two rows");
+
+// The tiles a rank owns: block rows rowA = rp and rowB = NT-1-rp (one row if
+// they coincide), and in them every block column J <= the row (sp = 1) or the
+// columns J = h (mod 2) (sp = 2, half h of the pair).  Tile q of the rank's
+// list: the row-A tiles by increasing J, then the row-B tiles.
+struct F2Own {
+    int rowA, rowB, nrows, h, sp, ntA, ntl;
+};
+__device__ __forceinline__ F2Own f2_own(int rank, int NT) {
+    F2Own o;
+    o.sp = f2_split(NT);
+    o.h = rank % o.sp;
+    o.rowA = rank / o.sp;
+    o.rowB = NT - 1 - o.rowA;
+    o.nrows = o.rowB > o.rowA ? 2 : 1;
+    o.ntA = o.rowA >= o.h ? (o.rowA - o.h) / o.sp + 1 : 0;
+    const int ntB = o.nrows == 2 && o.rowB >= o.h ? (o.rowB - o.h) / o.sp + 1 : 0;
+    o.ntl = o.ntA + ntB;
+    return o;
+}
+// LDS slot of block column J of the exchange column (J a column the rank
+// reads: one of its tile columns or one of its rows)
+__device__ __forceinline__ int f2_slot(const F2Own& o, int J) {
+    if (o.sp == 1) return J;
+    if ((J & 1) == o.h) return J >> 1;
+    return J == o.rowA ? F2_XSLOT_A : F2_XSLOT_B;
+}
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 typedef double d2 __attribute__((ext_vector_type(2)));
 
 struct FactorArgs {
     const SubDesc* subs;
-    int sub0, nsub;           // subdomains [sub0, nsub) of this launch; sub0 % 8 == 0
-    int pf;                   // rank slots per chain (the largest ceil(NT / 2))
+    int sub0, nsub;           // subdomains [sub0, nsub) of this launch; sub0 % lanes == 0
+    int lanes;                // subdomains side by side in the grid (8: one XCD each)
+    int pf;                   // rank slots per chain (the largest f2_ranks(NT))
     int groups;               // chains per subdomain: 1 (top to bottom) or 2 (twisted)
     int fp32;                 // 1: store the inverse tiles in single precision
     const double* f0;
@@ -207,21 +241,21 @@ __device__ bool f2_tpoll(const uint64_t* src, uint32_t tag, double* dst, const D
     return __syncthreads_and(ok) != 0;
 }
 
-__device__ __forceinline__ void f2_tile_of(int q, int rowA, int rowB, int& I, int& J) {
-    if (q <= rowA) { I = rowA; J = q; }
-    else           { I = rowB; J = q - rowA - 1; }
+__device__ __forceinline__ void f2_tile_of(int q, const F2Own& o, int& I, int& J) {
+    if (q < o.ntA) { I = o.rowA; J = o.h + o.sp * q; }
+    else           { I = o.rowB; J = o.h + o.sp * (q - o.ntA); }
 }
 
 // Publish block column `col` of the current matrix (the own blocks in it)
 // into the exchange slots xb[J] = S_{J,col} (32x32 row-major).
-__device__ __forceinline__ void f2_publish(const d4 (&acc)[F2_MAXBLK], double* xb, int col, int nblk, int rowA,
-                                           int rowB, int wv, int cr, int cc) {
+__device__ __forceinline__ void f2_publish(const d4 (&acc)[F2_MAXBLK], double* xb, int col, int nblk, const F2Own& o,
+                                           int wv, int cr, int cc) {
 #pragma unroll
     for (int b = 0; b < F2_MAXBLK; ++b) {
         const int blk = wv + F2_NW * b;
         if (blk >= nblk) continue;
         int I, J;
-        f2_tile_of(blk >> 2, rowA, rowB, I, J);
+        f2_tile_of(blk >> 2, o, I, J);
         const int qi = (blk >> 1) & 1, qj = blk & 1;
         if (J == col) {                                  // tile (I, col): slot I as is
 #pragma unroll
@@ -246,13 +280,13 @@ __device__ __forceinline__ void f2_publish(const d4 (&acc)[F2_MAXBLK], double* x
 // the diagonal entry of A_tt it came from (adiag_k, LDS).
 // Publish the own diagonal tile (col, col) as tagged words into the pivot-block slot db.
 __device__ __forceinline__ void f2_publish_diag(const d4 (&acc)[F2_MAXBLK], uint64_t* db, uint32_t tag, int col,
-                                                int nblk, int rowA, int rowB, int wv, int cr, int cc) {
+                                                int nblk, const F2Own& o, int wv, int cr, int cc) {
 #pragma unroll
     for (int b = 0; b < F2_MAXBLK; ++b) {
         const int blk = wv + F2_NW * b;
         if (blk >= nblk) continue;
         int I, J;
-        f2_tile_of(blk >> 2, rowA, rowB, I, J);
+        f2_tile_of(blk >> 2, o, I, J);
         const int qi = (blk >> 1) & 1, qj = blk & 1;
         if (I == col && J == col) {
 #pragma unroll
@@ -419,26 +453,28 @@ __device__ void f2_pivot_inverse(const double* Sk, double* piv, double* xr, cons
 }
 
 __global__ void __launch_bounds__(F2_THREADS) k_factor2(FactorArgs A) {
-    // LDS: exchange column (NT tiles), pivot inverse, scaled rows X_I (2 tiles)
-    __shared__ __attribute__((aligned(16))) double colk[F2_MAXNT * LTILE];
-    __shared__ double piv[LTILE];
-    __shared__ __attribute__((aligned(16))) double xr[2 * LTILE];
-    __shared__ double adiag[F2_MAXNT * TS];
-    __shared__ double Cl[F2_MAXNT * TS * 6];             // couplings to the next line, [m][6]
+    // LDS: exchange column (the rank's F2_SLOTS tiles), then pivot inverse and
+    // scaled rows X_I (2 tiles).  While a line is built, the exchange column's
+    // space holds the line's node blocks and couplings, and the pivot / X
+    // space the waves' window scratch.
+    __shared__ __attribute__((aligned(16))) double colk[F2_SLOTS * TSZ];
+    __shared__ __attribute__((aligned(16))) double pxr[3 * LTILE];
+    double* const piv = pxr;
+    double* const xr = pxr + LTILE;
     __shared__ int sh_ok;
 
-    // workgroup g runs on XCD g % 8: the ranks of subdomain i are the slots
-    // with g % 8 == i % 8, so its exchange stays inside one L2
+    // workgroup g runs on XCD g % 8: with A.lanes = 8 the ranks of subdomain
+    // i are the slots with g % 8 == i % 8, so its exchange stays inside one L2
     // per chain: ranks 0..pf-1 and the pivot server (rank pf)
-    const int ps = A.pf + 1, slot = blockIdx.x / 8, per = A.groups * ps;
-    const int sub = A.sub0 + (int)(blockIdx.x % 8) + 8 * (slot / per);
+    const int ps = A.pf + 1, slot = blockIdx.x / A.lanes, per = A.groups * ps;
+    const int sub = A.sub0 + (int)(blockIdx.x % A.lanes) + A.lanes * (slot / per);
     const int chain = (slot % per) / ps, rank = slot % ps;
     const bool server = rank == A.pf;
     if (sub >= A.nsub) return;                           // idle slot
     const SubDesc d = A.subs[sub];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int m = d.m, mp = d.mp, NT = d.NT, ms = d.ms;
-    const int Pf = (NT + 1) / 2;
+    const int Pf = f2_ranks(NT);
     if (!server && rank >= Pf) return;                   // surplus slot of a short subdomain
     double* Tout = A.factors + d.foff;
     double* Bst = A.factors + d.boff;
@@ -462,6 +498,7 @@ __global__ void __launch_bounds__(F2_THREADS) k_factor2(FactorArgs A) {
         // pivot server: for every pivot of every line of the chain, wait for
         // the pivot block S_kk, form Pi_k (wave 0) and publish it
         uint32_t npiv = 0;
+        double* adiag = colk + 2 * TSZ;          // beyond the 32 x LDP pivot block staged at colk
         for (int li = 0; li < nlines; ++li) {
             const int t = chain == 0 ? li : nt - 1 - li;
             const double* Ag = A.factors + d.aoff + (int64_t)t * ms * 18;
@@ -480,11 +517,17 @@ __global__ void __launch_bounds__(F2_THREADS) k_factor2(FactorArgs A) {
         return;
     }
 
-    // own block rows and tiles; tile list: row r first, then row NT-1-r
-    const int rowA = rank, rowB = NT - 1 - rank;
-    const int nrows = rowB > rowA ? 2 : 1;
-    const int ntl = (rowA + 1) + (nrows == 2 ? rowB + 1 : 0);
-    const int nblk = 4 * ntl;                 // 16x16 accumulator blocks
+    // own block rows and tiles; tile list: row rowA first, then row rowB
+    const F2Own own = f2_own(rank, NT);
+    const int rowA = own.rowA, rowB = own.rowB, nrows = own.nrows;
+    const int nblk = 4 * own.ntl;             // 16x16 accumulator blocks
+    // exchange-column tiles this rank reads, in load order: every block column
+    // (sp = 1), or the npar columns of its parity and then its rows of the
+    // other parity (sp = 2); f2_slot gives each one's LDS slot
+    const int npar = own.sp == 1 ? NT : (NT - own.h + 1) / 2;
+    const bool xtraA = own.sp == 2 && (rowA & 1) != own.h;
+    const bool xtraB = own.sp == 2 && nrows == 2 && (rowB & 1) != own.h;
+    const int nslots = npar + (xtraA ? 1 : 0) + (xtraB ? 1 : 0);
     d4 acc[F2_MAXBLK];
     // fragment coordinates of this lane inside a 16x16 block
     // (recomputed from an opaque copy of the lane id in every pivot step, so
@@ -509,6 +552,7 @@ __global__ void __launch_bounds__(F2_THREADS) k_factor2(FactorArgs A) {
         double* Aself = colk;                    // [ms][9]
         double* Anext = colk + 9 * ms;           // [ms][9]: block (s, s+1)
         double* Bl = colk + 18 * ms;             // [m][6]: B_t, nodes s-1, s of line t-1
+        double* Cl = Bl + 6 * m;                 // [m][6]: B_{t+1}^T, nodes s, s+1 of line t+1
         {
             const double* Ag = A.factors + d.aoff + (int64_t)t * ms * 18;
             for (int i = tid; i < 18 * ms; i += F2_THREADS) {
@@ -533,7 +577,6 @@ __global__ void __launch_bounds__(F2_THREADS) k_factor2(FactorArgs A) {
             }
         }
         __syncthreads();
-        for (int a = tid; a < mp; a += F2_THREADS) adiag[a] = a < m ? Aself[9 * (a / 3) + 4 * (a % 3)] : 1.0;
         // A_tt entry (a, a2), both < m
         auto a_entry = [&](int a, int a2) -> double {
             const int s = a / 3, c = a % 3, s2 = a2 / 3, c2 = a2 % 3;
@@ -555,7 +598,7 @@ __global__ void __launch_bounds__(F2_THREADS) k_factor2(FactorArgs A) {
             return;
         {
             constexpr int WN = 21;
-            double* win = colk + 4608 + wv * (WN * WN + WN * 16);   // [WN][WN]
+            double* win = pxr + wv * (WN * WN + WN * 16);           // [WN][WN]
             double* zb = win + WN * WN;                             // [WN][16]
             constexpr int NWL = (WN * WN + 63) / 64;              // window entries per lane
             // Work items: (block b of this wave, term).  The window loads of the
@@ -569,7 +612,7 @@ __global__ void __launch_bounds__(F2_THREADS) k_factor2(FactorArgs A) {
                 dn = nterm == 2 ? (it & 1) : (hup ? 0 : 1);
                 int I, J;
                 const int blk = wv + F2_NW * b;
-                f2_tile_of(blk >> 2, rowA, rowB, I, J);
+                f2_tile_of(blk >> 2, own, I, J);
                 r0 = I * TS + 16 * ((blk >> 1) & 1);
                 c0 = J * TS + 16 * (blk & 1);
             };
@@ -680,7 +723,7 @@ __global__ void __launch_bounds__(F2_THREADS) k_factor2(FactorArgs A) {
                 for (int b = 0; b < nbw; ++b) {
                     int I, J;
                     const int blk = wv + F2_NW * b;
-                    f2_tile_of(blk >> 2, rowA, rowB, I, J);
+                    f2_tile_of(blk >> 2, own, I, J);
                     a_init(I * TS + 16 * ((blk >> 1) & 1), J * TS + 16 * (blk & 1));
 #pragma unroll
                     for (int q = 0; q < 4; ++q) bscr[(b * 4 + q) * 64 + lane] = v[q];
@@ -712,10 +755,9 @@ __global__ void __launch_bounds__(F2_THREADS) k_factor2(FactorArgs A) {
         }
         __syncthreads();   // LDS (Aself/Anext/Bl) is reused for the exchange column below
 
-        if (rowA == 0)                                    // hand the first pivot block to the server
-            f2_publish_diag(acc, dslot + ((npiv + 1) & 1) * 2 * TSZ, A.epoch + npiv + 1, 0, nblk, rowA, rowB, wv,
-                            cr, cc);
-        f2_publish(acc, xch + (int64_t)(phase & 1) * NT * TSZ, 0, nblk, rowA, rowB, wv, cr, cc);
+        if (rowA == 0 && own.h == 0)                      // hand the first pivot block to the server
+            f2_publish_diag(acc, dslot + ((npiv + 1) & 1) * 2 * TSZ, A.epoch + npiv + 1, 0, nblk, own, wv, cr, cc);
+        f2_publish(acc, xch + (int64_t)(phase & 1) * NT * TSZ, 0, nblk, own, wv, cr, cc);
         f2_signal(cnt);
         ++phase;
 
@@ -736,17 +778,20 @@ __global__ void __launch_bounds__(F2_THREADS) k_factor2(FactorArgs A) {
             // instruction q fills LDS chunks 64 q .. 64 q + 63 of the permuted
             // layout, lane l fetching the chunk that belongs at position 64 q + l
             {
-                const int ln = tido & 63, nq = NT * (TSZ / 128);
+                const int ln = tido & 63, nq = nslots * (TSZ / 128);
                 const int wvu = __builtin_amdgcn_readfirstlane(wv);
 #pragma unroll
-                for (int u = 0; u < F2_MAXNT * (TSZ / 128) / F2_NW; ++u) {
+                for (int u = 0; u < F2_SLOTS * (TSZ / 128) / F2_NW; ++u) {
                     const int q = wvu + F2_NW * u;
                     if (q >= nq) break;
-                    const int J = q / (TSZ / 128), p = (q % (TSZ / 128)) * 64 + ln;
+                    const int sl = q / (TSZ / 128), p = (q % (TSZ / 128)) * 64 + ln;
+                    const int J = sl < npar ? own.h + own.sp * sl : ((sl == npar && xtraA) ? rowA : rowB);
+                    const int dsl = f2_slot(own, J);
                     const int r = p >> 4, ch = (p & 15) ^ (r & 15);
-                    __builtin_amdgcn_global_load_lds(xb + J * TSZ + r * TS + 2 * ch,
-                                                     (__attribute__((address_space(3))) void*)(colk + q * 128), 16, 0,
-                                                     16 /* sc1: device scope */);
+                    __builtin_amdgcn_global_load_lds(
+                        xb + J * TSZ + r * TS + 2 * ch,
+                        (__attribute__((address_space(3))) void*)(colk + (dsl * (TSZ / 128) + q % (TSZ / 128)) * 128),
+                        16, 0, 16 /* sc1: device scope */);
                 }
                 __builtin_amdgcn_s_waitcnt(0);
             }
@@ -763,7 +808,7 @@ __global__ void __launch_bounds__(F2_THREADS) k_factor2(FactorArgs A) {
                     d4 x = {0.0, 0.0, 0.0, 0.0};
                     #pragma unroll
                     for (int ks = 0; ks < TS / 4; ++ks) {
-                        const double a = colk[colk_at(I, 16 * qi + fr, 4 * ks + fk)];
+                        const double a = colk[colk_at(f2_slot(own, I), 16 * qi + fr, 4 * ks + fk)];
                         const double b = piv[(4 * ks + fk) * LDP + 16 * qj + fr];
                         x = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, x, 0, 0, 0);
                     }
@@ -778,7 +823,7 @@ __global__ void __launch_bounds__(F2_THREADS) k_factor2(FactorArgs A) {
             // that the server and the other ranks' waits overlap the remaining
             // updates.
             const int kn = k + 1;
-            const bool own_next = kn < NT && (rowA == kn || rowB == kn);
+            const bool own_next = kn < NT && (rowA == kn || rowB == kn) && kn % own.sp == own.h;
 #pragma unroll
             for (int pass = 0; pass < 3; ++pass) {
             if (pass == 0 && !own_next) continue;
@@ -787,7 +832,7 @@ __global__ void __launch_bounds__(F2_THREADS) k_factor2(FactorArgs A) {
                 const int blk = wv + F2_NW * b;
                 if (blk >= nblk) continue;
                 int I, J;
-                f2_tile_of(blk >> 2, rowA, rowB, I, J);
+                f2_tile_of(blk >> 2, own, I, J);
                 const int bp = kn >= NT ? 2 : (I == kn && J == kn ? 0 : (I == kn || J == kn ? 1 : 2));
                 if (bp != pass) continue;
                 const int qi = (blk >> 1) & 1, qj = blk & 1;
@@ -802,7 +847,7 @@ __global__ void __launch_bounds__(F2_THREADS) k_factor2(FactorArgs A) {
                     #pragma unroll
                     for (int u = 0; u < 4; ++u) {
                         av[u] = *reinterpret_cast<const d2*>(&xr[rr * LTILE + (16 * qi + fr) * LDP + 8 * fk + 2 * u]);
-                        bv[u] = *reinterpret_cast<const d2*>(&colk[colk_at(J, 16 * qj + fr, 8 * fk + 2 * u)]);
+                        bv[u] = *reinterpret_cast<const d2*>(&colk[colk_at(f2_slot(own, J), 16 * qj + fr, 8 * fk + 2 * u)]);
                     }
                     d4 v = acc[b];
                     #pragma unroll
@@ -821,7 +866,7 @@ __global__ void __launch_bounds__(F2_THREADS) k_factor2(FactorArgs A) {
                     #pragma unroll
                     for (int ks = 0; ks < TS / 4; ++ks) {
                         const double a = piv[(16 * qi + fr) * LDP + 4 * ks + fk];
-                        const double bb = colk[colk_at(J, 16 * qj + fr, 4 * ks + fk)];
+                        const double bb = colk[colk_at(f2_slot(own, J), 16 * qj + fr, 4 * ks + fk)];
                         v = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb, v, 0, 0, 0);
                     }
                     acc[b] = v;
@@ -834,10 +879,10 @@ __global__ void __launch_bounds__(F2_THREADS) k_factor2(FactorArgs A) {
                 __builtin_amdgcn_sched_barrier(0);
             }
             if (pass == 0)
-                f2_publish_diag(acc, dslot + ((npiv + 1) & 1) * 2 * TSZ, A.epoch + npiv + 1, kn, nblk, rowA, rowB, wv,
-                                cr, cc);
+                f2_publish_diag(acc, dslot + ((npiv + 1) & 1) * 2 * TSZ, A.epoch + npiv + 1, kn, nblk, own, wv, cr,
+                                cc);
             if (pass == 1 && kn < NT) {
-                f2_publish(acc, xch + (int64_t)(phase & 1) * NT * TSZ, kn, nblk, rowA, rowB, wv, cr, cc);
+                f2_publish(acc, xch + (int64_t)(phase & 1) * NT * TSZ, kn, nblk, own, wv, cr, cc);
                 f2_signal(cnt);
             }
             }
@@ -859,7 +904,7 @@ __global__ void __launch_bounds__(F2_THREADS) k_factor2(FactorArgs A) {
                 auto store_block = [&](int b, const double (&vals)[4]) {
                     const int blk = wv + F2_NW * b;
                     int I, J;
-                    f2_tile_of(blk >> 2, rowA, rowB, I, J);
+                    f2_tile_of(blk >> 2, own, I, J);
                     const int qi = (blk >> 1) & 1, qj = blk & 1;
                     const int q0 = I * (I + 1) / 2 + J;
                     const int64_t toff = ((int64_t)t * d.ntiles + q0) * TSZ;
@@ -921,6 +966,7 @@ int launch_factor2(sf_context* c, int sub0, int nsub_chunk, int Pf) {
     a.subs = c->d_subs;
     a.sub0 = sub0;
     a.nsub = sub0 + nsub_chunk;
+    a.lanes = c->factor_lanes;
     a.pf = Pf;
     a.groups = c->groups;
     a.fp32 = c->cfg.factor_precision == SF_FP32 ? 1 : 0;
@@ -940,8 +986,9 @@ int launch_factor2(sf_context* c, int sub0, int nsub_chunk, int Pf) {
     for (const auto& d : c->subs) maxpiv = std::max(maxpiv, d.nt * d.NT);
     c->factor_epoch += (uint32_t)maxpiv + 4;
     void* args[] = {&a};
-    if (hipLaunchCooperativeKernel((const void*)k_factor2, dim3(8 * ((nsub_chunk + 7) / 8) * c->groups * (Pf + 1)), dim3(F2_THREADS), args, 0,
-                                   c->stream) != hipSuccess)
+    const int L = c->factor_lanes;
+    if (hipLaunchCooperativeKernel((const void*)k_factor2, dim3(L * ((nsub_chunk + L - 1) / L) * c->groups * (Pf + 1)),
+                                   dim3(F2_THREADS), args, 0, c->stream) != hipSuccess)
         return SF_ERR_HIP;
     return SF_OK;
 }

@@ -12,6 +12,8 @@ namespace sfdd {
 constexpr int TS = 32;          // factor tile edge (doubles)
 constexpr int TSZ = TS * TS;    // doubles per tile
 constexpr int FACTOR_THREADS = 256;
+constexpr int FACTOR_WS_SLOTS = 64;  // factor workspaces: subdomains per factor launch at most
+constexpr int F2_MAX_NT = 24;        // cooperative factor: line matrices up to 768 x 768
 
 // One subdomain: a box of the pixel grid cut into lines along its shorter side.
 //   lines are columns (cols = 1): line t = x - bx0, position s = y - by0
@@ -59,13 +61,15 @@ struct sf_context {
     int state;                      // 0 created, 1 assembled, 2 factored
     std::vector<sfdd::SubDesc> subs;
     sfdd::SubDesc* d_subs;
-    int sweep_grid;                 // 8 * ceil(nsub / 8) * groups * maxP workgroups (idle slots exit)
     int maxP;                       // sweep workgroups per chain
     int sweep_capacity;             // co-resident sweep workgroups on the device
+    int sweep_lanes;                // subdomains side by side in a sweep grid (8: each on one XCD)
+    int sweep_chunk;                // subdomains per sweep launch (a multiple of sweep_lanes)
     int groups;                     // chains per subdomain: 2 = twisted factorisation, 1 = top to bottom
     int sweep_rows;                 // largest number of block rows a sweep workgroup owns
     int factor_pf;                  // workgroups per subdomain in the cooperative factor (0: one-WG factor)
-    int factor_chunk;               // subdomains per cooperative factor launch
+    int factor_chunk;               // subdomains per cooperative factor launch (a multiple of factor_lanes)
+    int factor_lanes;               // subdomains side by side in a factor grid (8: each on one XCD)
     uint32_t sweep_epoch;           // tag base for the sweep's published rows
     uint32_t factor_epoch;          // tag base for the factor's pivot blocks and inverses
     double* blur_w;                 // presmoothing weights, 2 blur_r + 1 (sigma > 0)
@@ -135,9 +139,10 @@ const void* factor2_kernel();
 int launch_sweep(sf_context* c, double* U, const double* r, int single_sub, const double* b_local,
                  double* x_local);
 uint32_t sweep_epoch_step(const sf_context* c);   // tag base advance of one sweep launch
-const void* sweep_kernel();
-const void* sweep_kernel_small();
-int sweep_threads(int fast);
+enum { SWEEP_GENERAL = 0, SWEEP_FAST2 = 1, SWEEP_FAST1 = 2 };
+const void* sweep_kernel(int form, int fp32);
+int sweep_threads(int form);
+int sweep_form(const sf_context* c);
 // timing helpers (api.hip): bracket a launch of kernel class `kind`
 int prof_begin(sf_context* c, int kind);
 int prof_end(sf_context* c);

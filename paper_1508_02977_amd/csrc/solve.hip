@@ -23,11 +23,19 @@
 
 namespace sfdd {
 
-constexpr int MAXMP = 512;
+#define SF_TRY_SWEEP(x)               \
+    do {                              \
+        int rc_ = (x);                \
+        if (rc_ != SF_OK) return rc_; \
+    } while (0)
+
+constexpr int MAXMP = 768;
 
 struct SweepArgs {
     const SubDesc* subs;
-    int nsub;               // subdomains (mode 0) ; the single subdomain index (mode 1)
+    int sub0;               // first subdomain of this launch (mode 0; a multiple of lanes)
+    int nsub;               // end of this launch's subdomains (mode 0) ; the single subdomain index (mode 1)
+    int lanes;              // subdomains side by side in the grid (8: the ranks of one on one XCD)
     const double* factors;
     double* work;
     const double* r;        // global residual [B][3][H][W] (mode 0)
@@ -43,7 +51,7 @@ struct SweepArgs {
     long long spin_limit;
 };
 
-constexpr int MAXR = 16;   // block rows per rank (NT <= 16)
+constexpr int MAXR = 16;   // block rows per rank in the general form
 
 // Tile (I, J) of the block row of symmetric S: lower tile (I,J) if J <= I,
 // else the lower tile (J,I) used transposed.  Lane (c, h), c = lane % 16,
@@ -209,7 +217,9 @@ __global__ void __launch_bounds__(64 * NWV) k_sweep(SweepArgs A) {
     constexpr int NRC = (RMAX * TS + 63) / 64;     // own rows per control lane
     // rows of z per tile-wave thread: general form, all rows over the tile
     // threads; fast form, the 32 (PF / 2) rows of the wave's column blocks
-    constexpr int RPT = RMAX == 2 ? (16 * PF + 63) / 64 : (LMAX + CW0 - 1) / CW0;
+    constexpr bool FAST = RMAX <= 2;
+    constexpr int PH = PF / RMAX;                  // fast form: tile slots per own row
+    constexpr int RPT = FAST ? (32 * PH + 63) / 64 : (LMAX + CW0 - 1) / CW0;
     __shared__ double z[LMAX];
     __shared__ double vup[LMAX];                   // vector of the line above (t - 1)
     __shared__ double vdn[LMAX];                   // vector of the line below (t + 1)
@@ -219,7 +229,7 @@ __global__ void __launch_bounds__(64 * NWV) k_sweep(SweepArgs A) {
     const int mode = A.mode, G = A.groups;
     int sub, grp, rank;
     {
-        const int x = blockIdx.x % 8, slot = blockIdx.x / 8;
+        const int x = blockIdx.x % A.lanes, slot = blockIdx.x / A.lanes;
         const int P0 = A.subs[0].P;
         if (mode == 1) {
             if (x != 0) return;                        // idle slot
@@ -227,7 +237,7 @@ __global__ void __launch_bounds__(64 * NWV) k_sweep(SweepArgs A) {
             grp = slot / P0;
             rank = slot % P0;
         } else {
-            sub = x + 8 * (slot / (G * P0));
+            sub = A.sub0 + x + A.lanes * (slot / (G * P0));
             grp = (slot % (G * P0)) / P0;
             rank = slot % P0;
             if (sub >= A.nsub) return;                 // idle slot
@@ -280,7 +290,7 @@ __global__ void __launch_bounds__(64 * NWV) k_sweep(SweepArgs A) {
     // Rows of z that this thread forms.  Fast form: a tile wave forms exactly
     // the rows it consumes (its column blocks wv + NWT i), so no workgroup
     // barrier separates z from the products; general form: rows tid + CW0 j.
-    static_assert(RMAX != 2 || 64 * RPT >= 16 * PF, "fast form: z rows of a wave = its column blocks");
+    static_assert(!FAST || (64 * RPT >= 32 * PH && PF % RMAX == 0), "fast form: z rows of a wave = its column blocks");
     // (The thread index is passed through an empty asm statement where rows
     // are formed inside the phase loop, so that the compiler recomputes the
     // few integer operations of their addresses instead of keeping a set of
@@ -289,9 +299,9 @@ __global__ void __launch_bounds__(64 * NWV) k_sweep(SweepArgs A) {
     auto zrow = [&](int j) -> int {
         int tx = tid;
         if constexpr (OPAQUE) asm volatile("" : "+v"(tx));
-        if constexpr (RMAX == 2) {
+        if constexpr (FAST) {
             const int k = (tx & 63) + 64 * j;
-            if (k >= 16 * PF) return LMAX;                  // no row (a lane beyond the wave's blocks)
+            if (k >= 32 * PH) return LMAX;                  // no row (a lane beyond the wave's blocks)
             return ((tx >> 6) + NWT * (k >> 5)) * TS + (k & 31);
         } else {
             return tx + CW0 * j;
@@ -314,21 +324,21 @@ __global__ void __launch_bounds__(64 * NWV) k_sweep(SweepArgs A) {
             return rbase[j] + (int64_t)t * rstep;
     };
     // this thread's prefetched tiles (fixed for all lines): offsets inside a line
-    // Fast form (RMAX == 2, NT <= NWT PF / 2): slot p holds tile (row p / (PF/2),
-    // column wv + NWT (p % (PF/2))), so a wave's tiles of one row are fixed and
-    // the row partials stay in registers until one reduction per row.  General
-    // form: slot p holds the tile qt = wv + NWT p of the rank's row-major list.
-    constexpr bool FAST = RMAX == 2;
+    // Fast form (RMAX <= 2 rows per rank, NT <= NWT PH, PH = PF / RMAX): slot p
+    // holds tile (row p / PH, column wv + NWT (p % PH)), so a wave's tiles of one
+    // row are fixed and the row partials stay in registers until one reduction
+    // per row.  General form: slot p holds the tile qt = wv + NWT p of the
+    // rank's row-major list.
     constexpr bool RELOAD = FAST && sizeof(TT) == 8;   // tile slots reloaded right after their products
     auto slot_ok = [&](int p) -> bool {
-        if constexpr (FAST) return p / (PF / 2) < R && wv + NWT * (p % (PF / 2)) < NT;
+        if constexpr (FAST) return p / PH < R && wv + NWT * (p % PH) < NT;
         else return wv + NWT * p < ntw;
     };
     int32_t toff[PF];                              // < ntiles * TSZ elements
 #pragma unroll
     for (int p = 0; p < PF; ++p) {
         if constexpr (FAST) {
-            toff[p] = slot_ok(p) ? tile_lane_offset(own_row(p / (PF / 2), rank, P), wv + NWT * (p % (PF / 2))) : 0;
+            toff[p] = slot_ok(p) ? tile_lane_offset(own_row(p / PH, rank, P), wv + NWT * (p % PH)) : 0;
         } else {
             const int qt = min(wv + NWT * p, ntw - 1);
             toff[p] = tile_lane_offset(own_row(qt / NT, rank, P), qt % NT);
@@ -393,37 +403,44 @@ __global__ void __launch_bounds__(64 * NWV) k_sweep(SweepArgs A) {
         for (int p = 0; p < PF; ++p)
             if (slot_ok(p)) load_tile(Tl + toff[p], pre[p]);
     };
-    // control wave: poll the published words of (group g, phase q) into dst
+    // control wave: poll the published words of (group g, phase q) into dst,
+    // at most GMAX words per lane in flight (registers), group after group
     auto gather = [&](int g, int q, double* dst) -> int {
         const uint32_t tag = tag_of(g, q);
         const uint64_t* pbuf = slot_of(g, q);
-        constexpr int NG = LMAX / 64;
-        uint64_t lo[NG], hi[NG];
-        unsigned pending = 0;
-#pragma unroll
-        for (int u = 0; u < NG; ++u)
-            if (lane + 64 * u < mp) pending |= 1u << u;
+        constexpr int NG = LMAX / 64, GMAX = 6;
         long long n = 0;
-        while (pending) {
+#pragma unroll 1
+        for (int u0 = 0; u0 < NG; u0 += GMAX) {
+            constexpr int GW = NG < GMAX ? NG : GMAX;
+            uint64_t lo[GW], hi[GW];
+            unsigned pending = 0;
 #pragma unroll
-            for (int u = 0; u < NG; ++u)
-                if (pending & (1u << u)) {
-                    const int a = lane + 64 * u;
-                    lo[u] = __hip_atomic_load(const_cast<uint64_t*>(pbuf + 2 * a), __ATOMIC_RELAXED,
-                                              __HIP_MEMORY_SCOPE_AGENT);
-                    hi[u] = __hip_atomic_load(const_cast<uint64_t*>(pbuf + 2 * a + 1), __ATOMIC_RELAXED,
-                                              __HIP_MEMORY_SCOPE_AGENT);
-                }
+            for (int v = 0; v < GW; ++v)
+                if (u0 + v < NG && lane + 64 * (u0 + v) < mp) pending |= 1u << v;
+            while (pending) {
 #pragma unroll
-            for (int u = 0; u < NG; ++u)
-                if ((pending & (1u << u)) && (uint32_t)(lo[u] >> 32) == tag && (uint32_t)(hi[u] >> 32) == tag) {
-                    dst[lane + 64 * u] = __longlong_as_double((long long)((hi[u] << 32) | (lo[u] & 0xffffffffull)));
-                    pending &= ~(1u << u);
-                }
-            if (!pending) break;
-            if (++n > spin || __hip_atomic_load(&st->code, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == SF_ERR_DEVICE)
-                return 0;
-            __builtin_amdgcn_s_sleep(1);
+                for (int v = 0; v < GW; ++v)
+                    if (pending & (1u << v)) {
+                        const int a = lane + 64 * (u0 + v);
+                        lo[v] = __hip_atomic_load(const_cast<uint64_t*>(pbuf + 2 * a), __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_AGENT);
+                        hi[v] = __hip_atomic_load(const_cast<uint64_t*>(pbuf + 2 * a + 1), __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_AGENT);
+                    }
+#pragma unroll
+                for (int v = 0; v < GW; ++v)
+                    if ((pending & (1u << v)) && (uint32_t)(lo[v] >> 32) == tag && (uint32_t)(hi[v] >> 32) == tag) {
+                        dst[lane + 64 * (u0 + v)] =
+                            __longlong_as_double((long long)((hi[v] << 32) | (lo[v] & 0xffffffffull)));
+                        pending &= ~(1u << v);
+                    }
+                if (!pending) break;
+                if (++n > spin ||
+                    __hip_atomic_load(&st->code, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == SF_ERR_DEVICE)
+                    return 0;
+                __builtin_amdgcn_s_sleep(1);
+            }
         }
         return 1;
     };
@@ -515,9 +532,8 @@ __global__ void __launch_bounds__(64 * NWV) k_sweep(SweepArgs A) {
                 // transposed partials tp0, tp1 of columns 2c, 2c+1, summed over
                 // this wave's tiles of the row, then one reduction per row
                 const int c = lane & 15, h = lane >> 4;
-                constexpr int PH = PF / 2;
 #pragma unroll
-                for (int i = 0; i < 2; ++i) {
+                for (int i = 0; i < RMAX; ++i) {
                     if (i >= R) break;
                     const int I = own_row(i, rank, P);
                     double d[8], s0 = 0.0, s1 = 0.0;
@@ -638,23 +654,33 @@ __global__ void k_zero_u32(uint32_t* p, int n) {
 }
 
 // Launch forms.  General: 4 waves (3 tile waves; one wave per SIMD, 512
-// registers each).  Fast (at most 2 block rows per rank, lines up to 384),
-// all of a phase's tiles in registers: 8 waves (7 tile waves, 4 tiles each,
-// within 256 VGPRs, two waves per SIMD), FP64 or FP32 tiles.
+// registers each), any number of block rows per rank.  Fast forms, all of a
+// phase's tiles in registers (8 waves: 7 tile waves of 4 tile slots, within
+// 256 VGPRs, two waves per SIMD): at most two block rows per rank and lines
+// up to 448 (NT <= 14), or one block row per rank and lines up to 768.
+// FP64 or FP32 tiles.
 constexpr int GEN_WAVES = 4;
-const void* sweep_kernel() { return (const void*)k_sweep<double, MAXR, 4, MAXMP, GEN_WAVES>; }
-const void* sweep_kernel_small() { return (const void*)k_sweep<double, 2, 4, 384, 8>; }
-
-static void sweep_form(const sf_context* c, bool fast, const void** kern, int* threads) {
-    if (c->cfg.factor_precision == SF_FP32) {
-        *kern = fast ? (const void*)k_sweep<float, 2, 4, 384, 8> : (const void*)k_sweep<float, MAXR, 4, MAXMP, GEN_WAVES>;
-        *threads = fast ? 512 : 64 * GEN_WAVES;
-    } else {
-        *kern = fast ? (const void*)k_sweep<double, 2, 4, 384, 8> : (const void*)k_sweep<double, MAXR, 4, MAXMP, GEN_WAVES>;
-        *threads = 64 * (fast ? 8 : GEN_WAVES);
-    }
+constexpr int FAST2_LMAX = 448, FAST1_LMAX = 768;
+template <typename TT>
+const void* sweep_kernel_of(int form) {
+    if (form == SWEEP_FAST2) return (const void*)k_sweep<TT, 2, 4, FAST2_LMAX, 8>;
+    if (form == SWEEP_FAST1) return (const void*)k_sweep<TT, 1, 4, FAST1_LMAX, 8>;
+    return (const void*)k_sweep<TT, MAXR, 4, MAXMP, GEN_WAVES>;
 }
-int sweep_threads(int fast) { return fast ? 512 : 64 * GEN_WAVES; }
+const void* sweep_kernel(int form, int fp32) {
+    return fp32 ? sweep_kernel_of<float>(form) : sweep_kernel_of<double>(form);
+}
+int sweep_threads(int form) { return form == SWEEP_GENERAL ? 64 * GEN_WAVES : 512; }
+
+// The form of the current shape: the fast forms when every rank owns at
+// most two block rows of lines up to 448 or one block row of any line.
+int sweep_form(const sf_context* c) {
+    int maxmp = 0;
+    for (const auto& d : c->subs) maxmp = std::max(maxmp, d.mp);
+    if (c->sweep_rows <= 2 && maxmp <= FAST2_LMAX) return SWEEP_FAST2;
+    if (c->sweep_rows <= 1 && maxmp <= FAST1_LMAX) return SWEEP_FAST1;
+    return SWEEP_GENERAL;
+}
 
 uint32_t sweep_epoch_step(const sf_context* c) {
     int maxph = 0;
@@ -665,7 +691,6 @@ uint32_t sweep_epoch_step(const sf_context* c) {
 int launch_sweep(sf_context* c, double* U, const double* r, int single_sub, const double* b_local, double* x_local) {
     SweepArgs a;
     a.subs = c->d_subs;
-    a.nsub = single_sub >= 0 ? single_sub : c->nsub;
     a.factors = c->factors;
     a.work = c->work;
     a.r = r;
@@ -680,29 +705,45 @@ int launch_sweep(sf_context* c, double* U, const double* r, int single_sub, cons
     a.groups = c->groups;
     a.spin_limit = 1ll << 20;
     // tags must differ from every tag left in the exchange buffers by earlier
-    // launches: advance by more than the tags of one launch (2 per phase).
-    // While a graph is captured the kernel reads the tag base from the device
-    // counter that the graph advances after every sweep.
+    // launches: advance by more than the tags of one sweep (2 per phase).  The
+    // launches of one sweep's chunks share the tag base: their subdomains'
+    // exchange buffers are disjoint.  While a graph is captured the kernel
+    // reads the tag base from the device counter that the graph advances
+    // after every sweep.
     a.epoch = c->sweep_epoch;
     a.epoch_dev = c->graph_capture ? c->gepoch_d : nullptr;
     c->sweep_epoch += sweep_epoch_step(c);
     const int ranks = c->groups * c->maxP;
-    const int grid = single_sub >= 0 ? 8 * ranks : c->sweep_grid;
-    int maxmp = 0;
-    for (const auto& d : c->subs) maxmp = std::max(maxmp, d.mp);
-    const bool fast = c->sweep_rows <= 2 && maxmp <= 384;
-    const void* kern;
-    int threads;
-    sweep_form(c, fast, &kern, &threads);
+    const int form = sweep_form(c);
+    const void* kern = sweep_kernel(form, c->cfg.factor_precision == SF_FP32);
+    const int threads = sweep_threads(form);
     void* args[] = {&a};
     // A captured launch is an ordinary kernel node: the grid fits the
     // co-resident capacity measured at creation, and every wait is bounded.
-    if (ranks > 1 && !c->graph_capture) {
-        if (hipLaunchCooperativeKernel(kern, dim3(grid), dim3(threads), args, 0, c->stream) != hipSuccess)
-            return SF_ERR_HIP;
-    } else {
-        if (hipLaunchKernel(kern, dim3(grid), dim3(threads), args, 0, c->stream) != hipSuccess)
-            return SF_ERR_HIP;
+    auto launch = [&](int grid) -> int {
+        if (ranks > 1 && !c->graph_capture) {
+            if (hipLaunchCooperativeKernel(kern, dim3(grid), dim3(threads), args, 0, c->stream) != hipSuccess)
+                return SF_ERR_HIP;
+        } else {
+            if (hipLaunchKernel(kern, dim3(grid), dim3(threads), args, 0, c->stream) != hipSuccess)
+                return SF_ERR_HIP;
+        }
+        return SF_OK;
+    };
+    if (single_sub >= 0) {
+        a.sub0 = 0;
+        a.nsub = single_sub;
+        a.lanes = 1;
+        return launch(ranks);
+    }
+    // chunks of subdomains whose ranks fit co-resident, one launch each
+    const int L = c->sweep_lanes, chunk = c->sweep_chunk;
+    a.lanes = L;
+    for (int s0 = 0; s0 < c->nsub; s0 += chunk) {
+        const int n = std::min(chunk, c->nsub - s0);
+        a.sub0 = s0;
+        a.nsub = s0 + n;
+        SF_TRY_SWEEP(launch(L * ((n + L - 1) / L) * ranks));
     }
     return SF_OK;
 }

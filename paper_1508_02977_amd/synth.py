@@ -24,6 +24,20 @@ used real sequences that are not available here):
     both frames after warping.
   * ``linear``   : ``I0 = 0.5 + p x + q y``, uniform translation, used by the
     exact-recovery pins.
+  * ``batch1080``: 1920x1080 (one pair of a batch, seed per pair), the
+    ``plain640`` bump density (about 1350 bumps, each cut off beyond 6 sigma),
+    flow piecewise affine over the Voronoi cells of 6 random centres (each
+    cell ``t + J (x - c)``, rescaled to max |w| <= 6 over the image), gain
+    ``1 + 0.15 b/max|b|``.
+  * ``prec4k``   : 4096x2160 band-limited texture ``0.5 + sum_k c cos(2 pi
+    omega_k . x + phi_k)`` of 512 plane waves, |omega_k| in [1/64, 1/8]
+    cycles/px, c = 0.15 sqrt(2/512) (standard deviation 0.15); smooth flow of
+    4 low-frequency sinusoids (wavelengths >= 512 px) scaled to max |w| <= 8;
+    ``I1 = g I0(x - w) + o`` with a gain g in 1 +- 0.2 and an offset o in
+    +- 0.2 mean(I0) (the offset breaks the model's negligible-translator
+    assumption on purpose).  Any window of it can be evaluated on its own.
+  * ``adj1024``  : 1024x1024, about 683 bumps (cut off beyond 6 sigma), a
+    known affine flow rescaled to max |w| <= 2, gain ``1 + 0.1 b/max|b|``.
 """
 from __future__ import annotations
 
@@ -89,6 +103,115 @@ def _gain_field(rng, W, H, X, Y, amp):
     return 1.0 + amp * bv / np.max(np.abs(bv))
 
 
+def _bump_sum_local(b: Bumps, X: np.ndarray, Y: np.ndarray, DX=None, DY=None, pad: float = 0.0) -> np.ndarray:
+    """``b`` at the points (X - DX, Y - DY) of a pixel grid, each bump summed
+    only where that point lies within 6 of its sigmas (the same cut for every
+    frame); ``pad`` bounds |(DX, DY)|, so a window of the grid around each
+    centre holds every such point."""
+    H, W = X.shape
+    out = np.full((H, W), b.base, dtype=np.float64)
+    x0, y0 = X[0, 0], Y[0, 0]
+    for cx, cy, sg, a in zip(b.cx, b.cy, b.s, b.a):
+        r = 6.0 * sg
+        i0 = max(0, int(math.floor(cy - r - pad - y0)))
+        i1 = min(H, int(math.ceil(cy + r + pad - y0)) + 1)
+        j0 = max(0, int(math.floor(cx - r - pad - x0)))
+        j1 = min(W, int(math.ceil(cx + r + pad - x0)) + 1)
+        if i0 >= i1 or j0 >= j1:
+            continue
+        px = X[i0:i1, j0:j1] - (0.0 if DX is None else DX[i0:i1, j0:j1]) - cx
+        py = Y[i0:i1, j0:j1] - (0.0 if DY is None else DY[i0:i1, j0:j1]) - cy
+        d2 = px * px + py * py
+        v = a * np.exp(-d2 / (2.0 * sg * sg))
+        out[i0:i1, j0:j1] += np.where(d2 <= r * r, v, 0.0)
+    return out
+
+
+def _voronoi_affine_flow(rng, W, H, X, Y, ncell=6, wmax=6.0):
+    cx = rng.uniform(0.0, W - 1.0, ncell)
+    cy = rng.uniform(0.0, H - 1.0, ncell)
+    t = rng.uniform(-1.0, 1.0, (ncell, 2))
+    J = rng.uniform(-0.01, 0.01, (ncell, 2, 2))
+    d2 = np.stack([(X - cx[k]) ** 2 + (Y - cy[k]) ** 2 for k in range(ncell)])
+    cell = np.argmin(d2, axis=0)
+    w1 = np.zeros_like(X)
+    w2 = np.zeros_like(X)
+    for k in range(ncell):
+        mk = cell == k
+        w1[mk] = t[k, 0] + J[k, 0, 0] * (X[mk] - cx[k]) + J[k, 0, 1] * (Y[mk] - cy[k])
+        w2[mk] = t[k, 1] + J[k, 1, 0] * (X[mk] - cx[k]) + J[k, 1, 1] * (Y[mk] - cy[k])
+    mx = float(np.max(np.hypot(w1, w2)))
+    if mx > 0.0:
+        w1 *= wmax / mx
+        w2 *= wmax / mx
+    return w1, w2
+
+
+def make_pair_4k(seed: int, x0: int = 0, y0: int = 0, W: int | None = None, H: int | None = None,
+                 device=None) -> Pair:
+    """The ``prec4k`` pair of ``seed`` on the window [x0, x0 + W) x [y0, y0 + H)
+    of its 4096x2160 image (default: all of it); ``device`` evaluates the
+    plane waves with torch there (a CUDA device for the full image), else on
+    the host in float64 numpy."""
+    FW, FH = 4096, 2160
+    W = FW - x0 if W is None else W
+    H = FH - y0 if H is None else H
+    rng = np.random.default_rng(seed)
+    nk = 512
+    rad = rng.uniform(1.0 / 64.0, 1.0 / 8.0, nk)
+    ang = rng.uniform(0.0, 2.0 * math.pi, nk)
+    om = np.stack([rad * np.cos(ang), rad * np.sin(ang)], 1)          # cycles per pixel
+    ph = rng.uniform(0.0, 2.0 * math.pi, nk)
+    c = 0.15 * math.sqrt(2.0 / nk)
+    # smooth flow: 4 sinusoids of wavelength >= 512 px per component
+    fw = rng.uniform(1.0 / 2048.0, 1.0 / 512.0, (2, 4, 2)) * rng.choice([-1.0, 1.0], (2, 4, 2))
+    fp = rng.uniform(0.0, 2.0 * math.pi, (2, 4))
+    fa = rng.uniform(0.5, 1.0, (2, 4))
+    # gain and offset: 3 sinusoids of wavelength >= 1024 px each
+    gw = rng.uniform(1.0 / 4096.0, 1.0 / 1024.0, (2, 3, 2))
+    gp = rng.uniform(0.0, 2.0 * math.pi, (2, 3))
+    X, Y = _grid(W, H)
+    X += x0
+    Y += y0
+
+    def smooth(freqs, phases, amps, XX, YY):
+        v = np.zeros_like(XX)
+        for k in range(len(phases)):
+            v += amps[k] * np.sin(2.0 * math.pi * (freqs[k, 0] * XX + freqs[k, 1] * YY) + phases[k])
+        return v
+
+    # maxima over the whole image from a coarse grid of it (so that every window
+    # uses the same scale factors)
+    Xc, Yc = np.meshgrid(np.linspace(0.0, FW - 1.0, 257), np.linspace(0.0, FH - 1.0, 136))
+    wc = np.hypot(smooth(fw[0], fp[0], fa[0], Xc, Yc), smooth(fw[1], fp[1], fa[1], Xc, Yc))
+    ws = 8.0 / float(np.max(wc))
+    gc = smooth(gw[0], gp[0], np.ones(3), Xc, Yc)
+    oc = smooth(gw[1], gp[1], np.ones(3), Xc, Yc)
+    w1 = ws * smooth(fw[0], fp[0], fa[0], X, Y)
+    w2 = ws * smooth(fw[1], fp[1], fa[1], X, Y)
+    gain = 1.0 + 0.2 * smooth(gw[0], gp[0], np.ones(3), X, Y) / float(np.max(np.abs(gc)))
+    off = 0.2 * 0.5 * smooth(gw[1], gp[1], np.ones(3), X, Y) / float(np.max(np.abs(oc)))
+
+    def texture(XX, YY):
+        if device is not None:
+            import torch
+            tX = torch.as_tensor(XX, dtype=torch.float64, device=device)
+            tY = torch.as_tensor(YY, dtype=torch.float64, device=device)
+            acc = torch.full_like(tX, 0.5)
+            for k in range(nk):
+                acc += c * torch.cos(2.0 * math.pi * (float(om[k, 0]) * tX + float(om[k, 1]) * tY) + float(ph[k]))
+            return acc.cpu().numpy()
+        acc = np.full_like(XX, 0.5)
+        for k in range(nk):
+            acc += c * np.cos(2.0 * math.pi * (om[k, 0] * XX + om[k, 1] * YY) + ph[k])
+        return acc
+
+    I0 = texture(X, Y)
+    I1 = gain * texture(X - w1, Y - w2) + off
+    return Pair(np.ascontiguousarray(I0), np.ascontiguousarray(I1), np.stack([w1, w2]), gain,
+                name=f"prec4k:{seed}:{x0},{y0}:{W}x{H}")
+
+
 def make_pair(kind: str, seed: int, W: int | None = None, H: int | None = None,
               noise: float | None = None) -> Pair:
     """Draw one pair of the named recipe; ``W``/``H`` override the size."""
@@ -131,6 +254,35 @@ def make_pair(kind: str, seed: int, W: int | None = None, H: int | None = None,
         I0 = img(X, Y)
         I1 = gain * img(X - w1, Y - w2)
         sig = 0.01 if noise is None else noise
+    elif kind == "batch1080":
+        W = W or 1920
+        H = H or 1080
+        nb = max(1, round(200 * W * H / (640 * 480)))
+        X, Y = _grid(W, H)
+        img = random_bumps(rng, W, H, nb)
+        w1, w2 = _voronoi_affine_flow(rng, W, H, X, Y, 6, 6.0)
+        gain = _gain_field(rng, W, H, X, Y, 0.15)
+        I0 = _bump_sum_local(img, X, Y)
+        I1 = gain * _bump_sum_local(img, X, Y, w1, w2, pad=6.0)
+        sig = 0.0 if noise is None else noise
+    elif kind == "adj1024":
+        W = W or 1024
+        H = H or 1024
+        nb = max(1, round(200 * W * H / (640 * 480)))
+        X, Y = _grid(W, H)
+        img = random_bumps(rng, W, H, nb)
+        t = rng.uniform(-1.0, 1.0, 2)
+        J = rng.uniform(-0.004, 0.004, (2, 2))
+        xc, yc = (W - 1) / 2.0, (H - 1) / 2.0
+        w1 = t[0] + J[0, 0] * (X - xc) + J[0, 1] * (Y - yc)
+        w2 = t[1] + J[1, 0] * (X - xc) + J[1, 1] * (Y - yc)
+        mx = np.max(np.hypot(w1, w2))
+        w1 *= 2.0 / mx
+        w2 *= 2.0 / mx
+        gain = _gain_field(rng, W, H, X, Y, 0.1)
+        I0 = _bump_sum_local(img, X, Y)
+        I1 = gain * _bump_sum_local(img, X, Y, w1, w2, pad=2.0)
+        sig = 0.0 if noise is None else noise
     else:
         raise ValueError(f"unknown pair kind {kind!r}")
     if sig > 0.0:

@@ -99,8 +99,14 @@ def test_sigma_bounds():
 def test_memory_bytes_linear_in_batch_and_tile_storage(W, H, px, py, d):
     _ensure_built()
     b1, b2, b5 = (api.sf_memory_bytes(W, H, b, px, py, d) for b in (1, 2, 5))
-    # every pair repeats the same subdomains and fields: exactly affine in the batch
-    assert b5 - b1 == 4 * (b2 - b1) and b2 > b1 > 0
+    # every pair repeats the same subdomains and fields; the factor workspace
+    # is shared by chunks of at most 64 subdomains, so the bytes grow by the
+    # same amount per pair once a batch has 64 subdomains, and never faster
+    assert b5 - b1 <= 4 * (b2 - b1) and b2 > b1 > 0
+    nsub = len(api.sf_plan(W, H, 1, px, py, d))
+    k = -(-64 // nsub)
+    bk, bk1, bk4 = (api.sf_memory_bytes(W, H, b, px, py, d) for b in (k, k + 1, k + 4))
+    assert bk4 - bk == 4 * (bk1 - bk) > 0
     # FP32 tiles halve exactly the inverse Schur tiles: per subdomain, lines x
     # lower tiles of the padded line matrix (32x32 tiles), from the geometry alone
     tile_bytes = 0
@@ -119,7 +125,8 @@ def test_memory_bytes_invalid():
     with pytest.raises(api.SfError):
         api.sf_memory_bytes(0, 10)
     with pytest.raises(api.SfError):
-        api.sf_memory_bytes(180, 171)          # lines of 171 nodes: above the largest line matrix
+        api.sf_memory_bytes(260, 257)          # lines of 257 nodes: above the largest line matrix (768)
+    assert api.sf_memory_bytes(264, 256) > 0    # lines of 256 nodes: the largest
 
 
 def test_library_built_from_the_current_sources():

@@ -1,6 +1,6 @@
 """GPU edge cases through the C ABI against the oracle: the smallest meshes,
 one-pixel-wide parts, overlaps wider than a part, the largest line matrix
-the library takes (and the first one it refuses), and a batch in which one
+the library takes (768 unknowns; and the first one it refuses), and a batch in which one
 pair has nothing to solve."""
 import numpy as np
 import pytest
@@ -69,8 +69,8 @@ def test_small_and_degenerate_meshes(gpu, W, H, px, py, d):
 
 
 def test_largest_line_matrix(gpu):
-    # lines of 170 nodes: m = 510 unknowns, padded to 512, the largest taken
-    W, H = 176, 170
+    # lines of 256 nodes: m = 768 unknowns, the largest taken
+    W, H = 264, 256
     I0, I1 = frames(W, H, 4)
     al = synth.constant_alpha(W, H)
     ctx = api.sf_create(W, H, 1, 1, 1, 0)
@@ -92,9 +92,9 @@ def test_largest_line_matrix(gpu):
 
 
 def test_first_refused_line_matrix(gpu):
-    # lines of 171 nodes would need 513 unknowns per line
+    # lines of 257 nodes would need 771 unknowns per line
     with pytest.raises(api.SfError) as e:
-        api.sf_create(180, 171, 1, 1, 1, 0)
+        api.sf_create(260, 257, 1, 1, 1, 0)
     assert e.value.code == api.SF_ERR_INVALID
 
 

@@ -28,8 +28,10 @@ from paper_1508_02977_amd import api  # noqa: E402
 CASES = {
     "plain64": dict(kind="plain64", seed=1, W=64, H=64, px=2, py=2, d=4),
     "noisy": dict(kind="plain640", seed=3, W=72, H=56, px=3, py=3, d=8),
-    # line matrices above 384 x 384: one-workgroup factor, general sweep
+    # line matrices above 384 x 384 (13 block rows): factor ranks split by column parity
     "wide": dict(kind="plain640", seed=4, W=300, H=136, px=2, py=1, d=8),
+    # 170-node lines (16 block rows): one block row per sweep rank
+    "wider": dict(kind="plain640", seed=6, W=348, H=170, px=2, py=1, d=8),
 }
 
 
@@ -47,7 +49,7 @@ def context(case, precision):
     return p, al, ctx
 
 
-@pytest.mark.parametrize("name", ["plain64", "noisy", "wide"])
+@pytest.mark.parametrize("name", ["plain64", "noisy", "wide", "wider"])
 def test_fp32_local_solves_match_lapack(gpu, name):
     case = CASES[name]
     p, al, ctx = context(case, api.SF_FP32)

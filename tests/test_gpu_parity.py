@@ -22,7 +22,7 @@ CASES = {
     "noisy": dict(kind="plain640", seed=3, W=72, H=56, px=3, py=3, d=8),         # 640x480 recipe, cropped
     "single": dict(kind="plain64", seed=8, W=9, H=12, px=1, py=1, d=0),          # one line tile (m <= 32)
 }
-# line matrices above 384 x 384 take the one-workgroup factorisation
+# line matrices above 384 x 384 (13 block rows): the factor's ranks split by column parity
 WIDE = dict(kind="plain640", seed=4, W=300, H=136, px=2, py=1, d=8)
 
 
