@@ -275,6 +275,11 @@ def _cpu_sample(pair, alpha0, sweeps_total, solves, updates, np, adapt, fem, sch
                 measured_s=round(t4 - t0, 2))
 
 
+def _progress(msg):
+    """A progress line on stderr (stdout carries only the JSON record)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
 def _timed(fn):
     """Wall time of fn() between two device synchronisations, in ms."""
     import torch
@@ -300,6 +305,7 @@ def other_workload(args, api, synth, torch, np, dev):
         t0 = time.perf_counter()
         pairs = [synth.make_pair("batch1080", 3000 + i) for i in range(N)]
         gen_s = time.perf_counter() - t0
+        _progress(f"batch1080: {N} pairs generated in {gen_s:.1f} s")
         I0 = torch.tensor(np.stack([q.I0 for q in pairs]), dtype=torch.float64, device=dev)
         I1 = torch.tensor(np.stack([q.I1 for q in pairs]), dtype=torch.float64, device=dev)
         del pairs
@@ -318,6 +324,7 @@ def other_workload(args, api, synth, torch, np, dev):
         api.sf_factor_subdomains(c1)
         band = api.sf_autotune(c1, torch.zeros((1, 3, Hb, Wb), dtype=torch.float64, device=dev), 2)
         c1.close()
+        _progress(f"batch1080: waves of {wave} pairs, autotuned {band} sweep workgroups per chain")
         ms_total, sweeps, rel, nsub = 0.0, [], [], 0
         prof = {}
         for s0 in range(0, N, wave):
@@ -333,6 +340,7 @@ def other_workload(args, api, synth, torch, np, dev):
                 api.sf_factor_subdomains(ctx)
                 return api.sf_schwarz_solve_graph(ctx, Ub, RTOL, MAX_SWEEPS)
             ms, (code, sw, rr) = _timed(job)
+            _progress(f"batch1080: pairs {s0}..{s1 - 1} in {ms:.0f} ms, sweeps {min(sw)}..{max(sw)}")
             ms_total += ms
             sweeps += sw
             rel += rr
@@ -372,6 +380,7 @@ def other_workload(args, api, synth, torch, np, dev):
                 api.sf_factor_subdomains(ctx)
                 return api.sf_schwarz_solve(ctx, U, RTOL, MAX_SWEEPS)
             ms, (code, sw, rr) = _timed(job)
+            _progress(f"prec4k: precision {prec}: {ms:.0f} ms, {sw[0]} sweeps, relres {rr[0]:.2e}")
             prof = {k: v[0] for k, v in api.sf_profile(ctx, 0).items()}
             forms[prec] = dict(ms=ms, sweeps=sw[0], relres=rr[0], U=U, prof=prof)
             if prec == api.SF_FP64:
@@ -427,6 +436,7 @@ def other_workload(args, api, synth, torch, np, dev):
             loss.backward()
             return loss.detach()
         ms, loss = _timed(job)
+        _progress(f"adj1024: precision {prec}: {ms:.0f} ms, loss {float(loss):.6f}")
         res[prec] = dict(ms=ms, loss=float(loss), g=[I0g.grad, I1g.grad, Ag.grad])
         ctx.close()
     g32, g64 = res[api.SF_FP32]["g"], res[api.SF_FP64]["g"]
