@@ -73,6 +73,14 @@ typedef struct sf_config {
                                  rows then columns, clamp to edge)              */
     int32_t factor_precision; /* SF_FP64 or SF_FP32                               */
     int32_t band_tile;        /* sweep workgroups per chain of a subdomain; 0 = auto */
+    double  rho;              /* Gaussian K_rho of the data term (Section 1,
+                                 functionals (BW), (BW2)): A_rho = K_rho * (a a^T),
+                                 F = -K_rho * (a f_t); 0 = off, at most
+                                 SF_SIGMA_MAX.  Read as the sampled normalised
+                                 Gaussian (|k| <= ceil(3 rho)) over whole-pixel
+                                 shifts of the element data, clamp to edge per
+                                 axis, integrated exactly (rho = 0: the plain
+                                 data term)                                     */
 } sf_config;
 
 typedef struct sf_context sf_context;
@@ -91,7 +99,8 @@ void sf_destroy(sf_context* ctx);
 
 /* Section 1 and 2.2: copy I0, I1 and alpha into the context and build the
  * right-hand side F_i = -int f_t a phi_i, a = (f_x, f_y, -f), f = K_sigma * I0
- * (P1), f_t = K_sigma * (I1 - I0) (P1), integrated exactly.  Returns SF_NONFINITE if a frame
+ * (P1), f_t = K_sigma * (I1 - I0) (P1), integrated exactly (with rho > 0,
+ * -int (K_rho * (f_t a)) phi_i, and the smoothed data term of A).  Returns SF_NONFINITE if a frame
  * value is not finite and SF_ERR_INVALID if an alpha is not finite or <= 0.
  * Makes previous factors stale.                                             */
 int sf_assemble(sf_context* ctx, const double* I0, const double* I1, const double* alpha);
@@ -154,7 +163,7 @@ int sf_autotune(sf_context* ctx, double* U, int32_t trials, int32_t* band_tile);
  * dalpha [B][H-1][W-1][2] are device outputs, any may be NULL.  sweeps and
  * relres [B] are HOST arrays or NULL.  Needs current factors
  * (SF_ERR_STATE otherwise); SF_ERR_INVALID when the context presmooths
- * (sigma > 0).  Returns SF_NOT_CONVERGED (gradients still written) like
+ * (sigma > 0) or smooths the data term (rho > 0).  Returns SF_NOT_CONVERGED (gradients still written) like
  * sf_schwarz_solve.                                                       */
 int sf_adjoint(sf_context* ctx, const double* U, const double* G, double* P,
                double* dI0, double* dI1, double* dalpha,

@@ -43,6 +43,7 @@ class sf_config(ctypes.Structure):
         ("parts_x", c_int32), ("parts_y", c_int32), ("overlap", c_int32),
         ("lambda_", c_double), ("sigma", c_double),
         ("factor_precision", c_int32), ("band_tile", c_int32),
+        ("rho", c_double),
     ]
 
 
@@ -200,16 +201,18 @@ class Context:
 
 
 def make_config(width, height, batch=1, parts_x=1, parts_y=1, overlap=0, lam=1.0, sigma=0.0,
-                factor_precision=SF_FP64, band_tile=0) -> sf_config:
-    return sf_config(width, height, batch, parts_x, parts_y, overlap, lam, sigma, factor_precision, band_tile)
+                factor_precision=SF_FP64, band_tile=0, rho=0.0) -> sf_config:
+    return sf_config(width, height, batch, parts_x, parts_y, overlap, lam, sigma, factor_precision, band_tile,
+                     rho)
 
 
 # ---- the C entry points --------------------------------------------------
 
 def sf_create(width, height, batch=1, parts_x=1, parts_y=1, overlap=0, lam=1.0, sigma=0.0,
-              factor_precision=SF_FP64, band_tile=0, stream=None) -> Context:
+              factor_precision=SF_FP64, band_tile=0, stream=None, rho=0.0) -> Context:
     import torch
-    cfg = make_config(width, height, batch, parts_x, parts_y, overlap, lam, sigma, factor_precision, band_tile)
+    cfg = make_config(width, height, batch, parts_x, parts_y, overlap, lam, sigma, factor_precision, band_tile,
+                      rho)
     if stream is None:
         stream = torch.cuda.current_stream()
     h = c_void_p()
@@ -341,9 +344,9 @@ def sf_plan(width, height, batch=1, parts_x=1, parts_y=1, overlap=0, lam=1.0):
 
 
 def sf_memory_bytes(width, height, batch=1, parts_x=1, parts_y=1, overlap=0, lam=1.0, sigma=0.0,
-                    factor_precision=SF_FP64) -> int:
+                    factor_precision=SF_FP64, rho=0.0) -> int:
     """Host-only: device bytes a context of this configuration allocates."""
-    cfg = make_config(width, height, batch, parts_x, parts_y, overlap, lam, sigma, factor_precision)
+    cfg = make_config(width, height, batch, parts_x, parts_y, overlap, lam, sigma, factor_precision, 0, rho)
     out = ctypes.c_int64()
     _check(lib().sf_memory_bytes(ctypes.byref(cfg), ctypes.byref(out)), "sf_memory_bytes")
     return out.value

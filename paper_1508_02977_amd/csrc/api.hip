@@ -85,7 +85,8 @@ int check_config(const sf_config& k) {
     if (k.width < 2 || k.height < 2 || k.batch < 1) return SF_ERR_INVALID;
     if (k.parts_x < 1 || k.parts_y < 1 || k.parts_x > k.width || k.parts_y > k.height) return SF_ERR_INVALID;
     if (k.overlap < 0 || !(k.lambda > 0.0) || !std::isfinite(k.lambda)) return SF_ERR_INVALID;
-    if (!(k.sigma >= 0.0 && k.sigma <= SF_SIGMA_MAX) || (k.factor_precision != SF_FP64 && k.factor_precision != SF_FP32) ||
+    if (!(k.sigma >= 0.0 && k.sigma <= SF_SIGMA_MAX) || !(k.rho >= 0.0 && k.rho <= SF_SIGMA_MAX) ||
+        (k.factor_precision != SF_FP64 && k.factor_precision != SF_FP32) ||
         k.band_tile < 0)
         return SF_ERR_INVALID;
     if ((int64_t)k.width * k.height * k.batch > (1ll << 31)) return SF_ERR_INVALID;
@@ -210,7 +211,7 @@ void sf_destroy(sf_context* c) {
     if (!c) return;
     void* ptrs[] = {c->d_subs, c->f0, c->ft, c->alpha, c->F, c->r, c->eta, c->Fn2, c->Gn2,
                     c->partials, c->relres_d, c->sweeps_d, c->done_d, c->counters, c->etamax_bits,
-                    c->flags_d, c->factors, c->work, c->status_d, c->blur_w};
+                    c->flags_d, c->factors, c->work, c->status_d, c->blur_w, c->clg_w, c->coef, c->clg_tmp};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (c->host_stage) (void)hipHostFree(c->host_stage);
@@ -261,6 +262,8 @@ static int64_t field_bytes(const sf_config& k, int64_t nsub) {
     int64_t bytes = d * 8 + (int64_t)sizeof(SubDesc) * nsub;
     bytes += 4 * (2 * B) + 8 * B + 4 * (2 * sfdd::F2_COUNTERS * nsub) + 16 + sizeof(sfdd::DevStatus);
     if (k.sigma > 0.0) bytes += 8 * (2 * (int64_t)std::ceil(3.0 * k.sigma) + 1);   // blur weights
+    if (k.rho > 0.0)                                    // K_rho weights, coefficient planes and first-pass sums
+        bytes += 8 * (2 * (int64_t)std::ceil(3.0 * k.rho) + 1) + 2 * 8 * (int64_t)sfdd::CLG_COEFS * ne * B;
     return bytes;
 }
 
@@ -415,17 +418,29 @@ int sf_create(const sf_config* cfg, void* stream, sf_context** out) {
     rc |= dalloc(&c->factors, (size_t)c->factor_doubles);
     rc |= dalloc(&c->work, (size_t)c->work_doubles);
     rc |= dalloc(&c->status_d, 1);
-    // presmoothing weights (Section 1): sampled Gaussian, |k| <= ceil(3 sigma), normalised
-    std::vector<double> bw;
-    if (k.sigma > 0.0) {
-        c->blur_r = (int)std::ceil(3.0 * k.sigma);
+    // presmoothing weights K_sigma and data-term weights K_rho (Section 1):
+    // sampled Gaussian, |k| <= ceil(3 s), normalised
+    auto gauss = [](double sg, int* r) {
+        std::vector<double> w;
+        *r = (int)std::ceil(3.0 * sg);
         double sum = 0.0;
-        for (int i = -c->blur_r; i <= c->blur_r; ++i) {
-            bw.push_back(std::exp(-(double)i * i / (2.0 * k.sigma * k.sigma)));
-            sum += bw.back();
+        for (int i = -*r; i <= *r; ++i) {
+            w.push_back(std::exp(-(double)i * i / (2.0 * sg * sg)));
+            sum += w.back();
         }
-        for (auto& v : bw) v /= sum;
+        for (auto& v : w) v /= sum;
+        return w;
+    };
+    std::vector<double> bw, cw;
+    if (k.sigma > 0.0) {
+        bw = gauss(k.sigma, &c->blur_r);
         rc |= dalloc(&c->blur_w, bw.size());
+    }
+    if (k.rho > 0.0) {
+        cw = gauss(k.rho, &c->clg_r);
+        rc |= dalloc(&c->clg_w, cw.size());
+        rc |= dalloc(&c->coef, (size_t)sfdd::CLG_COEFS * ne * c->B);
+        rc |= dalloc(&c->clg_tmp, (size_t)sfdd::CLG_COEFS * ne * c->B);
     }
     if (rc != SF_OK) { sf_destroy(c); return SF_ERR_OOM; }
     const size_t stage = STAGE_A + 24 * (size_t)c->B + 64;
@@ -448,9 +463,12 @@ int sf_create(const sf_config* cfg, void* stream, sf_context** out) {
     }
     c->sweep_epoch = 1;
     c->factor_epoch = 1;
-    if (!bw.empty() &&
-        hipMemcpyAsync(c->blur_w, bw.data(), bw.size() * sizeof(double), hipMemcpyHostToDevice, c->stream) !=
-            hipSuccess) {
+    if ((!bw.empty() &&
+         hipMemcpyAsync(c->blur_w, bw.data(), bw.size() * sizeof(double), hipMemcpyHostToDevice, c->stream) !=
+             hipSuccess) ||
+        (!cw.empty() &&
+         hipMemcpyAsync(c->clg_w, cw.data(), cw.size() * sizeof(double), hipMemcpyHostToDevice, c->stream) !=
+             hipSuccess)) {
         sf_destroy(c);
         return SF_ERR_HIP;
     }
@@ -490,6 +508,8 @@ int sf_assemble(sf_context* c, const double* I0, const double* I1, const double*
     } else {
         SF_TRY(sfdd::launch_assemble(c, I0, I1, alpha));
     }
+    // K_rho data term: coefficient planes from the (smoothed) frames, then F
+    if (c->coef) SF_TRY(sfdd::launch_clg(c));
     SF_TRY(sfdd::prof_end(c));
     c->state = ST_ASSEMBLED;
     return SF_OK;
@@ -763,7 +783,8 @@ int sf_autotune(sf_context* c, double* U, int32_t trials, int32_t* band_tile) {
 int sf_adjoint(sf_context* c, const double* U, const double* G, double* P, double* dI0, double* dI1, double* dalpha,
                double rtol, int32_t max_sweeps, int32_t* sweeps, double* relres) {
     if (!c || !U || !G || !P || max_sweeps < 0 || !(rtol >= 0.0)) return SF_ERR_INVALID;
-    if (c->blur_r > 0) return SF_ERR_INVALID;   // gradients are taken with respect to unsmoothed frames
+    // gradients are taken with respect to unsmoothed frames and the plain data term
+    if (c->blur_r > 0 || c->coef) return SF_ERR_INVALID;
     if (c->state != ST_FACTORED) return SF_ERR_STATE;
     SF_TRY(sfdd::launch_norm2(c, G, c->Gn2));
     const int rc = schwarz_loop(c, P, G, c->Gn2, rtol, max_sweeps, sweeps, relres);

@@ -92,7 +92,7 @@ __device__ void set_status(DevStatus* st, int code, int sub, int64_t row) {
 __global__ void __launch_bounds__(FACTOR_THREADS)
 k_factor(const SubDesc* __restrict__ subs, const double* __restrict__ f0_all, const double* __restrict__ al_all,
          double* __restrict__ factors, double* __restrict__ work, DevStatus* __restrict__ status,
-         int W, int H, double lam, int fp32, int sub0) {
+         int W, int H, double lam, int fp32, int sub0, const double* __restrict__ coef_all) {
     const int sub = sub0 + blockIdx.x;
     const SubDesc d = subs[sub];
     const int tid = threadIdx.x, wv = tid >> 6, nw = FACTOR_THREADS / 64;
@@ -100,6 +100,7 @@ k_factor(const SubDesc* __restrict__ subs, const double* __restrict__ f0_all, co
     const int64_t nn = (int64_t)W * H, ne = (int64_t)(W - 1) * (H - 1) * 2;
     const double* f0 = f0_all + d.pair * nn;
     const double* al = al_all + d.pair * ne;
+    const double* cf = coef_all ? coef_all + (int64_t)d.pair * CLG_NCOEF * ne : nullptr;   // K_rho data term
     double* S = work + d.soff;                 // mp x mp: S_t, then its Cholesky factor
     double* Y = S + (int64_t)mp * mp;          // mp x mp: B P, then D^{-1}
     double* Pv = Y + (int64_t)mp * mp;         // mp x mp: S_{t-1}^{-1}, full symmetric
@@ -124,12 +125,12 @@ k_factor(const SubDesc* __restrict__ subs, const double* __restrict__ f0_all, co
             int x, y;
             local_to_global(d, t, s, x, y);
             double blk[9];
-            stencil_block(f0, al, W, H, x, y, 0, 0, lam, blk);
+            stencil_block(f0, al, W, H, x, y, 0, 0, lam, blk, cf);
             for (int c = 0; c < 3; ++c)
                 for (int e = 0; e < 3; ++e) S[(3 * s + c) * mp + 3 * s + e] = blk[3 * c + e];
             if (s + 1 < ms) {   // next node along the line
-                if (d.cols) stencil_block(f0, al, W, H, x, y, 0, 1, lam, blk);
-                else        stencil_block(f0, al, W, H, x, y, 1, 0, lam, blk);
+                if (d.cols) stencil_block(f0, al, W, H, x, y, 0, 1, lam, blk, cf);
+                else        stencil_block(f0, al, W, H, x, y, 1, 0, lam, blk, cf);
                 for (int c = 0; c < 3; ++c)
                     for (int e = 0; e < 3; ++e) {
                         S[(3 * s + c) * mp + 3 * (s + 1) + e] = blk[3 * c + e];
@@ -143,12 +144,12 @@ k_factor(const SubDesc* __restrict__ subs, const double* __restrict__ f0_all, co
                 int px, py;
                 local_to_global(d, t - 1, s, px, py);
                 double bs[9], bd[9];
-                if (d.cols) stencil_block(f0, al, W, H, px, py, 1, 0, lam, bs);
-                else        stencil_block(f0, al, W, H, px, py, 0, 1, lam, bs);
+                if (d.cols) stencil_block(f0, al, W, H, px, py, 1, 0, lam, bs, cf);
+                else        stencil_block(f0, al, W, H, px, py, 0, 1, lam, bs, cf);
                 if (s > 0) {
                     int qx, qy;
                     local_to_global(d, t - 1, s - 1, qx, qy);
-                    stencil_block(f0, al, W, H, qx, qy, 1, 1, lam, bd);
+                    stencil_block(f0, al, W, H, qx, qy, 1, 1, lam, bd, cf);
                 } else {
                     for (int k = 0; k < 9; ++k) bd[k] = 0.0;
                 }
@@ -323,7 +324,7 @@ int launch_factor(sf_context* c) {
         const int n = std::min(c->factor_chunk, c->nsub - s0);
         hipLaunchKernelGGL(k_factor, dim3(n), dim3(FACTOR_THREADS), 0, c->stream, c->d_subs, c->f0, c->alpha,
                            c->factors, c->work, c->status_d, c->W, c->H, c->cfg.lambda,
-                           c->cfg.factor_precision == SF_FP32 ? 1 : 0, s0);
+                           c->cfg.factor_precision == SF_FP32 ? 1 : 0, s0, (const double*)c->coef);
         if (hipGetLastError() != hipSuccess) return SF_ERR_HIP;
     }
     return SF_OK;

@@ -116,7 +116,7 @@ struct FactorArgs {
 // coupling rows B_t[3s+c][.] (6 doubles per row, boff + (t*m + 3s+c)*6).
 __global__ void k_line_coeffs(const SubDesc* __restrict__ subs, const double* __restrict__ f0_all,
                               const double* __restrict__ al_all, double* __restrict__ factors, int W, int H,
-                              double lam, int sub0) {
+                              double lam, int sub0, const double* __restrict__ coef_all) {
     const SubDesc d = subs[sub0 + blockIdx.y];
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (int64_t)d.nt * d.ms) return;
@@ -124,15 +124,16 @@ __global__ void k_line_coeffs(const SubDesc* __restrict__ subs, const double* __
     const int64_t nn = (int64_t)W * H, ne = (int64_t)(W - 1) * (H - 1) * 2;
     const double* f0 = f0_all + d.pair * nn;
     const double* al = al_all + d.pair * ne;
+    const double* cf = coef_all ? coef_all + (int64_t)d.pair * CLG_NCOEF * ne : nullptr;   // K_rho data term
     double* Ab = factors + d.aoff + idx * 18;
     int x, y;
     local_to_global(d, t, s, x, y);
     double blk[9];
-    stencil_block(f0, al, W, H, x, y, 0, 0, lam, blk);
+    stencil_block(f0, al, W, H, x, y, 0, 0, lam, blk, cf);
     for (int k = 0; k < 9; ++k) Ab[k] = blk[k];
     if (s + 1 < d.ms) {
-        if (d.cols) stencil_block(f0, al, W, H, x, y, 0, 1, lam, blk);
-        else        stencil_block(f0, al, W, H, x, y, 1, 0, lam, blk);
+        if (d.cols) stencil_block(f0, al, W, H, x, y, 0, 1, lam, blk, cf);
+        else        stencil_block(f0, al, W, H, x, y, 1, 0, lam, blk, cf);
     } else {
         for (int k = 0; k < 9; ++k) blk[k] = 0.0;
     }
@@ -141,12 +142,12 @@ __global__ void k_line_coeffs(const SubDesc* __restrict__ subs, const double* __
         int px, py;
         local_to_global(d, t - 1, s, px, py);
         double bs[9], bd[9];
-        if (d.cols) stencil_block(f0, al, W, H, px, py, 1, 0, lam, bs);
-        else        stencil_block(f0, al, W, H, px, py, 0, 1, lam, bs);
+        if (d.cols) stencil_block(f0, al, W, H, px, py, 1, 0, lam, bs, cf);
+        else        stencil_block(f0, al, W, H, px, py, 0, 1, lam, bs, cf);
         if (s > 0) {
             int qx, qy;
             local_to_global(d, t - 1, s - 1, qx, qy);
-            stencil_block(f0, al, W, H, qx, qy, 1, 1, lam, bd);
+            stencil_block(f0, al, W, H, qx, qy, 1, 1, lam, bd, cf);
         } else {
             for (int k = 0; k < 9; ++k) bd[k] = 0.0;
         }
@@ -957,7 +958,7 @@ int launch_line_coeffs(sf_context* c) {
     int maxn = 0;
     for (const auto& d : c->subs) maxn = std::max(maxn, d.nt * d.ms);
     hipLaunchKernelGGL(k_line_coeffs, dim3((maxn + 255) / 256, c->nsub), dim3(256), 0, c->stream, c->d_subs, c->f0,
-                       c->alpha, c->factors, c->W, c->H, c->cfg.lambda, 0);
+                       c->alpha, c->factors, c->W, c->H, c->cfg.lambda, 0, (const double*)c->coef);
     return hipGetLastError() == hipSuccess ? SF_OK : SF_ERR_HIP;
 }
 

@@ -95,10 +95,12 @@ __global__ void k_finalize_norm(const double* __restrict__ partials, int npart, 
 }
 
 // r = F - A U and ||r||^2 partials; pairs already converged are skipped.
+template <bool CLG>
 __global__ void k_residual(const double* __restrict__ f0, const double* __restrict__ al,
                            const double* __restrict__ F, const double* __restrict__ U,
                            double* __restrict__ r, double* __restrict__ partials, int npart,
-                           int W, int H, double lam, const int32_t* __restrict__ done) {
+                           int W, int H, double lam, const int32_t* __restrict__ done,
+                           const double* __restrict__ coef) {
     __shared__ double sh[NODE_THREADS / 64];
     const int pair = blockIdx.y;
     if (done != nullptr && done[pair]) {
@@ -121,7 +123,6 @@ __global__ void k_residual(const double* __restrict__ f0, const double* __restri
             const Around a = around(k);
             const int cx = x + a.dcx, cy = y + a.dcy;
             if (cx < 0 || cy < 0 || cx >= W - 1 || cy >= H - 1) continue;
-            Elem e = load_elem(fp, ap, W, H, cx, cy, a.t);
             double u[3][3];
 #pragma unroll
             for (int v = 0; v < 3; ++v) {
@@ -130,7 +131,14 @@ __global__ void k_residual(const double* __restrict__ f0, const double* __restri
                 for (int c = 0; c < 3; ++c) u[v][c] = Up[c * nn + n];
             }
             double o[3];
-            elem_apply_row(e, a.t, a.v, u, lam, o);
+            if constexpr (CLG) {
+                const ElemC e = load_elem_c(coef + (int64_t)pair * CLG_NCOEF * ne, ap, ne,
+                                            ((int64_t)cy * (W - 1) + cx) * 2 + a.t);
+                elemc_apply_row(e, a.t, a.v, u, lam, o);
+            } else {
+                Elem e = load_elem(fp, ap, W, H, cx, cy, a.t);
+                elem_apply_row(e, a.t, a.v, u, lam, o);
+            }
             out[0] -= o[0];
             out[1] -= o[1];
             out[2] -= o[2];
@@ -175,6 +183,101 @@ __global__ void k_converge(const double* __restrict__ partials, int npart, const
     }
 }
 
+// --- smoothed data term K_rho (Section 1) ---------------------------------
+//
+// The 30 coefficient planes of every element (element.h): the weighted sums
+// over whole-pixel shifts s of the products of the shifted element's data,
+// K - s of the same type, the cell index clamped to the cell grid per axis.
+// The weights are separable, so the sums run in two passes: along x (the
+// products formed on the fly from f0 and ft) into tmp, then along y into coef.
+// Both arrays are [B][CLG_NCOEF][ne].
+
+__device__ __forceinline__ void elem_products(const double* __restrict__ fp, const double* __restrict__ tp, int W,
+                                              int cx, int cy, int t, double q[CLG_NCOEF]) {
+    double f[3], ft[3], gx, gy;
+#pragma unroll
+    for (int v = 0; v < 3; ++v) {
+        const int64_t n = (int64_t)(cy + vdy(t, v)) * W + cx + vdx(t, v);
+        f[v] = fp[n];
+        ft[v] = tp[n];
+    }
+    elem_grad(t, f, gx, gy);
+    clg_products(f, gx, gy, ft, q);
+}
+
+__global__ void k_clg_smooth_x(const double* __restrict__ f0, const double* __restrict__ ft,
+                               const double* __restrict__ w, int r, double* __restrict__ tmp, int W, int H) {
+    const int pair = blockIdx.y;
+    const int64_t nn = (int64_t)W * H, ne = (int64_t)(W - 1) * (H - 1) * 2;
+    const int64_t e_id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e_id >= ne) return;
+    const int t = (int)(e_id & 1), cell = (int)(e_id >> 1);
+    const int cx = cell % (W - 1), cy = cell / (W - 1);
+    double acc[CLG_NCOEF];
+#pragma unroll
+    for (int q = 0; q < CLG_NCOEF; ++q) acc[q] = 0.0;
+    for (int k = -r; k <= r; ++k) {
+        const int sx = min(max(cx - k, 0), W - 2);
+        double q[CLG_NCOEF];
+        elem_products(f0 + pair * nn, ft + pair * nn, W, sx, cy, t, q);
+        const double wk = w[k + r];
+#pragma unroll
+        for (int i = 0; i < CLG_NCOEF; ++i) acc[i] = fma(wk, q[i], acc[i]);
+    }
+    double* out = tmp + (int64_t)pair * CLG_NCOEF * ne + e_id;
+#pragma unroll
+    for (int q = 0; q < CLG_NCOEF; ++q) out[(int64_t)q * ne] = acc[q];
+}
+
+__global__ void k_clg_smooth_y(const double* __restrict__ tmp, const double* __restrict__ w, int r,
+                               double* __restrict__ coef, int W, int H) {
+    const int pair = blockIdx.z, q = blockIdx.y;
+    const int64_t ne = (int64_t)(W - 1) * (H - 1) * 2;
+    const int64_t e_id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e_id >= ne) return;
+    const int64_t row = 2 * (int64_t)(W - 1);            // elements per cell row
+    const int cy = (int)(e_id / row);
+    const double* in = tmp + ((int64_t)pair * CLG_NCOEF + q) * ne + (e_id - cy * row);
+    double acc = 0.0;
+    for (int k = -r; k <= r; ++k) {
+        const int sy = min(max(cy - k, 0), H - 2);
+        acc = fma(w[k + r], in[sy * row], acc);
+    }
+    coef[((int64_t)pair * CLG_NCOEF + q) * ne + e_id] = acc;
+}
+
+// F with the smoothed data (replaces k_assemble's F) and ||F||^2 partials.
+__global__ void k_clg_rhs(const double* __restrict__ coef, const double* __restrict__ al, double* __restrict__ F,
+                          double* __restrict__ partials, int npart, int W, int H) {
+    __shared__ double sh[NODE_THREADS / 64];
+    const int pair = blockIdx.y;
+    const int64_t nn = (int64_t)W * H, ne = (int64_t)(W - 1) * (H - 1) * 2;
+    const int node = blockIdx.x * blockDim.x + threadIdx.x;
+    double acc = 0.0;
+    if (node < nn) {
+        const int x = node % W, y = node / W;
+        double out[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            const Around a = around(k);
+            const int cx = x + a.dcx, cy = y + a.dcy;
+            if (cx < 0 || cy < 0 || cx >= W - 1 || cy >= H - 1) continue;
+            const ElemC e = load_elem_c(coef + (int64_t)pair * CLG_NCOEF * ne, al + pair * ne, ne,
+                                        ((int64_t)cy * (W - 1) + cx) * 2 + a.t);
+            double o[3];
+            elemc_rhs_row(e, a.v, o);
+            out[0] += o[0];
+            out[1] += o[1];
+            out[2] += o[2];
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) F[(pair * 3 + c) * nn + node] = out[c];
+        acc = out[0] * out[0] + out[1] * out[1] + out[2] * out[2];
+    }
+    double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) partials[pair * npart + blockIdx.x] = s;
+}
+
 // --- residual error indicator (Section 2.3) -------------------------------
 //
 // eta_K = alpha_K^{-1/2} h_K |grad f| (int_K (s + f_t)^2)^{1/2}
@@ -204,7 +307,8 @@ __device__ void elem_flux(const double* __restrict__ Up, int64_t nn, int W, int 
 
 __global__ void k_indicator(const double* __restrict__ f0, const double* __restrict__ ft,
                             const double* __restrict__ al, const double* __restrict__ U,
-                            double* __restrict__ eta, uint64_t* __restrict__ etamax_bits, int W, int H) {
+                            double* __restrict__ eta, uint64_t* __restrict__ etamax_bits, int W, int H,
+                            const double* __restrict__ coef) {
     const int pair = blockIdx.y;
     const int64_t nn = (int64_t)W * H, ne = (int64_t)(W - 1) * (H - 1) * 2;
     const int64_t e_id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -247,6 +351,33 @@ __global__ void k_indicator(const double* __restrict__ f0, const double* __restr
     quad *= 0.5;
     const double sq2 = 1.4142135623730951;
     double res = sq2 * sqrt((e.gx * e.gx + e.gy * e.gy) * quad) / sqrt(e.al);
+    if (coef) {
+        // smoothed data: R_c = sum_d G_cd u_d - m sum_k GF_ck phi_k + sum_k GT_ck phi_k
+        // (c = x, y), int_K R_x^2 + R_y^2 by the same rule
+        const ElemC ec = load_elem_c(coef + (int64_t)pair * CLG_NCOEF * ne, ap, ne, e_id);
+        double qc = 0.0;
+        for (int g = 0; g < 2; ++g) {
+            const double a = qa[g], b = 1.0 - 2.0 * a;
+            for (int p = 0; p < 3; ++p) {
+                double l[3] = {a, a, a};
+                l[p] = b;
+                double u1 = 0.0, u2 = 0.0, m = 0.0, gf0 = 0.0, gf1 = 0.0, gt0 = 0.0, gt1 = 0.0;
+                for (int v = 0; v < 3; ++v) {
+                    u1 = fma(l[v], uv[v][0], u1);
+                    u2 = fma(l[v], uv[v][1], u2);
+                    m = fma(l[v], uv[v][2], m);
+                    gf0 = fma(l[v], ec.GF[0][v], gf0);
+                    gf1 = fma(l[v], ec.GF[1][v], gf1);
+                    gt0 = fma(l[v], ec.GT[0][v], gt0);
+                    gt1 = fma(l[v], ec.GT[1][v], gt1);
+                }
+                const double r0 = ec.G[0] * u1 + ec.G[1] * u2 - gf0 * m + gt0;
+                const double r1 = ec.G[1] * u1 + ec.G[2] * u2 - gf1 * m + gt1;
+                qc = fma(qw[g], r0 * r0 + r1 * r1, qc);
+            }
+        }
+        res = sq2 * sqrt(0.5 * qc) / sqrt(e.al);
+    }
     // flux jumps over the three edges
     double fin[2][2];
     elem_flux(Up, nn, W, cx, cy, t, e.al, fin);
@@ -506,6 +637,28 @@ int launch_validate(sf_context* c, const double* I0, const double* I1, const dou
     return SF_OK;
 }
 
+static_assert(CLG_NCOEF == CLG_COEFS, "coefficient planes of the smoothed data term");
+
+// K_rho data term: the coefficient planes of every element (two separable
+// passes over the shifts), then F from them and ||F||^2.
+int launch_clg(sf_context* c) {
+    const int64_t ne = (int64_t)(c->W - 1) * (c->H - 1) * 2, nn = (int64_t)c->W * c->H;
+    const unsigned eb = (unsigned)((ne + 255) / 256);
+    hipLaunchKernelGGL(k_clg_smooth_x, dim3(eb, c->B), dim3(256), 0, c->stream, c->f0, c->ft, c->clg_w, c->clg_r,
+                       c->clg_tmp, c->W, c->H);
+    SF_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_clg_smooth_y, dim3(eb, CLG_NCOEF, c->B), dim3(256), 0, c->stream, c->clg_tmp, c->clg_w,
+                       c->clg_r, c->coef, c->W, c->H);
+    SF_LAUNCH_CHECK();
+    dim3 grid((unsigned)((nn + NODE_THREADS - 1) / NODE_THREADS), c->B);
+    hipLaunchKernelGGL(k_clg_rhs, grid, dim3(NODE_THREADS), 0, c->stream, c->coef, c->alpha, c->F, c->partials,
+                       c->npart, c->W, c->H);
+    SF_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_finalize_norm, dim3(c->B), dim3(64), 0, c->stream, c->partials, c->npart, c->Fn2);
+    SF_LAUNCH_CHECK();
+    return SF_OK;
+}
+
 int launch_assemble(sf_context* c, const double* I0, const double* I1, const double* alpha) {
     const int64_t nn = (int64_t)c->W * c->H;
     dim3 grid((unsigned)((nn + NODE_THREADS - 1) / NODE_THREADS), c->B);
@@ -523,9 +676,13 @@ int launch_residual(sf_context* c, const double* U, double* r, int fuse_converge
     if (!rhs_n2) rhs_n2 = c->Fn2;
     const int64_t nn = (int64_t)c->W * c->H;
     dim3 grid((unsigned)((nn + NODE_THREADS - 1) / NODE_THREADS), c->B);
-    hipLaunchKernelGGL(k_residual, grid, dim3(NODE_THREADS), 0, c->stream, c->f0, c->alpha, rhs, U, r,
-                       c->partials, c->npart, c->W, c->H, c->cfg.lambda,
-                       fuse_converge ? (const int32_t*)c->done_d : (const int32_t*)nullptr);
+    const int32_t* done = fuse_converge ? (const int32_t*)c->done_d : (const int32_t*)nullptr;
+    if (c->coef)
+        hipLaunchKernelGGL(k_residual<true>, grid, dim3(NODE_THREADS), 0, c->stream, c->f0, c->alpha, rhs, U, r,
+                           c->partials, c->npart, c->W, c->H, c->cfg.lambda, done, (const double*)c->coef);
+    else
+        hipLaunchKernelGGL(k_residual<false>, grid, dim3(NODE_THREADS), 0, c->stream, c->f0, c->alpha, rhs, U, r,
+                           c->partials, c->npart, c->W, c->H, c->cfg.lambda, done, (const double*)nullptr);
     SF_LAUNCH_CHECK();
     if (fuse_converge) {
         hipLaunchKernelGGL(k_converge, dim3(c->B), dim3(NODE_THREADS), 0, c->stream, c->partials, c->npart,
@@ -583,8 +740,12 @@ int64_t scratch_residual_doubles(const sf_context* c) { return (int64_t)c->B * c
 int launch_residual_scratch(sf_context* c, const double* U, double* r, double* scr) {
     const int64_t nn = (int64_t)c->W * c->H;
     dim3 grid((unsigned)((nn + NODE_THREADS - 1) / NODE_THREADS), c->B);
-    hipLaunchKernelGGL(k_residual, grid, dim3(NODE_THREADS), 0, c->stream, c->f0, c->alpha, c->F, U, r, scr,
-                       c->npart, c->W, c->H, c->cfg.lambda, (const int32_t*)nullptr);
+    if (c->coef)
+        hipLaunchKernelGGL(k_residual<true>, grid, dim3(NODE_THREADS), 0, c->stream, c->f0, c->alpha, c->F, U, r,
+                           scr, c->npart, c->W, c->H, c->cfg.lambda, (const int32_t*)nullptr, (const double*)c->coef);
+    else
+        hipLaunchKernelGGL(k_residual<false>, grid, dim3(NODE_THREADS), 0, c->stream, c->f0, c->alpha, c->F, U, r,
+                           scr, c->npart, c->W, c->H, c->cfg.lambda, (const int32_t*)nullptr, (const double*)nullptr);
     SF_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_finalize_norm, dim3(c->B), dim3(64), 0, c->stream, scr, c->npart,
                        scr + (int64_t)c->B * c->npart);
@@ -600,7 +761,7 @@ int launch_indicator(sf_context* c, const double* U, double* eta, int reset_max)
     }
     dim3 grid((unsigned)((ne + 255) / 256), c->B);
     hipLaunchKernelGGL(k_indicator, grid, dim3(256), 0, c->stream, c->f0, c->ft, c->alpha, U, eta,
-                       c->etamax_bits, c->W, c->H);
+                       c->etamax_bits, c->W, c->H, (const double*)c->coef);
     SF_LAUNCH_CHECK();
     return SF_OK;
 }

@@ -14,6 +14,7 @@ constexpr int TSZ = TS * TS;    // doubles per tile
 constexpr int FACTOR_THREADS = 256;
 constexpr int FACTOR_WS_SLOTS = 64;  // factor workspaces: subdomains per factor launch at most
 constexpr int F2_MAX_NT = 24;        // cooperative factor: line matrices up to 768 x 768
+constexpr int CLG_COEFS = 30;        // smoothed data-term coefficients per element (element.h)
 
 // One subdomain: a box of the pixel grid cut into lines along its shorter side.
 //   lines are columns (cols = 1): line t = x - bx0, position s = y - by0
@@ -74,6 +75,10 @@ struct sf_context {
     uint32_t factor_epoch;          // tag base for the factor's pivot blocks and inverses
     double* blur_w;                 // presmoothing weights, 2 blur_r + 1 (sigma > 0)
     int blur_r;
+    double* clg_w;                  // K_rho weights, 2 clg_r + 1 (rho > 0)
+    int clg_r;
+    double* coef;                   // [B][30][ne] smoothed data-term coefficients (rho > 0), else null
+    double* clg_tmp;                // [B][30][ne] first-pass sums (rho > 0)
     // per-pair field data
     double *f0, *ft, *alpha;        // [B][H][W], [B][H][W], [B][H-1][W-1][2]
     double *F, *r;                  // [B][3][H][W]
@@ -120,6 +125,7 @@ namespace sfdd {
 int launch_validate(sf_context* c, const double* I0, const double* I1, const double* alpha);
 int launch_assemble(sf_context* c, const double* I0, const double* I1, const double* alpha);
 int launch_presmooth(sf_context* c, const double* I, double* out, double* tmp);
+int launch_clg(sf_context* c);
 int launch_residual(sf_context* c, const double* U, double* r, int fuse_converge, double rtol, int sweep,
                     int max_sweeps, const double* rhs = nullptr, const double* rhs_n2 = nullptr);
 int launch_norm2(sf_context* c, const double* G, double* out);
