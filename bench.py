@@ -30,15 +30,23 @@ KAPPA, ETA_THR, ALPHA_TH = 1.0, 0.1, 1e-3
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sweep_plain640_traffic.txt")
 SWEEP_SOURCES = ("paper_1508_02977_amd/csrc/solve.hip", "paper_1508_02977_amd/csrc/sfdd_internal.h")
+FACTOR_MFMA_FILE = os.path.join(ROOT, "profiles", "k_factor2_plain640_mfma.txt")
+FACTOR_SOURCES = ("paper_1508_02977_amd/csrc/factor2.hip", "paper_1508_02977_amd/csrc/factor2_layout.h",
+                  "paper_1508_02977_amd/csrc/element.h", "paper_1508_02977_amd/csrc/sfdd_internal.h")
 
 
 def sweep_source_digest():
     """SHA-256 over the code (comments and blank space removed) of the
     sources the sweep kernel is built from."""
+    return source_digest(SWEEP_SOURCES)
+
+
+def source_digest(sources):
+    """SHA-256 over the code (comments and blank space removed) of `sources`."""
     import hashlib
     import re
     h = hashlib.sha256()
-    for rel in SWEEP_SOURCES:
+    for rel in sources:
         with open(os.path.join(ROOT, rel)) as f:
             code = f.read()
         code = re.sub(r"/\*.*?\*/", " ", code, flags=re.S)
@@ -65,6 +73,27 @@ def measured_traffic():
         if kv.get("sweep_source_sha256") != sweep_source_digest():
             return None
         return float(kv["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def measured_factor_mfma():
+    """MFMA utilisation of k_factor2 (SQ_VALU_MFMA_BUSY_CYCLES over the
+    GUI-active cycles of all SIMDs) and its executed FP64 MFMA flops per
+    launch from the committed counter summary; None when the factor's sources
+    have changed since the counters were taken."""
+    try:
+        kv = {}
+        with open(FACTOR_MFMA_FILE) as f:
+            for line in f:
+                if ":" in line and not line.startswith("#"):
+                    k, v = line.split(":", 1)
+                    kv[k.strip()] = v.strip()
+        if kv.get("factor_source_sha256") != source_digest(FACTOR_SOURCES):
+            return None
+        return {"mfma_util_pct": float(kv["mfma_util_pct"]),
+                "mfma_flop_per_launch": float(kv["mfma_flop_per_launch"]),
+                "source": "profiles/k_factor2_plain640_mfma.txt (rocprofv3 --pmc)"}
     except (OSError, KeyError, ValueError):
         return None
 
@@ -606,7 +635,7 @@ def main():
     out["secondary"] = {
         "k_factor2": {"bound": "mfma", "flop_per_launch": fl, "avg_launch_ms": f_ms / max(f_n, 1),
                       "achieved": fl * f_n / (f_ms * 1e-3) / 1e12, "peak": 78.6, "unit": "TFLOP/s",
-                      "frac": fl * f_n / (f_ms * 1e-3) / 1e12 / 78.6},
+                      "frac": fl * f_n / (f_ms * 1e-3) / 1e12 / 78.6, "counters": measured_factor_mfma()},
         "k_residual": {"bound": "hbm", "bytes_per_launch": rb, "avg_launch_ms": r_ms / max(r_n, 1),
                        "achieved": rb * r_n / (r_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                        "frac": rb * r_n / (r_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
