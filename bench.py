@@ -399,7 +399,7 @@ def other_workload(args, api, synth, torch, np, dev):
         del pr
         A0 = torch.full((1, H4 - 1, W4 - 1, 2), ALPHA0, dtype=torch.float64, device=dev)
         forms = {}
-        for prec in (api.SF_FP64, api.SF_FP32):
+        for prec in (api.SF_FP64, api.SF_FP32_FACTOR, api.SF_FP32):
             ctx = api.sf_create(W4, H4, 1, px, py, d, lam=LAM, factor_precision=prec)
             U = torch.zeros(ctx.field_shape(), dtype=torch.float64, device=dev)
             api.sf_profile(ctx, 1)
@@ -411,7 +411,7 @@ def other_workload(args, api, synth, torch, np, dev):
             ms, (code, sw, rr) = _timed(job)
             _progress(f"prec4k: precision {prec}: {ms:.0f} ms, {sw[0]} sweeps, relres {rr[0]:.2e}")
             prof = {k: v[0] for k, v in api.sf_profile(ctx, 0).items()}
-            forms[prec] = dict(ms=ms, sweeps=sw[0], relres=rr[0], U=U, prof=prof)
+            forms[prec] = dict(ms=ms, sweeps=sw[0], relres=rr[0], U=U, prof=prof, fallbacks=api.sf_factor_fallbacks(ctx))
             if prec == api.SF_FP64:
                 # the FP64 reference: the plain solve continued to 1e-12
                 Us = U.clone()
@@ -422,7 +422,7 @@ def other_workload(args, api, synth, torch, np, dev):
         def errs(Ux):
             return [float(torch.linalg.norm(Ux[0, c] - ref["U"][0, c]) / torch.linalg.norm(ref["U"][0, c]))
                     for c in range(3)]
-        p64, p32 = forms[api.SF_FP64], forms[api.SF_FP32]
+        p64, p32, pt = forms[api.SF_FP64], forms[api.SF_FP32_FACTOR], forms[api.SF_FP32]
         unknowns = 3 * W4 * H4
         return dict(base, value=unknowns / (p64["ms"] * 1e-3), ms_per_step=p64["ms"], dtype="f64", steps=1,
                     warmup=0,
@@ -432,13 +432,18 @@ def other_workload(args, api, synth, torch, np, dev):
                             "rel_error_vs_reference_per_field": errs(p64["U"]),
                             "input_generation_s": round(gen_s, 1)},
                     phase_ms_per_step=p64["prof"],
-                    chosen_form={"form": "inverse Schur tiles stored in FP32, FP64 arithmetic, FP64-residual "
-                                         "Schwarz refinement",
+                    chosen_form={"form": "subdomain factors computed in FP32 arithmetic (FP32 MFMA) and stored in "
+                                         "FP32, applied in FP64, FP64-residual Schwarz refinement",
                                  "value": unknowns / (p32["ms"] * 1e-3), "ms_per_step": p32["ms"],
                                  "speedup_vs_plain": p64["ms"] / p32["ms"], "sweeps": p32["sweeps"],
-                                 "final_relres": p32["relres"],
+                                 "final_relres": p32["relres"], "fp64_fallback_subdomains": p32["fallbacks"],
                                  "rel_error_vs_reference_per_field": errs(p32["U"]),
                                  "phase_ms_per_step": p32["prof"]},
+                    fp32_tiles_form={"form": "subdomain factors computed in FP64, inverse tiles stored in FP32",
+                                     "value": unknowns / (pt["ms"] * 1e-3), "ms_per_step": pt["ms"],
+                                     "speedup_vs_plain": p64["ms"] / pt["ms"], "sweeps": pt["sweeps"],
+                                     "rel_error_vs_reference_per_field": errs(pt["U"]),
+                                     "phase_ms_per_step": pt["prof"]},
                     reference={"form": "plain FP64 solve continued to rel. residual 1e-12",
                                "sweeps": ref["sweeps"], "relres": ref["relres"]})
     # adj1024: solve, mean end-point-error loss against the known flow, adjoint gradients
@@ -453,7 +458,7 @@ def other_workload(args, api, synth, torch, np, dev):
     del pairs
     A0 = torch.full((N, Ha - 1, Wa - 1, 2), ALPHA0, dtype=torch.float64, device=dev)
     res = {}
-    for prec in (api.SF_FP32, api.SF_FP64):
+    for prec in (api.SF_FP32_FACTOR, api.SF_FP64):
         ctx = api.sf_create(Wa, Ha, N, px, py, d, lam=LAM, factor_precision=prec)
         I0g, I1g, Ag = (t.clone().requires_grad_(True) for t in (I0, I1, A0))
 
@@ -468,19 +473,20 @@ def other_workload(args, api, synth, torch, np, dev):
         _progress(f"adj1024: precision {prec}: {ms:.0f} ms, loss {float(loss):.6f}")
         res[prec] = dict(ms=ms, loss=float(loss), g=[I0g.grad, I1g.grad, Ag.grad])
         ctx.close()
-    g32, g64 = res[api.SF_FP32]["g"], res[api.SF_FP64]["g"]
+    g32, g64 = res[api.SF_FP32_FACTOR]["g"], res[api.SF_FP64]["g"]
     gerr = [float(torch.linalg.norm(a - b) / torch.linalg.norm(b)) for a, b in zip(g32, g64)]
     unknowns = 3 * Wa * Ha * N
-    r32 = res[api.SF_FP32]
+    r32 = res[api.SF_FP32_FACTOR]
     return dict(base, value=unknowns / (r32["ms"] * 1e-3), ms_per_step=r32["ms"], dtype="f64", steps=1, warmup=0,
                 config={"workload": f"adj1024: {N} pairs of 1024x1024 (seeds 5000..{4999 + N}), 8x8 subdomains, "
                                     "8-node overlap, lambda 1, alpha 0.1; solve to rel. residual 1e-8, loss = mean "
                                     "end-point error against the known flow, adjoint solve to 1e-8 and gradients "
                                     "with respect to I0, I1 and alpha",
-                        "form": "inverse Schur tiles stored in FP32, FP64 arithmetic and residuals",
+                        "form": "subdomain factors computed in FP32 arithmetic and stored in FP32, applied in FP64, "
+                                "FP64 residuals",
                         "loss": r32["loss"]},
                 fp64_check={"ms_per_step": res[api.SF_FP64]["ms"], "loss": res[api.SF_FP64]["loss"],
-                            "grad_rel_diff_fp32_tiles_vs_fp64": {"I0": gerr[0], "I1": gerr[1], "alpha": gerr[2]}})
+                            "grad_rel_diff_fp32_factors_vs_fp64": {"I0": gerr[0], "I1": gerr[1], "alpha": gerr[2]}})
 
 
 def main():
@@ -641,9 +647,11 @@ def main():
                        "frac": rb * r_n / (r_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
     }
     if not args.plain_only:
-        # the chosen form: inverse tiles stored in FP32, FP64 arithmetic and
-        # residuals (the Schwarz iteration refines); same workload, same 1e-8
-        ch = run_form(api.SF_FP32)
+        # the chosen form: the subdomain factorisation in FP32 arithmetic, its
+        # inverse tiles stored in FP32 and applied in FP64, FP64 residuals (the
+        # Schwarz iteration refines); same workload, same 1e-8
+        ch = run_form(api.SF_FP32_FACTOR)
+        tl = run_form(api.SF_FP32)
         Up, Uc = plain["U"][0], ch["U"][0]
         field_diff = [float(torch.linalg.norm(Uc[c] - Up[c]) / torch.linalg.norm(Up[c])) for c in range(3)]
         Us, us_sweeps, us_rel = reference_solution(plain["alpha"], plain["U"])
@@ -651,7 +659,8 @@ def main():
         out["config"]["rel_error_vs_reference_per_field"] = err_plain
         b32 = sweep_bytes(ch["plan"], tile_bytes=4)
         out["chosen_form"] = {
-            "form": "inverse Schur tiles stored in FP32, FP64 arithmetic, FP64-residual Schwarz refinement",
+            "form": "subdomain factors computed in FP32 arithmetic (FP32 MFMA) and stored in FP32, applied in FP64, "
+                    "FP64-residual Schwarz refinement",
             "value": 3 * W * H / (ch["ms_step"] * 1e-3), "unit": "unknowns/s", "ms_per_step": ch["ms_step"],
             "speedup_vs_plain": ms_step / ch["ms_step"],
             "sweeps_per_solve": [s[0] for s in ch["last"].sweeps],
@@ -664,6 +673,15 @@ def main():
             "sweep_bytes_per_launch": b32,
             "sweep_achieved_GBs": b32 / (ch["avg_sweep_ms"] * 1e-3) / 1e9,
             "phase_ms_per_step": phases(ch),
+        }
+        out["fp32_tiles_form"] = {
+            "form": "subdomain factors computed in FP64, inverse Schur tiles stored in FP32, FP64 arithmetic, "
+                    "FP64-residual Schwarz refinement",
+            "value": 3 * W * H / (tl["ms_step"] * 1e-3), "unit": "unknowns/s", "ms_per_step": tl["ms_step"],
+            "speedup_vs_plain": ms_step / tl["ms_step"],
+            "sweeps_per_solve": [s[0] for s in tl["last"].sweeps],
+            "rel_error_vs_reference_per_field": field_errors(tl["U"], Us),
+            "phase_ms_per_step": phases(tl),
         }
     if not args.plain_only:
         # batching: two pairs (seeds 2 and 3) share every launch, plain FP64

@@ -58,6 +58,12 @@ extern "C" {
                                    local solve whose error the Schwarz iteration on
                                    FP64 residuals removes (iterative refinement);
                                    the iteration converges to the same solution  */
+#define SF_FP32_FACTOR 2        /* the factorisation itself in FP32 arithmetic
+                                   (FP32 MFMA), tiles stored in FP32 and applied
+                                   in FP64 arithmetic as with SF_FP32; a
+                                   subdomain whose FP32 factorisation meets a
+                                   pivot <= pivot_tol x its diagonal entry of A
+                                   is factored again in FP64 arithmetic         */
 
 typedef struct sf_config {
     int32_t width;            /* W >= 2 nodes                                    */
@@ -81,6 +87,8 @@ typedef struct sf_config {
                                  shifts of the element data, clamp to edge per
                                  axis, integrated exactly (rho = 0: the plain
                                  data term)                                     */
+    double  pivot_tol;        /* SF_FP32_FACTOR: relative pivot threshold of the
+                                 FP32 factorisation (0 = default 1e-5)          */
 } sf_config;
 
 typedef struct sf_context sf_context;
@@ -250,6 +258,11 @@ int sf_choose_split(int32_t width, int32_t height, int32_t nparts, int32_t* part
 
 /* Number of subdomains over all pairs (B * parts_x * parts_y).             */
 int sf_num_subdomains(const sf_context* ctx);
+
+/* With SF_FP32_FACTOR: the number of subdomains that the last
+ * sf_factor_subdomains factored again in FP64 arithmetic because their FP32
+ * factorisation met a pivot below the threshold (0 otherwise).            */
+int sf_factor_fallbacks(const sf_context* ctx);
 
 /* geom[13] (HOST): pair, box x0, x1, y0, y1 (half-open), owned x0, x1, y0,
  * y1, lines-are-columns flag, sweep workgroups per chain, chains (1: lines

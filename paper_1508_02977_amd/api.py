@@ -29,6 +29,7 @@ SF_NOT_CONVERGED = 2
 SF_NONFINITE = 3
 SF_FP64 = 0
 SF_FP32 = 1
+SF_FP32_FACTOR = 2
 SF_SIGMA_MAX = 16.0
 SF_NOALLOC_SCRATCH_BYTES = 1 << 20
 
@@ -43,7 +44,7 @@ class sf_config(ctypes.Structure):
         ("parts_x", c_int32), ("parts_y", c_int32), ("overlap", c_int32),
         ("lambda_", c_double), ("sigma", c_double),
         ("factor_precision", c_int32), ("band_tile", c_int32),
-        ("rho", c_double),
+        ("rho", c_double), ("pivot_tol", c_double),
     ]
 
 
@@ -78,6 +79,7 @@ _SIGS = {
     "sf_plan": (c_int32, [ctypes.POINTER(sf_config), c_void_p]),
     "sf_memory_bytes": (c_int32, [ctypes.POINTER(sf_config), ctypes.POINTER(ctypes.c_int64)]),
     "sf_num_subdomains": (c_int32, [c_void_p]),
+    "sf_factor_fallbacks": (c_int32, [c_void_p]),
     "sf_subdomain_geometry": (c_int32, [c_void_p, c_int32, c_void_p]),
     "sf_subdomain_solve": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p]),
     "sf_profile": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p]),
@@ -201,18 +203,18 @@ class Context:
 
 
 def make_config(width, height, batch=1, parts_x=1, parts_y=1, overlap=0, lam=1.0, sigma=0.0,
-                factor_precision=SF_FP64, band_tile=0, rho=0.0) -> sf_config:
+                factor_precision=SF_FP64, band_tile=0, rho=0.0, pivot_tol=0.0) -> sf_config:
     return sf_config(width, height, batch, parts_x, parts_y, overlap, lam, sigma, factor_precision, band_tile,
-                     rho)
+                     rho, pivot_tol)
 
 
 # ---- the C entry points --------------------------------------------------
 
 def sf_create(width, height, batch=1, parts_x=1, parts_y=1, overlap=0, lam=1.0, sigma=0.0,
-              factor_precision=SF_FP64, band_tile=0, stream=None, rho=0.0) -> Context:
+              factor_precision=SF_FP64, band_tile=0, stream=None, rho=0.0, pivot_tol=0.0) -> Context:
     import torch
     cfg = make_config(width, height, batch, parts_x, parts_y, overlap, lam, sigma, factor_precision, band_tile,
-                      rho)
+                      rho, pivot_tol)
     if stream is None:
         stream = torch.cuda.current_stream()
     h = c_void_p()
@@ -381,6 +383,11 @@ def sf_profile(ctx: Context, enable: int = -1):
 
 def sf_num_subdomains(ctx: Context) -> int:
     return lib().sf_num_subdomains(ctx.handle)
+
+
+def sf_factor_fallbacks(ctx: Context) -> int:
+    """SF_FP32_FACTOR: subdomains the last factorisation redid in FP64."""
+    return lib().sf_factor_fallbacks(ctx.handle)
 
 
 def sf_subdomain_geometry(ctx: Context, sub: int):

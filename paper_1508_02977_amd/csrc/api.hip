@@ -86,7 +86,8 @@ int check_config(const sf_config& k) {
     if (k.parts_x < 1 || k.parts_y < 1 || k.parts_x > k.width || k.parts_y > k.height) return SF_ERR_INVALID;
     if (k.overlap < 0 || !(k.lambda > 0.0) || !std::isfinite(k.lambda)) return SF_ERR_INVALID;
     if (!(k.sigma >= 0.0 && k.sigma <= SF_SIGMA_MAX) || !(k.rho >= 0.0 && k.rho <= SF_SIGMA_MAX) ||
-        (k.factor_precision != SF_FP64 && k.factor_precision != SF_FP32) ||
+        (k.factor_precision != SF_FP64 && k.factor_precision != SF_FP32 && k.factor_precision != SF_FP32_FACTOR) ||
+        !(k.pivot_tol >= 0.0 && k.pivot_tol < 1.0) ||
         k.band_tile < 0)
         return SF_ERR_INVALID;
     if ((int64_t)k.width * k.height * k.batch > (1ll << 31)) return SF_ERR_INVALID;
@@ -211,10 +212,12 @@ void sf_destroy(sf_context* c) {
     if (!c) return;
     void* ptrs[] = {c->d_subs, c->f0, c->ft, c->alpha, c->F, c->r, c->eta, c->Fn2, c->Gn2,
                     c->partials, c->relres_d, c->sweeps_d, c->done_d, c->counters, c->etamax_bits,
-                    c->flags_d, c->factors, c->work, c->status_d, c->blur_w, c->clg_w, c->coef, c->clg_tmp};
+                    c->flags_d, c->factors, c->work, c->status_d, c->blur_w, c->clg_w, c->coef, c->clg_tmp,
+                    c->fail_d, c->sublist_d};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (c->host_stage) (void)hipHostFree(c->host_stage);
+    if (c->host_fail) (void)hipHostFree(c->host_fail);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     release_graph_resources(c);
     delete c;
@@ -230,7 +233,7 @@ static void storage_offsets(std::vector<SubDesc>& subs, int precision, int64_t* 
     for (auto& d : subs) {
         d.foff = foff;
         // tiles in doubles, or in floats packed two per double
-        foff += (int64_t)d.nt * d.ntiles * sfdd::TSZ / (precision == SF_FP32 ? 2 : 1);
+        foff += (int64_t)d.nt * d.ntiles * sfdd::TSZ / (precision != SF_FP64 ? 2 : 1);
         d.boff = foff;
         foff += (int64_t)d.nt * d.m * 6;
         d.aoff = foff;
@@ -261,6 +264,7 @@ static int64_t field_bytes(const sf_config& k, int64_t nsub) {
     d += 2 * B + npart * B + B;                                  // Fn2, Gn2, partials, relres
     int64_t bytes = d * 8 + (int64_t)sizeof(SubDesc) * nsub;
     bytes += 4 * (2 * B) + 8 * B + 4 * (2 * sfdd::F2_COUNTERS * nsub) + 16 + sizeof(sfdd::DevStatus);
+    bytes += 4 * nsub + 4;                                          // factor failure flags, subdomain list
     if (k.sigma > 0.0) bytes += 8 * (2 * (int64_t)std::ceil(3.0 * k.sigma) + 1);   // blur weights
     if (k.rho > 0.0)                                    // K_rho weights, coefficient planes and first-pass sums
         bytes += 8 * (2 * (int64_t)std::ceil(3.0 * k.rho) + 1) + 2 * 8 * (int64_t)sfdd::CLG_COEFS * ne * B;
@@ -340,7 +344,7 @@ int sf_create(const sf_config* cfg, void* stream, sf_context** out) {
     }
     // co-resident sweep workgroups: the least of the forms this precision uses
     int occ = 1 << 30;
-    const int fp32 = k.factor_precision == SF_FP32;
+    const int fp32 = k.factor_precision != SF_FP64;
     for (int form : {sfdd::SWEEP_GENERAL, sfdd::SWEEP_FAST2, sfdd::SWEEP_FAST1}) {
         int o = 0;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, sfdd::sweep_kernel(form, fp32), sfdd::sweep_threads(form),
@@ -356,9 +360,14 @@ int sf_create(const sf_config* cfg, void* stream, sf_context** out) {
     // factorisation) when 8 subdomains fit one launch with both chains in the
     // factor and with the fast sweep's ranks, else one chain
     int occ2 = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ2, sfdd::factor2_kernel(), sfdd::F2_WAVES * 64, 0) !=
-        hipSuccess)
-        occ2 = 0;
+    // (both arithmetic forms of the cooperative factor: the least of the two)
+    for (int f32 = 0; f32 < 2; ++f32) {
+        int o = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, sfdd::factor2_kernel(f32), sfdd::F2_WAVES * 64, 0) !=
+            hipSuccess)
+            o = 0;
+        occ2 = f32 == 0 ? o : std::min(occ2, o);
+    }
     const int fcap = ncu * occ2;
     int Pf = 0;
     for (const auto& d : c->subs) Pf = std::max(Pf, sfdd::f2_ranks(d.NT));
@@ -415,6 +424,8 @@ int sf_create(const sf_config* cfg, void* stream, sf_context** out) {
     rc |= dalloc(&c->counters, 2 * sfdd::F2_COUNTERS * (size_t)c->nsub);
     rc |= dalloc(&c->etamax_bits, c->B);
     rc |= dalloc(&c->flags_d, 4);
+    rc |= dalloc(&c->fail_d, c->nsub);
+    rc |= dalloc(&c->sublist_d, 1);
     rc |= dalloc(&c->factors, (size_t)c->factor_doubles);
     rc |= dalloc(&c->work, (size_t)c->work_doubles);
     rc |= dalloc(&c->status_d, 1);
@@ -446,6 +457,11 @@ int sf_create(const sf_config* cfg, void* stream, sf_context** out) {
     const size_t stage = STAGE_A + 24 * (size_t)c->B + 64;
     if (hipHostMalloc(&c->host_stage, stage, hipHostMallocDefault) != hipSuccess) {
         c->host_stage = nullptr;
+        sf_destroy(c);
+        return SF_ERR_OOM;
+    }
+    if (hipHostMalloc(&c->host_fail, sizeof(int32_t) * (size_t)c->nsub, hipHostMallocDefault) != hipSuccess) {
+        c->host_fail = nullptr;
         sf_destroy(c);
         return SF_ERR_OOM;
     }
@@ -519,24 +535,57 @@ int sf_factor_subdomains(sf_context* c) {
     if (!c) return SF_ERR_INVALID;
     if (c->state < ST_ASSEMBLED) return SF_ERR_STATE;
     SF_TRY(sfdd::prof_begin(c, sfdd::PROF_FACTOR));
+    const int fp32_arith = c->cfg.factor_precision == SF_FP32_FACTOR && c->factor_pf > 0;
+    const int ncnt = 2 * sfdd::F2_COUNTERS * c->nsub;
+    auto zero_counters = [&]() -> int {
+        hipLaunchKernelGGL(k_fill_i32, dim3((ncnt + 255) / 256), dim3(256), 0, c->stream, (int32_t*)c->counters, ncnt,
+                           0);
+        return hipGetLastError() == hipSuccess ? SF_OK : SF_ERR_HIP;
+    };
     if (c->factor_pf > 0) {
         SF_TRY(sfdd::launch_line_coeffs(c));
         hipLaunchKernelGGL(k_zero_status_api, dim3(1), dim3(1), 0, c->stream, c->status_d);
         SF_HIP(hipGetLastError());
+        if (fp32_arith) SF_TRY(fill_i32(c, c->fail_d, c->nsub, 0));
+        // a pivot of the FP32 factorisation is rejected below pivot_tol (its
+        // subdomain is then factored again in FP64), one of the FP64
+        // factorisation below 1e-13 (SF_NOT_SPD)
+        const double ptol = fp32_arith ? (c->cfg.pivot_tol > 0.0 ? c->cfg.pivot_tol : 1e-5) : 1e-13;
         for (int s0 = 0; s0 < c->nsub; s0 += c->factor_chunk) {
             const int n = std::min(c->factor_chunk, c->nsub - s0);
-            const int ncnt = 2 * sfdd::F2_COUNTERS * c->nsub;
-            hipLaunchKernelGGL(k_fill_i32, dim3((ncnt + 255) / 256), dim3(256), 0, c->stream,
-                               (int32_t*)c->counters, ncnt, 0);
-            SF_HIP(hipGetLastError());
-            SF_TRY(sfdd::launch_factor2(c, s0, n, c->factor_pf));
+            SF_TRY(zero_counters());
+            SF_TRY(sfdd::launch_factor2(c, s0, n, c->factor_pf, fp32_arith, nullptr, c->factor_lanes, ptol));
         }
     } else {
         SF_TRY(sfdd::launch_factor(c));
     }
     SF_TRY(sfdd::prof_end(c));
-    const int code = pull_status(c);
+    int code = pull_status(c);
     SF_TRY(sfdd::prof_harvest(c));
+    if (fp32_arith && code == SF_NOT_SPD) {
+        // FP64 fallback, subdomain by subdomain (each one alone in its launch,
+        // so the factor workspace slots cannot collide)
+        int32_t* hf = (int32_t*)c->host_fail;
+        SF_HIP(hipMemcpyAsync(hf, c->fail_d, c->nsub * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+        SF_HIP(hipStreamSynchronize(c->stream));
+        hipLaunchKernelGGL(k_zero_status_api, dim3(1), dim3(1), 0, c->stream, c->status_d);
+        SF_HIP(hipGetLastError());
+        c->fp64_fallbacks = 0;
+        SF_TRY(sfdd::prof_begin(c, sfdd::PROF_FACTOR));
+        for (int i = 0; i < c->nsub; ++i) {
+            if (!hf[i]) continue;
+            ++c->fp64_fallbacks;
+            hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(1), 0, c->stream, c->sublist_d, 1, (int32_t)i);
+            SF_HIP(hipGetLastError());
+            SF_TRY(zero_counters());
+            SF_TRY(sfdd::launch_factor2(c, 0, 1, sfdd::f2_ranks(c->subs[i].NT), 0, c->sublist_d, 1, 1e-13));
+        }
+        SF_TRY(sfdd::prof_end(c));
+        code = pull_status(c);
+        SF_TRY(sfdd::prof_harvest(c));
+    } else {
+        c->fp64_fallbacks = 0;
+    }
     if (code != SF_OK) {
         c->state = ST_ASSEMBLED;
         return code;
@@ -893,6 +942,8 @@ int sf_choose_split(int32_t width, int32_t height, int32_t nparts, int32_t* part
 }
 
 int sf_num_subdomains(const sf_context* c) { return c ? c->nsub : SF_ERR_INVALID; }
+
+int sf_factor_fallbacks(const sf_context* c) { return c ? c->fp64_fallbacks : SF_ERR_INVALID; }
 
 int sf_profile(sf_context* c, int32_t enable, double* ms, int64_t* launches) {
     if (!c) return SF_ERR_INVALID;

@@ -324,7 +324,7 @@ int launch_factor(sf_context* c) {
         const int n = std::min(c->factor_chunk, c->nsub - s0);
         hipLaunchKernelGGL(k_factor, dim3(n), dim3(FACTOR_THREADS), 0, c->stream, c->d_subs, c->f0, c->alpha,
                            c->factors, c->work, c->status_d, c->W, c->H, c->cfg.lambda,
-                           c->cfg.factor_precision == SF_FP32 ? 1 : 0, s0, (const double*)c->coef);
+                           c->cfg.factor_precision != SF_FP64 ? 1 : 0, s0, (const double*)c->coef);
         if (hipGetLastError() != hipSuccess) return SF_ERR_HIP;
     }
     return SF_OK;

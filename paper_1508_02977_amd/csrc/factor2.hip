@@ -90,6 +90,40 @@ __device__ __forceinline__ int f2_slot(const F2Own& o, int J) {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 typedef double d2 __attribute__((ext_vector_type(2)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+// Arithmetic of the ranks' tiles: FP64 (v_mfma_f64_16x16x4f64) or FP32
+// (v_mfma_f32_16x16x4f32).  Both take A[i][k] in lane i + 16k and B[k][j] in
+// lane j + 16k; they differ in where an accumulator element lives (checked
+// on gfx950): FP64 element q of lane l is D[l/16 + 4q][l%16], FP32 element q
+// is D[4(l/16) + q][l%16].  LDS tiles of the exchange column keep rows of 32
+// values with the 16-byte chunks of row r permuted (chunk c at c ^ (r mod the
+// chunks per row)); the pivot and X tiles use a row pitch that keeps 16-byte
+// reads aligned.
+template <typename T> struct F2T;
+template <> struct F2T<double> {
+    using V4 = d4;
+    static constexpr int LDPT = 34;       // LDS row pitch of the pivot / X tiles
+    static constexpr int EPC = 2;         // values per 16-byte chunk
+    __device__ static __forceinline__ V4 mfma(double a, double b, V4 c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    __device__ static __forceinline__ int row(int cr, int q) { return cr + 4 * q; }
+};
+template <> struct F2T<float> {
+    using V4 = f4;
+    static constexpr int LDPT = 36;
+    static constexpr int EPC = 4;
+    __device__ static __forceinline__ V4 mfma(float a, float b, V4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    __device__ static __forceinline__ int row(int cr, int q) { return 4 * cr + q; }
+};
+template <typename T>
+__device__ __forceinline__ int colk_at_t(int slot, int r, int c) {
+    constexpr int E = F2T<T>::EPC, CPR = TS / E;   // chunks per row
+    return slot * TSZ + r * TS + (((c / E) ^ (r & (CPR - 1))) * E) + (c & (E - 1));
+}
 
 struct FactorArgs {
     const SubDesc* subs;
@@ -108,6 +142,9 @@ struct FactorArgs {
     double lam;
     long long spin_limit;
     uint32_t epoch;           // tag base of this launch (pivot-block and Pi words carry epoch + pivot)
+    double ptol;              // a pivot p is accepted when p > ptol x the diagonal entry of A_tt it came from
+    int32_t* fail;            // [subdomains] set to 1 where a pivot is rejected (or null)
+    const int32_t* sublist;   // if set: the launch factors subdomains sublist[0 .. nsub - sub0)
 };
 
 // Line coefficients of every subdomain, computed once before the
@@ -160,11 +197,20 @@ __global__ void k_line_coeffs(const SubDesc* __restrict__ subs, const double* __
     }
 }
 
-__device__ __forceinline__ void xstore(double* p, double v) {
+// One 16-byte global-to-LDS load per lane, device-scope coherent (sc1).  Kept
+// out of the kernel template: its LDS address-space cast has no meaning in the
+// host compilation, which instantiates the template to emit its launch stub.
+__device__ __forceinline__ void f2_load_lds16(const void* src, void* lds) {
+    __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)lds, 16, 0, 16 /* sc1 */);
+}
+
+template <typename T>
+__device__ __forceinline__ void xstore(T* p, T v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ double xload(const double* p) {
-    return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+template <typename T>
+__device__ __forceinline__ T xload(const T* p) {
+    return __hip_atomic_load(const_cast<T*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __device__ __forceinline__ bool f2_wait(uint32_t* cnt, uint32_t target, const FactorArgs& A, int sub, int* sh_ok) {
@@ -195,20 +241,29 @@ __device__ __forceinline__ void f2_signal(uint32_t* cnt) {
     if (threadIdx.x == 0) __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// a double as two tagged 64-bit words
+// A value as tagged 64-bit words (32-bit tag, 32 bits of the value): a
+// double takes two words, a float one; entry i of a tile sits at word
+// 2 i either way.
 __device__ __forceinline__ void f2_tstore(uint64_t* p, uint32_t tag, double v) {
     const uint64_t bits = (uint64_t)__double_as_longlong(v), tg = (uint64_t)tag << 32;
     __hip_atomic_store(p, tg | (bits & 0xffffffffull), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __hip_atomic_store(p + 1, tg | (bits >> 32), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+__device__ __forceinline__ void f2_tstore(uint64_t* p, uint32_t tag, float v) {
+    const uint64_t bits = (uint64_t)__float_as_uint(v), tg = (uint64_t)tag << 32;
+    __hip_atomic_store(p, tg | bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
-// Poll the 32x32 tile of tagged words at src until every entry carries `tag`;
-// entry i = tix + 256 u (tix: this thread's index) goes to the LDS tile dst
-// (pitch LDP) as soon as it is seen.  False (and SF_ERR_DEVICE) when the
-// wait is abandoned; the result is uniform over the workgroup.
-__device__ bool f2_tpoll(const uint64_t* src, uint32_t tag, double* dst, const DevStatus* stc, DevStatus* st,
+// Poll the 32x32 tile of tagged words (values of type TW) at src until every
+// entry carries `tag`; entry i = tix + 256 u (tix: this thread's index) goes
+// to the LDS tile dst (pitch ldp, type TD) as soon as it is seen.  False (and
+// SF_ERR_DEVICE) when the wait is abandoned; the result is uniform over the
+// workgroup.
+template <typename TW, typename TD>
+__device__ __forceinline__ bool f2_tpoll(const uint64_t* src, uint32_t tag, TD* dst, int ldp, const DevStatus* stc, DevStatus* st,
                          long long spin, int sub, int tix) {
     constexpr int NU = TSZ / 256;
+    constexpr bool W2 = sizeof(TW) == 8;
     unsigned pending = (1u << NU) - 1;
     long long n = 0;
     int ok = 1;
@@ -219,13 +274,17 @@ __device__ bool f2_tpoll(const uint64_t* src, uint32_t tag, double* dst, const D
             if (pending & (1u << u)) {
                 const uint64_t* w = src + 2 * (tix + 256 * u);
                 lo[u] = __hip_atomic_load(const_cast<uint64_t*>(w), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                hi[u] = __hip_atomic_load(const_cast<uint64_t*>(w + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                hi[u] = W2 ? __hip_atomic_load(const_cast<uint64_t*>(w + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                           : lo[u];
             }
 #pragma unroll
         for (int u = 0; u < NU; ++u)
             if ((pending & (1u << u)) && (uint32_t)(lo[u] >> 32) == tag && (uint32_t)(hi[u] >> 32) == tag) {
                 const int i = tix + 256 * u;
-                dst[(i / TS) * LDP + i % TS] = __longlong_as_double((long long)((hi[u] << 32) | (lo[u] & 0xffffffffull)));
+                TD v;
+                if constexpr (W2) v = (TD)__longlong_as_double((long long)((hi[u] << 32) | (lo[u] & 0xffffffffull)));
+                else v = (TD)__uint_as_float((unsigned)(lo[u] & 0xffffffffull));
+                dst[(i / TS) * ldp + i % TS] = v;
                 pending &= ~(1u << u);
             }
         if (!pending) break;
@@ -249,8 +308,9 @@ __device__ __forceinline__ void f2_tile_of(int q, const F2Own& o, int& I, int& J
 
 // Publish block column `col` of the current matrix (the own blocks in it)
 // into the exchange slots xb[J] = S_{J,col} (32x32 row-major).
-__device__ __forceinline__ void f2_publish(const d4 (&acc)[F2_MAXBLK], double* xb, int col, int nblk, const F2Own& o,
-                                           int wv, int cr, int cc) {
+template <typename T>
+__device__ __forceinline__ void f2_publish(const typename F2T<T>::V4 (&acc)[F2_MAXBLK], T* xb, int col, int nblk,
+                                           const F2Own& o, int wv, int cr, int cc) {
 #pragma unroll
     for (int b = 0; b < F2_MAXBLK; ++b) {
         const int blk = wv + F2_NW * b;
@@ -261,11 +321,11 @@ __device__ __forceinline__ void f2_publish(const d4 (&acc)[F2_MAXBLK], double* x
         if (J == col) {                                  // tile (I, col): slot I as is
 #pragma unroll
             for (int q = 0; q < 4; ++q)
-                xstore(xb + (int64_t)I * TSZ + (16 * qi + cr + 4 * q) * TS + 16 * qj + cc, acc[b][q]);
+                xstore(xb + (int64_t)I * TSZ + (16 * qi + F2T<T>::row(cr, q)) * TS + 16 * qj + cc, acc[b][q]);
         } else if (I == col) {                           // tile (col, J), J < col: slot J transposed
 #pragma unroll
             for (int q = 0; q < 4; ++q)
-                xstore(xb + (int64_t)J * TSZ + (16 * qj + cc) * TS + 16 * qi + cr + 4 * q, acc[b][q]);
+                xstore(xb + (int64_t)J * TSZ + (16 * qj + cc) * TS + 16 * qi + F2T<T>::row(cr, q), acc[b][q]);
         }
         __builtin_amdgcn_sched_barrier(0);
     }
@@ -280,8 +340,9 @@ __device__ __forceinline__ void f2_publish(const d4 (&acc)[F2_MAXBLK], double* x
 // The pivots met are those of the unblocked sweep; each is checked against
 // the diagonal entry of A_tt it came from (adiag_k, LDS).
 // Publish the own diagonal tile (col, col) as tagged words into the pivot-block slot db.
-__device__ __forceinline__ void f2_publish_diag(const d4 (&acc)[F2_MAXBLK], uint64_t* db, uint32_t tag, int col,
-                                                int nblk, const F2Own& o, int wv, int cr, int cc) {
+template <typename T>
+__device__ __forceinline__ void f2_publish_diag(const typename F2T<T>::V4 (&acc)[F2_MAXBLK], uint64_t* db, uint32_t tag,
+                                                int col, int nblk, const F2Own& o, int wv, int cr, int cc) {
 #pragma unroll
     for (int b = 0; b < F2_MAXBLK; ++b) {
         const int blk = wv + F2_NW * b;
@@ -291,7 +352,8 @@ __device__ __forceinline__ void f2_publish_diag(const d4 (&acc)[F2_MAXBLK], uint
         const int qi = (blk >> 1) & 1, qj = blk & 1;
         if (I == col && J == col) {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) f2_tstore(db + 2 * ((16 * qi + cr + 4 * q) * TS + 16 * qj + cc), tag, acc[b][q]);
+            for (int q = 0; q < 4; ++q)
+                f2_tstore(db + 2 * ((16 * qi + F2T<T>::row(cr, q)) * TS + 16 * qj + cc), tag, (T)acc[b][q]);
         }
         __builtin_amdgcn_sched_barrier(0);
     }
@@ -341,7 +403,7 @@ __device__ __forceinline__ void f2_gj_step(double (&v)[4], const double (&adg)[1
 #pragma unroll
     for (int q = 0; q < 4; ++q) colp[q] = f2_row_lane<P>(v[q]);   // M[ri + 4q][P]
     const double pp = f2_lane(v[Q], P + 16 * R);             // M[P][P]
-    const bool okp = pp > 1e-13 * adg[P] && isfinite(pp);
+    const bool okp = pp > adg[P] && isfinite(pp);      // adg: the pivot threshold
     bad = (bad < 0 && !okp) ? P : bad;
     double ip = __builtin_amdgcn_rcp(pp);
     ip = fma(fma(-pp, ip, 1.0), ip, ip);
@@ -367,8 +429,8 @@ struct F2Sweep<16> {
     __device__ static __forceinline__ void run(double (&)[4], const double (&)[16], int, int, int&) {}
 };
 
-__device__ void f2_pivot_inverse(const double* Sk, double* piv, double* xr, const double* adiag_k, int lane,
-                                 DevStatus* status, int sub, int64_t row0) {
+__device__ __forceinline__ void f2_pivot_inverse(const double* Sk, double* piv, double* xr, const double* adiag_k, int lane,
+                                 DevStatus* status, int sub, int64_t row0, double ptol, int32_t* fail) {
     constexpr int PB = 17;                        // pitch of the 16x16 scratch blocks
     double* bA = xr;                              // A^-1
     double* bB = bA + 16 * PB;                    // B, then -C'^-1 X
@@ -391,15 +453,18 @@ __device__ void f2_pivot_inverse(const double* Sk, double* piv, double* xr, cons
     auto sweep16 = [&](d4& v, int poff) {
         double adg[16];
 #pragma unroll
-        for (int p = 0; p < 16; ++p) adg[p] = adiag_k[poff + p];
+        for (int p = 0; p < 16; ++p) adg[p] = ptol * adiag_k[poff + p];
         double w[4] = {v[0], v[1], v[2], v[3]};
         int bad = -1;
         F2Sweep<0>::run(w, adg, ci, ri, bad);
 #pragma unroll
         for (int q = 0; q < 4; ++q) v[q] = w[q];
-        if (lane == 0 && bad >= 0 && atomicCAS(&status->code, 0, SF_NOT_SPD) == 0) {
-            status->sub = sub;
-            status->row = row0 + poff + bad;
+        if (lane == 0 && bad >= 0) {
+            if (fail) fail[sub] = 1;
+            if (atomicCAS(&status->code, 0, SF_NOT_SPD) == 0) {
+                status->sub = sub;
+                status->row = row0 + poff + bad;
+            }
         }
     };
     auto put = [&](double* buf, const d4& v, double sgn) {
@@ -453,25 +518,29 @@ __device__ void f2_pivot_inverse(const double* Sk, double* piv, double* xr, cons
     }
 }
 
+template <typename T>
 __global__ void __launch_bounds__(F2_THREADS) k_factor2(FactorArgs A) {
+    using V4 = typename F2T<T>::V4;
+    constexpr int LDPT = F2T<T>::LDPT, LTT = TS * LDPT;
     // LDS: exchange column (the rank's F2_SLOTS tiles), then pivot inverse and
     // scaled rows X_I (2 tiles).  While a line is built, the exchange column's
     // space holds the line's node blocks and couplings, and the pivot / X
     // space the waves' window scratch.
-    __shared__ __attribute__((aligned(16))) double colk[F2_SLOTS * TSZ];
-    __shared__ __attribute__((aligned(16))) double pxr[3 * LTILE];
-    double* const piv = pxr;
-    double* const xr = pxr + LTILE;
+    __shared__ __attribute__((aligned(16))) T colk[F2_SLOTS * TSZ];
+    __shared__ __attribute__((aligned(16))) T pxr[3 * LTT];
+    T* const piv = pxr;
+    T* const xr = pxr + LTT;
     __shared__ int sh_ok;
 
     // workgroup g runs on XCD g % 8: with A.lanes = 8 the ranks of subdomain
     // i are the slots with g % 8 == i % 8, so its exchange stays inside one L2
     // per chain: ranks 0..pf-1 and the pivot server (rank pf)
     const int ps = A.pf + 1, slot = blockIdx.x / A.lanes, per = A.groups * ps;
-    const int sub = A.sub0 + (int)(blockIdx.x % A.lanes) + A.lanes * (slot / per);
+    const int local = (int)(blockIdx.x % A.lanes) + A.lanes * (slot / per);
     const int chain = (slot % per) / ps, rank = slot % ps;
     const bool server = rank == A.pf;
-    if (sub >= A.nsub) return;                           // idle slot
+    if (local >= A.nsub - A.sub0) return;                // idle slot
+    const int sub = A.sublist ? A.sublist[local] : A.sub0 + local;
     const SubDesc d = A.subs[sub];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int m = d.m, mp = d.mp, NT = d.NT, ms = d.ms;
@@ -482,14 +551,14 @@ __global__ void __launch_bounds__(F2_THREADS) k_factor2(FactorArgs A) {
     // per chain: the full symmetric inverse of its latest line (mp x mp),
     // [2][NT][32x32] exchange slots, then per rank and wave F2_MAXBLK 16x16
     // blocks of build scratch
-    const int64_t cstride = f2_chain_doubles(mp, NT);
-    double* Sup = A.work + d.soff;                      // top chain: S_{t-1}^{-1}
-    double* Sdn = Sup + cstride;                        // bottom chain: S_{t+1}^{-1}
-    double* Sown = chain == 0 ? Sup : Sdn;
-    double* xch = Sown + (int64_t)mp * mp;
+    const int64_t cstride = f2_chain_doubles(mp, NT);   // (in doubles; values of type T from its start)
+    T* Sup = reinterpret_cast<T*>(A.work + d.soff);                   // top chain: S_{t-1}^{-1}
+    T* Sdn = reinterpret_cast<T*>(A.work + d.soff + cstride);         // bottom chain: S_{t+1}^{-1}
+    T* Sown = chain == 0 ? Sup : Sdn;
+    T* xch = Sown + (int64_t)mp * mp;
     uint64_t* dslot = reinterpret_cast<uint64_t*>(xch + 2ll * NT * TSZ);   // [2][TSZ] tagged pivot blocks
     uint64_t* pslot = dslot + 4 * TSZ;                                        // [2][TSZ] tagged Pi
-    double* bscr = reinterpret_cast<double*>(pslot + 4 * TSZ) + (int64_t)(rank * F2_NW + wv) * F2_MAXBLK * 256;
+    T* bscr = reinterpret_cast<T*>(pslot + 4 * TSZ) + (int64_t)(rank * F2_NW + wv) * F2_MAXBLK * 256;
     uint32_t* cnt = A.counters + F2_COUNTERS * (2 * sub + chain);   // column parts published
 
     const int nt = d.nt, km = d.kmid;
@@ -498,21 +567,31 @@ __global__ void __launch_bounds__(F2_THREADS) k_factor2(FactorArgs A) {
     if (server) {
         // pivot server: for every pivot of every line of the chain, wait for
         // the pivot block S_kk, form Pi_k (wave 0) and publish it
+        // FP64 scratch in the exchange column's LDS: pivot block, Pi, the
+        // pivot inverse's 16x16 blocks, the diagonal of A_tt
         uint32_t npiv = 0;
-        double* adiag = colk + 2 * TSZ;          // beyond the 32 x LDP pivot block staged at colk
+        double* const sd = reinterpret_cast<double*>(colk);
+        double* const sk = sd;                   // 32 x LDP
+        double* const spiv = sd + LTILE;         // 32 x LDP
+        double* const sxr = sd + 2 * LTILE;      // 4 blocks of 16 x 17
+        double* const adiag = sd + 3 * LTILE;    // mp
+        static_assert(3 * LTILE + F2_MAXNT * TS <= F2_SLOTS * TSZ / 2, "server scratch fits the exchange column");
         for (int li = 0; li < nlines; ++li) {
             const int t = chain == 0 ? li : nt - 1 - li;
             const double* Ag = A.factors + d.aoff + (int64_t)t * ms * 18;
             for (int a = tid; a < mp; a += F2_THREADS) adiag[a] = a < m ? Ag[18 * (a / 3) + 4 * (a % 3)] : 1.0;
             for (int k = 0; k < NT; ++k) {
                 ++npiv;
-                if (!f2_tpoll(dslot + (npiv & 1) * 2 * TSZ, A.epoch + npiv, colk, A.status, A.status, A.spin_limit, sub,
-                              tid))
+                if (!f2_tpoll<T, double>(dslot + (npiv & 1) * 2 * TSZ, A.epoch + npiv, sk, LDP, A.status, A.status,
+                                         A.spin_limit, sub, tid))
                     return;
-                if (wv == 0) f2_pivot_inverse(colk, piv, xr, adiag + k * TS, lane, A.status, sub, (int64_t)t * m + k * TS);
+                if (wv == 0)
+                    f2_pivot_inverse(sk, spiv, sxr, adiag + k * TS, lane, A.status, sub, (int64_t)t * m + k * TS, A.ptol,
+                                     A.fail);
                 __syncthreads();
                 uint64_t* pb = pslot + (npiv & 1) * 2 * TSZ;
-                for (int i = tid; i < TSZ; i += F2_THREADS) f2_tstore(pb + 2 * i, A.epoch + npiv, piv[(i / TS) * LDP + i % TS]);
+                for (int i = tid; i < TSZ; i += F2_THREADS)
+                    f2_tstore(pb + 2 * i, A.epoch + npiv, (T)spiv[(i / TS) * LDP + i % TS]);
             }
         }
         return;
@@ -529,13 +608,13 @@ __global__ void __launch_bounds__(F2_THREADS) k_factor2(FactorArgs A) {
     const bool xtraA = own.sp == 2 && (rowA & 1) != own.h;
     const bool xtraB = own.sp == 2 && nrows == 2 && (rowB & 1) != own.h;
     const int nslots = npar + (xtraA ? 1 : 0) + (xtraB ? 1 : 0);
-    d4 acc[F2_MAXBLK];
+    V4 acc[F2_MAXBLK];
     // fragment coordinates of this lane inside a 16x16 block
     // (recomputed from an opaque copy of the lane id in every pivot step, so
     // that the compiler does not keep the dozens of loop-invariant LDS
     // addresses of the unrolled block loops live across the whole line)
     int fr = lane & 15, fk = lane >> 4;                    // A/B operand: row fr, k-slice fk
-    int cr = lane >> 4, cc = lane & 15;                    // accumulator element q: row cr + 4q, col cc
+    int cr = lane >> 4, cc = lane & 15;                    // accumulator element q: row F2T<T>::row(cr, q), col cc
 
     // Lines of the chains: the top chain (0) takes lines 0..k-1 and then the
     // middle line k, the bottom chain (1) lines nt-1..k+1 (k = d.kmid; with one
@@ -550,10 +629,10 @@ __global__ void __launch_bounds__(F2_THREADS) k_factor2(FactorArgs A) {
         const bool hdn = (chain == 1 || mid) && t < nt - 1;      // term of line t+1
         // ---------- phase 0 of the line: build own tiles of S_t -------------
         // A_tt node blocks and the couplings of this line into LDS
-        double* Aself = colk;                    // [ms][9]
-        double* Anext = colk + 9 * ms;           // [ms][9]: block (s, s+1)
-        double* Bl = colk + 18 * ms;             // [m][6]: B_t, nodes s-1, s of line t-1
-        double* Cl = Bl + 6 * m;                 // [m][6]: B_{t+1}^T, nodes s, s+1 of line t+1
+        T* Aself = colk;                         // [ms][9]
+        T* Anext = colk + 9 * ms;                // [ms][9]: block (s, s+1)
+        T* Bl = colk + 18 * ms;                  // [m][6]: B_t, nodes s-1, s of line t-1
+        T* Cl = Bl + 6 * m;                      // [m][6]: B_{t+1}^T, nodes s, s+1 of line t+1
         {
             const double* Ag = A.factors + d.aoff + (int64_t)t * ms * 18;
             for (int i = tid; i < 18 * ms; i += F2_THREADS) {
@@ -579,12 +658,12 @@ __global__ void __launch_bounds__(F2_THREADS) k_factor2(FactorArgs A) {
         }
         __syncthreads();
         // A_tt entry (a, a2), both < m
-        auto a_entry = [&](int a, int a2) -> double {
+        auto a_entry = [&](int a, int a2) -> T {
             const int s = a / 3, c = a % 3, s2 = a2 / 3, c2 = a2 % 3;
             if (s == s2) return Aself[9 * s + 3 * c + c2];
             if (s2 == s + 1) return Anext[9 * s + 3 * c + c2];
             if (s == s2 + 1) return Anext[9 * s2 + 3 * c2 + c];
-            return 0.0;
+            return T(0);
         };
         // Own blocks of S_t = A_tt - (coupling terms).  A term C S^{-1} C^T with
         // couplings C to the two nodes s-1+dn, s+dn of the neighbouring line
@@ -599,8 +678,8 @@ __global__ void __launch_bounds__(F2_THREADS) k_factor2(FactorArgs A) {
             return;
         {
             constexpr int WN = 21;
-            double* win = pxr + wv * (WN * WN + WN * 16);           // [WN][WN]
-            double* zb = win + WN * WN;                             // [WN][16]
+            T* win = pxr + wv * (WN * WN + WN * 16);                // [WN][WN]
+            T* zb = win + WN * WN;                                  // [WN][16]
             constexpr int NWL = (WN * WN + 63) / 64;              // window entries per lane
             // Work items: (block b of this wave, term).  The window loads of the
             // next item are issued before the current item is computed, so the
@@ -621,12 +700,12 @@ __global__ void __launch_bounds__(F2_THREADS) k_factor2(FactorArgs A) {
                 w0 = max(0, 3 * (x0 / 3 - 1 + dn));
                 n = max(0, min(m, 3 * ((x0 + 15) / 3 + dn) + 3) - w0);
             };
-            auto issue = [&](int it, double (&w)[NWL]) {
+            auto issue = [&](int it, T (&w)[NWL]) {
                 int b, dn, r0, c0, wr0, nr, wc0, nc;
                 item(it, b, dn, r0, c0);
                 win_rows(r0, dn, wr0, nr);
                 win_rows(c0, dn, wc0, nc);
-                const double* S = dn ? Sdn : Sup;
+                const T* S = dn ? Sdn : Sup;
                 // every lane loads, with indices clamped into the window (which
                 // lies inside the mp x mp inverse: wr0, wc0 <= the block's first
                 // row, wr0 + nr, wc0 + nc <= m); the entries outside the window
@@ -640,27 +719,27 @@ __global__ void __launch_bounds__(F2_THREADS) k_factor2(FactorArgs A) {
                     w[u] = xload(S + (int64_t)(wr0 + min(i, imax)) * mp + wc0 + min(j, jmax));
                 }
             };
-            d4 v = {0.0, 0.0, 0.0, 0.0};
+            V4 v = {T(0), T(0), T(0), T(0)};
             auto a_init = [&](int r0, int c0) {
                 const int a2 = c0 + cc;
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    const int a = r0 + cr + 4 * q;
-                    v[q] = (a < m && a2 < m) ? a_entry(a, a2) : (a == a2 ? 1.0 : 0.0);   // identity on the padding
+                    const int a = r0 + F2T<T>::row(cr, q);
+                    v[q] = (a < m && a2 < m) ? a_entry(a, a2) : (a == a2 ? T(1) : T(0));   // identity on the padding
                 }
             };
             // subtract the item's term C_R Z, Z = S^{-1}[W(R), W(C)] C_C^T, from v
-            auto process = [&](int it, const double (&w)[NWL]) {
+            auto process = [&](int it, const T (&w)[NWL]) {
                 int b, dn, r0, c0, wr0, nr, wc0, nc;
                 item(it, b, dn, r0, c0);
                 win_rows(r0, dn, wr0, nr);
                 win_rows(c0, dn, wc0, nc);
-                const double* cf = dn ? Cl : Bl;
+                const T* cf = dn ? Cl : Bl;
                 if (nterm == 1 || dn == 0) a_init(r0, c0);         // first term of the block
 #pragma unroll
                 for (int u = 0; u < NWL; ++u) {
                     const int e = lane + 64 * u, i = e / WN, j = e % WN;
-                    if (e < WN * WN) win[e] = (i < nr && j < nc) ? w[u] : 0.0;
+                    if (e < WN * WN) win[e] = (i < nr && j < nc) ? w[u] : T(0);
                 }
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -671,18 +750,18 @@ __global__ void __launch_bounds__(F2_THREADS) k_factor2(FactorArgs A) {
                     const int jc = lane & 15, a2 = c0 + jc;
                     const bool live = a2 < m;
                     const int nlo = a2 / 3 - 1 + dn, nhi = a2 / 3 + dn;
-                    double c2[6];
+                    T c2[6];
 #pragma unroll
-                    for (int g = 0; g < 6; ++g) c2[g] = live ? cf[a2 * 6 + g] : 0.0;
+                    for (int g = 0; g < 6; ++g) c2[g] = live ? cf[a2 * 6 + g] : T(0);
                     const bool ulo = live && nlo >= 0, uhi = live && nhi < ms;
                     const int olo = 3 * nlo - wc0, ohi = 3 * nhi - wc0;
 #pragma unroll
                     for (int u = 0; u < (WN * 16 + 63) / 64; ++u) {
                         const int i = (lane >> 4) + 4 * u;
                         if (i >= WN) break;
-                        double zv = 0.0;
+                        T zv = T(0);
                         if (i < nr) {
-                            const double* wr = win + i * WN;
+                            const T* wr = win + i * WN;
 #pragma unroll
                             for (int g = 0; g < 3; ++g) {
                                 if (ulo) zv = fma(wr[olo + g], c2[g], zv);
@@ -698,11 +777,11 @@ __global__ void __launch_bounds__(F2_THREADS) k_factor2(FactorArgs A) {
                 const int a2 = c0 + cc;
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    const int a = r0 + cr + 4 * q;
+                    const int a = r0 + F2T<T>::row(cr, q);
                     if (a < m && a2 < m) {
                         const int nlo = a / 3 - 1 + dn, nhi = a / 3 + dn;
-                        const double* c1 = cf + a * 6;
-                        double u = 0.0;
+                        const T* c1 = cf + a * 6;
+                        T u = T(0);
 #pragma unroll
                         for (int g = 0; g < 3; ++g) {
                             if (nlo >= 0) u = fma(c1[g], zb[(3 * nlo + g - wr0) * 16 + cc], u);
@@ -734,8 +813,8 @@ __global__ void __launch_bounds__(F2_THREADS) k_factor2(FactorArgs A) {
                 // processed; issues are unconditional (an index past the last
                 // item reloads its window, unused) so that the only waits are
                 // for the window about to be stored
-                double wa[NWL], wb[NWL];
-                auto iss = [&](int it, double (&w)[NWL]) { issue(min(it, nitem - 1), w); };
+                T wa[NWL], wb[NWL];
+                auto iss = [&](int it, T (&w)[NWL]) { issue(min(it, nitem - 1), w); };
                 if (nitem > 0) iss(0, wa);
 #pragma unroll 1
                 for (int it = 0; it < nitem; it += 2) {
@@ -748,7 +827,7 @@ __global__ void __launch_bounds__(F2_THREADS) k_factor2(FactorArgs A) {
             // blocks of this wave beyond nbw stay zero (never used)
             for (int b = nbw; b < F2_MAXBLK; ++b)
 #pragma unroll
-                for (int q = 0; q < 4; ++q) bscr[(b * 4 + q) * 64 + lane] = 0.0;
+                for (int q = 0; q < 4; ++q) bscr[(b * 4 + q) * 64 + lane] = T(0);
 #pragma unroll
             for (int b = 0; b < F2_MAXBLK; ++b)
 #pragma unroll
@@ -757,8 +836,8 @@ __global__ void __launch_bounds__(F2_THREADS) k_factor2(FactorArgs A) {
         __syncthreads();   // LDS (Aself/Anext/Bl) is reused for the exchange column below
 
         if (rowA == 0 && own.h == 0)                      // hand the first pivot block to the server
-            f2_publish_diag(acc, dslot + ((npiv + 1) & 1) * 2 * TSZ, A.epoch + npiv + 1, 0, nblk, own, wv, cr, cc);
-        f2_publish(acc, xch + (int64_t)(phase & 1) * NT * TSZ, 0, nblk, own, wv, cr, cc);
+            f2_publish_diag<T>(acc, dslot + ((npiv + 1) & 1) * 2 * TSZ, A.epoch + npiv + 1, 0, nblk, own, wv, cr, cc);
+        f2_publish<T>(acc, xch + (int64_t)(phase & 1) * NT * TSZ, 0, nblk, own, wv, cr, cc);
         f2_signal(cnt);
         ++phase;
 
@@ -772,31 +851,31 @@ __global__ void __launch_bounds__(F2_THREADS) k_factor2(FactorArgs A) {
             cc = fr;
             ++npiv;
             if (!f2_wait(cnt, Pf * phase, A, sub, &sh_ok)) return;
-            const double* xb = xch + (int64_t)((phase - 1) & 1) * NT * TSZ;
+            const T* xb = xch + (int64_t)((phase - 1) & 1) * NT * TSZ;
             const uint64_t* pb = pslot + (npiv & 1) * 2 * TSZ;
             // the column straight into LDS (device-scope 16-byte loads, no
             // registers), while the pivot server is still forming Pi_k:
             // instruction q fills LDS chunks 64 q .. 64 q + 63 of the permuted
             // layout, lane l fetching the chunk that belongs at position 64 q + l
             {
-                const int ln = tido & 63, nq = nslots * (TSZ / 128);
+                // E values per 16-byte chunk, CPR chunks per tile row, LPT loads
+                // (of 64 chunks) per tile
+                constexpr int E = F2T<T>::EPC, CPR = TS / E, LPT = TSZ / (64 * E);
+                const int ln = tido & 63, nq = nslots * LPT;
                 const int wvu = __builtin_amdgcn_readfirstlane(wv);
 #pragma unroll
-                for (int u = 0; u < F2_SLOTS * (TSZ / 128) / F2_NW; ++u) {
+                for (int u = 0; u < F2_SLOTS * LPT / F2_NW; ++u) {
                     const int q = wvu + F2_NW * u;
                     if (q >= nq) break;
-                    const int sl = q / (TSZ / 128), p = (q % (TSZ / 128)) * 64 + ln;
+                    const int sl = q / LPT, p = (q % LPT) * 64 + ln;
                     const int J = sl < npar ? own.h + own.sp * sl : ((sl == npar && xtraA) ? rowA : rowB);
                     const int dsl = f2_slot(own, J);
-                    const int r = p >> 4, ch = (p & 15) ^ (r & 15);
-                    __builtin_amdgcn_global_load_lds(
-                        xb + J * TSZ + r * TS + 2 * ch,
-                        (__attribute__((address_space(3))) void*)(colk + (dsl * (TSZ / 128) + q % (TSZ / 128)) * 128),
-                        16, 0, 16 /* sc1: device scope */);
+                    const int r = p / CPR, ch = (p % CPR) ^ (r & (CPR - 1));
+                    f2_load_lds16(xb + J * TSZ + r * TS + E * ch, colk + (dsl * LPT + q % LPT) * 64 * E);
                 }
                 __builtin_amdgcn_s_waitcnt(0);
             }
-            if (!f2_tpoll(pb, A.epoch + npiv, piv, A.status, A.status, A.spin_limit, sub, tido)) return;
+            if (!f2_tpoll<T, T>(pb, A.epoch + npiv, piv, LDPT, A.status, A.status, A.spin_limit, sub, tido)) return;
             __builtin_amdgcn_sched_barrier(0);
             __syncthreads();
             // X_I = S_Ik Pi for the own rows I != k
@@ -806,15 +885,15 @@ __global__ void __launch_bounds__(F2_THREADS) k_factor2(FactorArgs A) {
                 // 4 blocks of 16x16 per row, one per wave
                 {
                     const int qi = (wv >> 1) & 1, qj = wv & 1;
-                    d4 x = {0.0, 0.0, 0.0, 0.0};
+                    V4 x = {T(0), T(0), T(0), T(0)};
                     #pragma unroll
                     for (int ks = 0; ks < TS / 4; ++ks) {
-                        const double a = colk[colk_at(f2_slot(own, I), 16 * qi + fr, 4 * ks + fk)];
-                        const double b = piv[(4 * ks + fk) * LDP + 16 * qj + fr];
-                        x = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, x, 0, 0, 0);
+                        const T a = colk[colk_at_t<T>(f2_slot(own, I), 16 * qi + fr, 4 * ks + fk)];
+                        const T b = piv[(4 * ks + fk) * LDPT + 16 * qj + fr];
+                        x = F2T<T>::mfma(a, b, x);
                     }
                     #pragma unroll
-                    for (int q = 0; q < 4; ++q) xr[rr * LTILE + (16 * qi + cr + 4 * q) * LDP + 16 * qj + cc] = x[q];
+                    for (int q = 0; q < 4; ++q) xr[rr * LTT + (16 * qi + F2T<T>::row(cr, q)) * LDPT + 16 * qj + cc] = x[q];
                 }
             }
             __syncthreads();
@@ -844,46 +923,49 @@ __global__ void __launch_bounds__(F2_THREADS) k_factor2(FactorArgs A) {
                     // sum up to rounding), so that a lane's operands of two slices
                     // are one 16-byte LDS read; all 8 reads are issued before the
                     // 8 products, so only the first product waits on LDS.
-                    d2 av[4], bv[4];
+                    // (16-byte reads: 2 values each in FP64, 4 in FP32)
+                    constexpr int E = F2T<T>::EPC, NR = 8 / E;
+                    using VE = T __attribute__((ext_vector_type(E)));
+                    VE av[NR], bv[NR];
                     #pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        av[u] = *reinterpret_cast<const d2*>(&xr[rr * LTILE + (16 * qi + fr) * LDP + 8 * fk + 2 * u]);
-                        bv[u] = *reinterpret_cast<const d2*>(&colk[colk_at(f2_slot(own, J), 16 * qj + fr, 8 * fk + 2 * u)]);
+                    for (int u = 0; u < NR; ++u) {
+                        av[u] = *reinterpret_cast<const VE*>(&xr[rr * LTT + (16 * qi + fr) * LDPT + 8 * fk + E * u]);
+                        bv[u] = *reinterpret_cast<const VE*>(
+                            &colk[colk_at_t<T>(f2_slot(own, J), 16 * qj + fr, 8 * fk + E * u)]);
                     }
-                    d4 v = acc[b];
+                    V4 v = acc[b];
                     #pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        v = __builtin_amdgcn_mfma_f64_16x16x4f64(-av[u][0], bv[u][0], v, 0, 0, 0);
-                        v = __builtin_amdgcn_mfma_f64_16x16x4f64(-av[u][1], bv[u][1], v, 0, 0, 0);
-                    }
-                    __builtin_amdgcn_sched_group_barrier(0x100, 8, 0);   // the 8 LDS reads
-                    __builtin_amdgcn_sched_group_barrier(0x008, 8, 0);   // then the 8 products
+                    for (int u = 0; u < NR; ++u)
+                        #pragma unroll
+                        for (int e = 0; e < E; ++e) v = F2T<T>::mfma(-av[u][e], bv[u][e], v);
+                    __builtin_amdgcn_sched_group_barrier(0x100, 2 * NR, 0);   // the LDS reads
+                    __builtin_amdgcn_sched_group_barrier(0x008, 8, 0);        // then the 8 products
                     acc[b] = v;
                 } else if (I != k) {        // J == k: S_Ik <- X_I
                     #pragma unroll
-                    for (int q = 0; q < 4; ++q) acc[b][q] = xr[rr * LTILE + (16 * qi + cr + 4 * q) * LDP + 16 * qj + cc];
+                    for (int q = 0; q < 4; ++q) acc[b][q] = xr[rr * LTT + (16 * qi + F2T<T>::row(cr, q)) * LDPT + 16 * qj + cc];
                 } else if (J != k) {        // I == k: S_kJ <- Pi S_kJ = Pi colk[J]^T
-                    d4 v = {0.0, 0.0, 0.0, 0.0};
+                    V4 v = {T(0), T(0), T(0), T(0)};
                     #pragma unroll
                     for (int ks = 0; ks < TS / 4; ++ks) {
-                        const double a = piv[(16 * qi + fr) * LDP + 4 * ks + fk];
-                        const double bb = colk[colk_at(f2_slot(own, J), 16 * qj + fr, 4 * ks + fk)];
-                        v = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb, v, 0, 0, 0);
+                        const T a = piv[(16 * qi + fr) * LDPT + 4 * ks + fk];
+                        const T bb = colk[colk_at_t<T>(f2_slot(own, J), 16 * qj + fr, 4 * ks + fk)];
+                        v = F2T<T>::mfma(a, bb, v);
                     }
                     acc[b] = v;
                 } else {                    // S_kk <- -Pi
                     #pragma unroll
-                    for (int q = 0; q < 4; ++q) acc[b][q] = -piv[(16 * qi + cr + 4 * q) * LDP + 16 * qj + cc];
+                    for (int q = 0; q < 4; ++q) acc[b][q] = -piv[(16 * qi + F2T<T>::row(cr, q)) * LDPT + 16 * qj + cc];
                 }
                 // keep the scheduler from hoisting the operand loads of all
                 // blocks at once (register budget)
                 __builtin_amdgcn_sched_barrier(0);
             }
             if (pass == 0)
-                f2_publish_diag(acc, dslot + ((npiv + 1) & 1) * 2 * TSZ, A.epoch + npiv + 1, kn, nblk, own, wv, cr,
+                f2_publish_diag<T>(acc, dslot + ((npiv + 1) & 1) * 2 * TSZ, A.epoch + npiv + 1, kn, nblk, own, wv, cr,
                                 cc);
             if (pass == 1 && kn < NT) {
-                f2_publish(acc, xch + (int64_t)(phase & 1) * NT * TSZ, kn, nblk, own, wv, cr, cc);
+                f2_publish<T>(acc, xch + (int64_t)(phase & 1) * NT * TSZ, kn, nblk, own, wv, cr, cc);
                 f2_signal(cnt);
             }
             }
@@ -895,14 +977,14 @@ __global__ void __launch_bounds__(F2_THREADS) k_factor2(FactorArgs A) {
                 // block's values are a short LDS read away.
                 constexpr int NSTG = 12;                 // staged blocks per wave (LDS budget)
                 __syncthreads();
-                double* stg = colk + wv * NSTG * 256;
+                T* stg = colk + wv * NSTG * 256;
 #pragma unroll
                 for (int b = 0; b < NSTG; ++b)
 #pragma unroll
                     for (int q = 0; q < 4; ++q) stg[(b * 4 + q) * 64 + lane] = acc[b][q];
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                auto store_block = [&](int b, const double (&vals)[4]) {
+                auto store_block = [&](int b, const T (&vals)[4]) {
                     const int blk = wv + F2_NW * b;
                     int I, J;
                     f2_tile_of(blk >> 2, own, I, J);
@@ -913,15 +995,15 @@ __global__ void __launch_bounds__(F2_THREADS) k_factor2(FactorArgs A) {
                     float* tf = reinterpret_cast<float*>(Tout) + toff;
 #pragma unroll
                     for (int q = 0; q < 4; ++q) {
-                        const int r = 16 * qi + cr + 4 * q, c = 16 * qj + cc;
+                        const int r = 16 * qi + F2T<T>::row(cr, q), c = 16 * qj + cc;
                         if (I == J && r < c) continue;           // diagonal tiles: mirror the lower half
-                        const double v = -vals[q];
-                        if (A.fp32) {
+                        const T v = -vals[q];
+                        if (sizeof(T) == 4 || A.fp32) {
                             tf[r * TS + c] = (float)v;
                             if (I == J) tf[c * TS + r] = (float)v;
                         } else {
-                            tl[r * TS + c] = v;
-                            if (I == J) tl[c * TS + r] = v;
+                            tl[r * TS + c] = (double)v;
+                            if (I == J) tl[c * TS + r] = (double)v;
                         }
                         if (!mid) {                              // the next line of this chain needs it
                             const int ga = I * TS + r, gc = J * TS + c;
@@ -941,7 +1023,7 @@ __global__ void __launch_bounds__(F2_THREADS) k_factor2(FactorArgs A) {
                         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
                     }
                     const int sb = b < NSTG ? b : 0;
-                    double vals[4];
+                    T vals[4];
 #pragma unroll
                     for (int q = 0; q < 4; ++q) vals[q] = stg[(sb * 4 + q) * 64 + lane];
                     store_block(b, vals);
@@ -952,7 +1034,11 @@ __global__ void __launch_bounds__(F2_THREADS) k_factor2(FactorArgs A) {
     }
 }
 
-const void* factor2_kernel() { return (const void*)k_factor2; }
+template <typename T>
+const void* factor2_kernel_of() {
+    return (const void*)k_factor2<T>;
+}
+const void* factor2_kernel(int fp32) { return fp32 ? factor2_kernel_of<float>() : factor2_kernel_of<double>(); }
 
 int launch_line_coeffs(sf_context* c) {
     int maxn = 0;
@@ -962,15 +1048,20 @@ int launch_line_coeffs(sf_context* c) {
     return hipGetLastError() == hipSuccess ? SF_OK : SF_ERR_HIP;
 }
 
-int launch_factor2(sf_context* c, int sub0, int nsub_chunk, int Pf) {
+// One cooperative factor launch: subdomains [sub0, sub0 + nsub_chunk), or
+// the nsub_chunk subdomains listed at sublist (device), in FP64 or FP32
+// arithmetic (fp32_arith; the tiles are then stored in FP32), with the pivot
+// threshold ptol; rejected pivots flag their subdomain in c->fail_d.
+int launch_factor2(sf_context* c, int sub0, int nsub_chunk, int Pf, int fp32_arith, const int32_t* sublist,
+                   int lanes, double ptol) {
     FactorArgs a;
     a.subs = c->d_subs;
-    a.sub0 = sub0;
-    a.nsub = sub0 + nsub_chunk;
-    a.lanes = c->factor_lanes;
+    a.sub0 = sublist ? 0 : sub0;
+    a.nsub = a.sub0 + nsub_chunk;
+    a.lanes = lanes;
     a.pf = Pf;
     a.groups = c->groups;
-    a.fp32 = c->cfg.factor_precision == SF_FP32 ? 1 : 0;
+    a.fp32 = c->cfg.factor_precision != SF_FP64 ? 1 : 0;
     a.f0 = c->f0;
     a.al = c->alpha;
     a.factors = c->factors;
@@ -981,14 +1072,17 @@ int launch_factor2(sf_context* c, int sub0, int nsub_chunk, int Pf) {
     a.H = c->H;
     a.lam = c->cfg.lambda;
     a.spin_limit = 1ll << 20;
+    a.ptol = ptol;
+    a.fail = c->fail_d;
+    a.sublist = sublist;
     // tags must differ from those left in the slots by earlier launches
     a.epoch = c->factor_epoch;
     int maxpiv = 0;
     for (const auto& d : c->subs) maxpiv = std::max(maxpiv, d.nt * d.NT);
     c->factor_epoch += (uint32_t)maxpiv + 4;
     void* args[] = {&a};
-    const int L = c->factor_lanes;
-    if (hipLaunchCooperativeKernel((const void*)k_factor2, dim3(L * ((nsub_chunk + L - 1) / L) * c->groups * (Pf + 1)),
+    const int L = lanes;
+    if (hipLaunchCooperativeKernel(factor2_kernel(fp32_arith), dim3(L * ((nsub_chunk + L - 1) / L) * c->groups * (Pf + 1)),
                                    dim3(F2_THREADS), args, 0, c->stream) != hipSuccess)
         return SF_ERR_HIP;
     return SF_OK;

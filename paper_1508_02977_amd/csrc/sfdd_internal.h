@@ -93,6 +93,8 @@ struct sf_context {
     uint32_t *counters;             // [2 nsub] factor synchronisation, one per chain
     uint64_t *etamax_bits;          // [B]
     int32_t *flags_d;               // [4] input validation flags
+    int32_t *fail_d;                // [nsub] subdomains whose factor met a rejected pivot
+    int32_t *sublist_d;             // [1] the subdomain of a single-subdomain factor launch
     // subdomain storage
     double *factors;                // all subdomains' tiles and couplings
     double *work;                   // factor workspaces + sweep scratch
@@ -101,6 +103,8 @@ struct sf_context {
     sfdd::DevStatus status_h;       // last error detail
     // host staging (pinned)
     void *host_stage;
+    void *host_fail;                // [nsub] failure flags of the FP32 factorisation
+    int fp64_fallbacks;             // subdomains of the last factorisation refactored in FP64
     // device address of the allocation-free entry point's static scratch array
     double *scratch;
     // graph-replayed Schwarz loop (sf_schwarz_solve_graph): a private stream,
@@ -139,9 +143,10 @@ int launch_residual_scratch(sf_context* c, const double* U, double* r, double* s
 int launch_alpha_update(sf_context* c, const double* eta, double* alpha_out, double kappa,
                         double eta_thr, double alpha_th);
 int launch_factor(sf_context* c);
-int launch_factor2(sf_context* c, int sub0, int nsub_chunk, int Pf);
+int launch_factor2(sf_context* c, int sub0, int nsub_chunk, int Pf, int fp32_arith, const int32_t* sublist,
+                   int lanes, double ptol);
 int launch_line_coeffs(sf_context* c);
-const void* factor2_kernel();
+const void* factor2_kernel(int fp32);
 int launch_sweep(sf_context* c, double* U, const double* r, int single_sub, const double* b_local,
                  double* x_local);
 uint32_t sweep_epoch_step(const sf_context* c);   // tag base advance of one sweep launch

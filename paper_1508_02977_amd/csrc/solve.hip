@@ -715,7 +715,7 @@ int launch_sweep(sf_context* c, double* U, const double* r, int single_sub, cons
     c->sweep_epoch += sweep_epoch_step(c);
     const int ranks = c->groups * c->maxP;
     const int form = sweep_form(c);
-    const void* kern = sweep_kernel(form, c->cfg.factor_precision == SF_FP32);
+    const void* kern = sweep_kernel(form, c->cfg.factor_precision != SF_FP64);
     const int threads = sweep_threads(form);
     void* args[] = {&a};
     // A captured launch is an ordinary kernel node: the grid fits the
