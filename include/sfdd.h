@@ -89,6 +89,16 @@ typedef struct sf_config {
                                  data term)                                     */
     double  pivot_tol;        /* SF_FP32_FACTOR: relative pivot threshold of the
                                  FP32 factorisation (0 = default 1e-5)          */
+    int32_t deferred_status;  /* 0: sf_assemble and sf_factor_subdomains wait
+                                 for the stream and return the input check and
+                                 pivot status themselves.  1: they only enqueue
+                                 (no host synchronisation, capturable in a HIP
+                                 graph); that status is collected by the next
+                                 call that reads the context's results (solve,
+                                 residual, rhs, indicator, alpha update,
+                                 adjoint) or by sf_sync, which returns it.  The
+                                 FP64 refactorisation of SF_FP32_FACTOR
+                                 subdomains with a rejected pivot runs there.  */
 } sf_config;
 
 typedef struct sf_context sf_context;
@@ -112,6 +122,11 @@ void sf_destroy(sf_context* ctx);
  * value is not finite and SF_ERR_INVALID if an alpha is not finite or <= 0.
  * Makes previous factors stale.                                             */
 int sf_assemble(sf_context* ctx, const double* I0, const double* I1, const double* alpha);
+
+/* Wait for the context's stream and collect a status that sf_assemble or
+ * sf_factor_subdomains left pending (deferred_status = 1): their return
+ * value as it would have been without deferral (SF_OK if nothing pends).  */
+int sf_sync(sf_context* ctx);
 
 /* Section 3.2, local problems: factor every subdomain matrix A_i = A[S_i,S_i]
  * (ordering: lines along the shorter box side, 3 unknowns per node, band

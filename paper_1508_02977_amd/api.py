@@ -45,6 +45,7 @@ class sf_config(ctypes.Structure):
         ("lambda_", c_double), ("sigma", c_double),
         ("factor_precision", c_int32), ("band_tile", c_int32),
         ("rho", c_double), ("pivot_tol", c_double),
+        ("deferred_status", c_int32),
     ]
 
 
@@ -64,6 +65,7 @@ _SIGS = {
     "sf_destroy": (None, [c_void_p]),
     "sf_assemble": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "sf_factor_subdomains": (c_int32, [c_void_p]),
+    "sf_sync": (c_int32, [c_void_p]),
     "sf_schwarz_solve": (c_int32, [c_void_p, c_void_p, c_double, c_int32, c_void_p, c_void_p]),
     "sf_schwarz_solve_graph": (c_int32, [c_void_p, c_void_p, c_double, c_int32, c_void_p, c_void_p]),
     "sf_autotune": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p]),
@@ -203,18 +205,19 @@ class Context:
 
 
 def make_config(width, height, batch=1, parts_x=1, parts_y=1, overlap=0, lam=1.0, sigma=0.0,
-                factor_precision=SF_FP64, band_tile=0, rho=0.0, pivot_tol=0.0) -> sf_config:
+                factor_precision=SF_FP64, band_tile=0, rho=0.0, pivot_tol=0.0, deferred_status=0) -> sf_config:
     return sf_config(width, height, batch, parts_x, parts_y, overlap, lam, sigma, factor_precision, band_tile,
-                     rho, pivot_tol)
+                     rho, pivot_tol, deferred_status)
 
 
 # ---- the C entry points --------------------------------------------------
 
 def sf_create(width, height, batch=1, parts_x=1, parts_y=1, overlap=0, lam=1.0, sigma=0.0,
-              factor_precision=SF_FP64, band_tile=0, stream=None, rho=0.0, pivot_tol=0.0) -> Context:
+              factor_precision=SF_FP64, band_tile=0, stream=None, rho=0.0, pivot_tol=0.0,
+              deferred_status=0) -> Context:
     import torch
     cfg = make_config(width, height, batch, parts_x, parts_y, overlap, lam, sigma, factor_precision, band_tile,
-                      rho, pivot_tol)
+                      rho, pivot_tol, deferred_status)
     if stream is None:
         stream = torch.cuda.current_stream()
     h = c_void_p()
@@ -238,6 +241,12 @@ def sf_assemble(ctx: Context, I0, I1, alpha) -> None:
 def sf_factor_subdomains(ctx: Context) -> None:
     ctx.version += 1
     _check(lib().sf_factor_subdomains(ctx.handle), "sf_factor_subdomains", ctx)
+
+
+def sf_sync(ctx: Context) -> None:
+    """Wait for the context's stream; raises the status that a deferred
+    sf_assemble / sf_factor_subdomains left pending."""
+    _check(lib().sf_sync(ctx.handle), "sf_sync", ctx)
 
 
 def sf_schwarz_solve(ctx: Context, U, rtol: float, max_sweeps: int):
@@ -295,7 +304,7 @@ def sf_update_alpha(ctx: Context, U, alpha, kappa=1.0, eta_thr=0.1, alpha_th=1e-
     ctx.version += 1
     _check(lib().sf_update_alpha(ctx.handle, _dev(U, ctx.field_shape(), "U"),
                                  _dev(alpha, ctx.alpha_shape(), "alpha"), float(kappa), float(eta_thr),
-                                 float(alpha_th), ctypes.cast(em, c_void_p)), "sf_update_alpha")
+                                 float(alpha_th), ctypes.cast(em, c_void_p)), "sf_update_alpha", ctx)
     return list(em)
 
 
@@ -310,13 +319,13 @@ def sf_status_string(code: int) -> str:
 
 
 def sf_rhs(ctx: Context, F) -> None:
-    _check(lib().sf_rhs(ctx.handle, _dev(F, ctx.field_shape(), "F")), "sf_rhs")
+    _check(lib().sf_rhs(ctx.handle, _dev(F, ctx.field_shape(), "F")), "sf_rhs", ctx)
 
 
 def sf_residual(ctx: Context, U, r):
     n2 = (c_double * ctx.B)()
     _check(lib().sf_residual(ctx.handle, _dev(U, ctx.field_shape(), "U"), _dev(r, ctx.field_shape(), "r"),
-                             ctypes.cast(n2, c_void_p)), "sf_residual")
+                             ctypes.cast(n2, c_void_p)), "sf_residual", ctx)
     return list(n2)
 
 
@@ -326,13 +335,13 @@ def sf_residual_noalloc(ctx: Context, U, r, norms=True):
     NULL (no synchronisation) and returns None."""
     n2 = (c_double * ctx.B)()
     _check(lib().sf_residual_noalloc(ctx.handle, _dev(U, ctx.field_shape(), "U"), _dev(r, ctx.field_shape(), "r"),
-                                     ctypes.cast(n2, c_void_p) if norms else c_void_p()), "sf_residual_noalloc")
+                                     ctypes.cast(n2, c_void_p) if norms else c_void_p()), "sf_residual_noalloc", ctx)
     return list(n2) if norms else None
 
 
 def sf_indicator(ctx: Context, U, eta) -> None:
     _check(lib().sf_indicator(ctx.handle, _dev(U, ctx.field_shape(), "U"), _dev(eta, ctx.alpha_shape(), "eta")),
-           "sf_indicator")
+           "sf_indicator", ctx)
 
 
 def sf_plan(width, height, batch=1, parts_x=1, parts_y=1, overlap=0, lam=1.0):

@@ -12,6 +12,7 @@ using sfdd::SubDesc;
 namespace {
 
 constexpr int ST_CREATED = 0, ST_ASSEMBLED = 1, ST_FACTORED = 2;
+constexpr int PENDING_ASSEMBLE = 1, PENDING_FACTOR = 2;
 constexpr int MAX_LINE = 768;        // largest padded line matrix (3 x the shorter box side, rounded up to 32)
 
 template <class T>
@@ -63,6 +64,9 @@ int fill_i32(sf_context* c, int32_t* p, int n, int32_t v) {
     return hipGetLastError() == hipSuccess ? SF_OK : SF_ERR_HIP;
 }
 
+// Per-chain counters of the cooperative factor, cleared before each launch.
+int zero_factor_counters(sf_context* c) { return fill_i32(c, (int32_t*)c->counters, 2 * sfdd::F2_COUNTERS * c->nsub, 0); }
+
 // Pinned staging layout: status word at 0, flags at 64, then three arrays of
 // B 8-byte slots (A: done flags / norms, B: relres, C: sweeps).
 constexpr size_t STAGE_FLAGS = 64, STAGE_A = 128;
@@ -87,7 +91,7 @@ int check_config(const sf_config& k) {
     if (k.overlap < 0 || !(k.lambda > 0.0) || !std::isfinite(k.lambda)) return SF_ERR_INVALID;
     if (!(k.sigma >= 0.0 && k.sigma <= SF_SIGMA_MAX) || !(k.rho >= 0.0 && k.rho <= SF_SIGMA_MAX) ||
         (k.factor_precision != SF_FP64 && k.factor_precision != SF_FP32 && k.factor_precision != SF_FP32_FACTOR) ||
-        !(k.pivot_tol >= 0.0 && k.pivot_tol < 1.0) ||
+        !(k.pivot_tol >= 0.0 && k.pivot_tol < 1.0) || (k.deferred_status != 0 && k.deferred_status != 1) ||
         k.band_tile < 0)
         return SF_ERR_INVALID;
     if ((int64_t)k.width * k.height * k.batch > (1ll << 31)) return SF_ERR_INVALID;
@@ -499,18 +503,32 @@ int sf_create(const sf_config* cfg, void* stream, sf_context** out) {
     return SF_OK;
 }
 
-int sf_assemble(sf_context* c, const double* I0, const double* I1, const double* alpha) {
-    if (!c || !I0 || !I1 || !alpha) return SF_ERR_INVALID;
-    c->state = ST_CREATED;
-    SF_TRY(sfdd::prof_begin(c, sfdd::PROF_OTHER));
-    SF_TRY(fill_i32(c, c->flags_d, 4, 0));
-    SF_TRY(sfdd::launch_validate(c, I0, I1, alpha));
+// The input check of sf_assemble: the flags k_validate left (waits for the stream).
+static int assemble_status(sf_context* c) {
     int32_t* hf = (int32_t*)((char*)c->host_stage + STAGE_FLAGS);
     SF_HIP(hipMemcpyAsync(hf, c->flags_d, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
     SF_HIP(hipStreamSynchronize(c->stream));
-    if (hf[0] || hf[1]) {
-        SF_TRY(sfdd::prof_end(c));
-        return hf[0] ? SF_NONFINITE : SF_ERR_INVALID;
+    if (hf[0] || hf[1]) return hf[0] ? SF_NONFINITE : SF_ERR_INVALID;
+    return SF_OK;
+}
+
+int sf_assemble(sf_context* c, const double* I0, const double* I1, const double* alpha) {
+    if (!c || !I0 || !I1 || !alpha) return SF_ERR_INVALID;
+    c->state = ST_CREATED;
+    c->pending = 0;                         // a status of earlier data no longer applies
+    SF_TRY(sfdd::prof_begin(c, sfdd::PROF_OTHER));
+    SF_TRY(fill_i32(c, c->flags_d, 4, 0));
+    SF_TRY(sfdd::launch_validate(c, I0, I1, alpha));
+    if (c->cfg.deferred_status) {
+        // the kernels below run on whatever the frames hold; the check is
+        // reported by the next call that collects the status
+        c->pending |= PENDING_ASSEMBLE;
+    } else {
+        const int code = assemble_status(c);
+        if (code != SF_OK) {
+            SF_TRY(sfdd::prof_end(c));
+            return code;
+        }
     }
     if (c->blur_r > 0) {
         // smoothed frames in the residual array (free until the first solve)
@@ -531,17 +549,15 @@ int sf_assemble(sf_context* c, const double* I0, const double* I1, const double*
     return SF_OK;
 }
 
+static int factor_status(sf_context* c);
+
 int sf_factor_subdomains(sf_context* c) {
     if (!c) return SF_ERR_INVALID;
     if (c->state < ST_ASSEMBLED) return SF_ERR_STATE;
+    c->state = ST_ASSEMBLED;                // until the new factors are complete
     SF_TRY(sfdd::prof_begin(c, sfdd::PROF_FACTOR));
     const int fp32_arith = c->cfg.factor_precision == SF_FP32_FACTOR && c->factor_pf > 0;
-    const int ncnt = 2 * sfdd::F2_COUNTERS * c->nsub;
-    auto zero_counters = [&]() -> int {
-        hipLaunchKernelGGL(k_fill_i32, dim3((ncnt + 255) / 256), dim3(256), 0, c->stream, (int32_t*)c->counters, ncnt,
-                           0);
-        return hipGetLastError() == hipSuccess ? SF_OK : SF_ERR_HIP;
-    };
+    c->pending &= ~PENDING_FACTOR;
     if (c->factor_pf > 0) {
         SF_TRY(sfdd::launch_line_coeffs(c));
         hipLaunchKernelGGL(k_zero_status_api, dim3(1), dim3(1), 0, c->stream, c->status_d);
@@ -553,13 +569,26 @@ int sf_factor_subdomains(sf_context* c) {
         const double ptol = fp32_arith ? (c->cfg.pivot_tol > 0.0 ? c->cfg.pivot_tol : 1e-5) : 1e-13;
         for (int s0 = 0; s0 < c->nsub; s0 += c->factor_chunk) {
             const int n = std::min(c->factor_chunk, c->nsub - s0);
-            SF_TRY(zero_counters());
+            SF_TRY(zero_factor_counters(c));
             SF_TRY(sfdd::launch_factor2(c, s0, n, c->factor_pf, fp32_arith, nullptr, c->factor_lanes, ptol));
         }
     } else {
         SF_TRY(sfdd::launch_factor(c));
     }
     SF_TRY(sfdd::prof_end(c));
+    c->state = ST_FACTORED;
+    if (c->cfg.deferred_status) {
+        c->pending |= PENDING_FACTOR;
+        return SF_OK;
+    }
+    return factor_status(c);
+}
+
+// The pivot status of the factorisation just enqueued (waits for the
+// stream); with FP32 arithmetic, subdomains with a rejected pivot are
+// factored again in FP64 here.  On an error the factors are unusable.
+static int factor_status(sf_context* c) {
+    const int fp32_arith = c->cfg.factor_precision == SF_FP32_FACTOR && c->factor_pf > 0;
     int code = pull_status(c);
     SF_TRY(sfdd::prof_harvest(c));
     if (fp32_arith && code == SF_NOT_SPD) {
@@ -577,7 +606,7 @@ int sf_factor_subdomains(sf_context* c) {
             ++c->fp64_fallbacks;
             hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(1), 0, c->stream, c->sublist_d, 1, (int32_t)i);
             SF_HIP(hipGetLastError());
-            SF_TRY(zero_counters());
+            SF_TRY(zero_factor_counters(c));
             SF_TRY(sfdd::launch_factor2(c, 0, 1, sfdd::f2_ranks(c->subs[i].NT), 0, c->sublist_d, 1, 1e-13));
         }
         SF_TRY(sfdd::prof_end(c));
@@ -590,7 +619,40 @@ int sf_factor_subdomains(sf_context* c) {
         c->state = ST_ASSEMBLED;
         return code;
     }
-    c->state = ST_FACTORED;
+    return SF_OK;
+}
+
+#define SF_SETTLE(c)                           \
+    do {                                       \
+        const int sc_ = settle(c);             \
+        if (sc_ != SF_OK) return sc_;          \
+    } while (0)
+
+// Collect what sf_assemble / sf_factor_subdomains left pending (deferred
+// status): the input check first (on an error the context is back to
+// created), then the pivot status.
+static int settle(sf_context* c) {
+    if (c->pending & PENDING_ASSEMBLE) {
+        c->pending &= ~PENDING_ASSEMBLE;
+        const int code = assemble_status(c);
+        if (code != SF_OK) {
+            c->pending = 0;
+            c->state = ST_CREATED;
+            return code;
+        }
+    }
+    if (c->pending & PENDING_FACTOR) {
+        c->pending &= ~PENDING_FACTOR;
+        return factor_status(c);
+    }
+    return SF_OK;
+}
+
+int sf_sync(sf_context* c) {
+    if (!c) return SF_ERR_INVALID;
+    const int code = settle(c);
+    if (code != SF_OK) return code;
+    SF_HIP(hipStreamSynchronize(c->stream));
     return SF_OK;
 }
 
@@ -725,6 +787,7 @@ static int graph_iterations(sf_context* c, double* U, double rtol, int32_t max_s
 int sf_schwarz_solve_graph(sf_context* c, double* U, double rtol, int32_t max_sweeps, int32_t* sweeps,
                            double* relres) {
     if (!c || !U || max_sweeps < 0 || !(rtol >= 0.0)) return SF_ERR_INVALID;
+    SF_SETTLE(c);
     if (c->state != ST_FACTORED) return SF_ERR_STATE;
     if (!c->gstream) {
         // created together on first use; a failure leaves none of them, so a
@@ -766,12 +829,14 @@ int sf_schwarz_solve_graph(sf_context* c, double* U, double rtol, int32_t max_sw
 
 int sf_schwarz_solve(sf_context* c, double* U, double rtol, int32_t max_sweeps, int32_t* sweeps, double* relres) {
     if (!c || !U || max_sweeps < 0 || !(rtol >= 0.0)) return SF_ERR_INVALID;
+    SF_SETTLE(c);
     if (c->state != ST_FACTORED) return SF_ERR_STATE;
     return schwarz_loop(c, U, c->F, c->Fn2, rtol, max_sweeps, sweeps, relres);
 }
 
 int sf_autotune(sf_context* c, double* U, int32_t trials, int32_t* band_tile) {
     if (!c || !U || trials < 1) return SF_ERR_INVALID;
+    SF_SETTLE(c);
     if (c->state != ST_FACTORED) return SF_ERR_STATE;
     int maxnt = 0;
     for (const auto& d : c->subs) maxnt = std::max(maxnt, d.NT);
@@ -834,6 +899,7 @@ int sf_adjoint(sf_context* c, const double* U, const double* G, double* P, doubl
     if (!c || !U || !G || !P || max_sweeps < 0 || !(rtol >= 0.0)) return SF_ERR_INVALID;
     // gradients are taken with respect to unsmoothed frames and the plain data term
     if (c->blur_r > 0 || c->coef) return SF_ERR_INVALID;
+    SF_SETTLE(c);
     if (c->state != ST_FACTORED) return SF_ERR_STATE;
     SF_TRY(sfdd::launch_norm2(c, G, c->Gn2));
     const int rc = schwarz_loop(c, P, G, c->Gn2, rtol, max_sweeps, sweeps, relres);
@@ -849,6 +915,7 @@ int sf_adjoint(sf_context* c, const double* U, const double* G, double* P, doubl
 int sf_update_alpha(sf_context* c, const double* U, double* alpha, double kappa, double eta_thr, double alpha_th,
                     double* eta_max) {
     if (!c || !U || !alpha || !(kappa >= 0.0) || !std::isfinite(eta_thr) || !(alpha_th > 0.0)) return SF_ERR_INVALID;
+    SF_SETTLE(c);
     if (c->state < ST_ASSEMBLED) return SF_ERR_STATE;
     SF_TRY(sfdd::prof_begin(c, sfdd::PROF_OTHER));
     SF_TRY(sfdd::launch_indicator(c, U, c->eta, 1));
@@ -876,6 +943,7 @@ int sf_error_detail(const sf_context* c, int32_t* pair, int32_t* subdomain, int6
 
 int sf_rhs(sf_context* c, double* F) {
     if (!c || !F) return SF_ERR_INVALID;
+    SF_SETTLE(c);
     if (c->state < ST_ASSEMBLED) return SF_ERR_STATE;
     SF_HIP(hipMemcpyAsync(F, c->F, 3 * sizeof(double) * c->W * c->H * c->B, hipMemcpyDeviceToDevice, c->stream));
     return SF_OK;
@@ -883,6 +951,7 @@ int sf_rhs(sf_context* c, double* F) {
 
 int sf_residual(sf_context* c, const double* U, double* r, double* rnorm2) {
     if (!c || !U || !r) return SF_ERR_INVALID;
+    SF_SETTLE(c);
     if (c->state < ST_ASSEMBLED) return SF_ERR_STATE;
     SF_TRY(sfdd::launch_residual(c, U, r, 0, 0.0, 0, 0));
     if (rnorm2) {
@@ -896,6 +965,7 @@ int sf_residual(sf_context* c, const double* U, double* r, double* rnorm2) {
 
 int sf_residual_noalloc(sf_context* c, const double* U, double* r, double* rnorm2) {
     if (!c || !U || !r) return SF_ERR_INVALID;
+    SF_SETTLE(c);
     if (c->state < ST_ASSEMBLED) return SF_ERR_STATE;
     if (!c->scratch) return SF_ERR_STATE;
     if (sfdd::scratch_residual_doubles(c) * (int64_t)sizeof(double) > (int64_t)SF_NOALLOC_SCRATCH_BYTES)
@@ -913,6 +983,7 @@ int sf_residual_noalloc(sf_context* c, const double* U, double* r, double* rnorm
 
 int sf_indicator(sf_context* c, const double* U, double* eta) {
     if (!c || !U || !eta) return SF_ERR_INVALID;
+    SF_SETTLE(c);
     if (c->state < ST_ASSEMBLED) return SF_ERR_STATE;
     return sfdd::launch_indicator(c, U, eta, 1);
 }
@@ -1020,6 +1091,7 @@ int sf_subdomain_geometry(const sf_context* c, int32_t sub, int32_t* g) {
 
 int sf_subdomain_solve(sf_context* c, int32_t sub, const double* b, double* x) {
     if (!c || !b || !x || sub < 0 || sub >= c->nsub || b == x) return SF_ERR_INVALID;
+    SF_SETTLE(c);
     if (c->state != ST_FACTORED) return SF_ERR_STATE;
     hipLaunchKernelGGL(k_zero_status_api, dim3(1), dim3(1), 0, c->stream, c->status_d);
     SF_HIP(hipGetLastError());

@@ -60,6 +60,7 @@ struct sf_context {
     int W, H, B;
     int nsub;                       // over all pairs
     int state;                      // 0 created, 1 assembled, 2 factored
+    int pending;                    // deferred status: PENDING_ASSEMBLE | PENDING_FACTOR
     std::vector<sfdd::SubDesc> subs;
     sfdd::SubDesc* d_subs;
     int maxP;                       // sweep workgroups per chain
