@@ -4,9 +4,9 @@ The replayed chunk holds the same kernels in the same order as the ordinary
 loop, so the iterate, the sweep counts and the residuals must equal those of
 sf_schwarz_solve bit for bit: on small and ragged geometries, a batch with a
 pair that has nothing to solve, a max_sweeps that leaves a partial chunk,
-solves repeated with other work on the device in between, the FP32-tile
-sweep form, and the timed 640x480 workload.  One case is also held to the
-oracle's iterate.
+solves repeated with other work on the device in between, solves while
+another stream keeps the device busy, the FP32-tile sweep form, and the
+timed 640x480 workload.  One case is also held to the oracle's iterate.
 """
 import numpy as np
 import pytest
@@ -151,4 +151,30 @@ def test_graph_solve_with_fp32_tiles_equals_ordinary_solve(gpu):
     api.sf_factor_subdomains(ctx)
     (Ue, re), (Ug, rg) = both(ctx, 1e-9, 500)
     assert re[0] == api.SF_OK and rg == re and torch.equal(Ug, Ue)
+    ctx.close()
+
+
+def test_solves_beside_a_busy_stream(gpu):
+    # The replayed sweeps are ordinary launches whose workgroups wait on each
+    # other (their grid fits the co-resident capacity measured at creation);
+    # here the kernels of another stream hold CUs while they start, so some
+    # workgroups wait for others that are not yet resident.  Every wait is
+    # bounded; the solves (replayed and ordinary, cooperative) must still end
+    # with the iterate of the solve on an idle device.
+    ctx, _ = context("plain640", 3, 160, 120, 4, 4, 8)
+    Ue = torch.zeros(ctx.field_shape(), dtype=torch.float64, device="cuda")
+    re = api.sf_schwarz_solve(ctx, Ue, 1e-9, 500)
+    assert re[0] == api.SF_OK
+    side = torch.cuda.Stream()
+    a = torch.randn(2048, 2048, device="cuda")
+    torch.cuda.synchronize()
+    for solve in (api.sf_schwarz_solve_graph, api.sf_schwarz_solve):
+        with torch.cuda.stream(side):
+            for _ in range(100):
+                a = torch.tanh(a @ a * 1e-3)
+        U = torch.zeros(ctx.field_shape(), dtype=torch.float64, device="cuda")
+        r = solve(ctx, U, 1e-9, 500)
+        torch.cuda.synchronize()
+        assert r == re and torch.equal(U, Ue), solve.__name__
+    assert torch.isfinite(a).all()
     ctx.close()
