@@ -73,6 +73,27 @@ constexpr size_t STAGE_FLAGS = 64, STAGE_A = 128;
 inline char* stage_a(sf_context* c) { return (char*)c->host_stage + STAGE_A; }
 inline char* stage_b(sf_context* c) { return stage_a(c) + 8 * (size_t)c->B; }
 inline char* stage_c(sf_context* c) { return stage_b(c) + 8 * (size_t)c->B; }
+// Convergence-check slots: status, then B done flags, 64-byte aligned.
+inline size_t poll_slot_bytes(int B) { return (64 + 4 * (size_t)B + 63) / 64 * 64; }
+inline sfdd::DevStatus* poll_status(sf_context* c, int s) {
+    return (sfdd::DevStatus*)((char*)c->host_poll + s * poll_slot_bytes(c->B));
+}
+inline int32_t* poll_done(sf_context* c, int s) { return (int32_t*)((char*)poll_status(c, s) + 64); }
+// Queue the copies of the done flags and the status into slot s, then its event.
+static int poll_record(sf_context* c, int s) {
+    SF_HIP(hipMemcpyAsync(poll_done(c, s), c->done_d, c->B * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+    SF_HIP(hipMemcpyAsync(poll_status(c, s), c->status_d, sizeof(sfdd::DevStatus), hipMemcpyDeviceToHost, c->stream));
+    SF_HIP(hipEventRecord(c->poll_ev[s], c->stream));
+    return SF_OK;
+}
+// Wait for slot s; *stop when every pair is done or a device wait was abandoned.
+static int poll_check(sf_context* c, int s, bool* stop) {
+    SF_HIP(hipEventSynchronize(c->poll_ev[s]));
+    bool all = true;
+    for (int b = 0; b < c->B; ++b) all = all && poll_done(c, s)[b];
+    *stop = all || poll_status(c, s)->code != SF_OK;
+    return SF_OK;
+}
 
 int pull_status(sf_context* c) {
     sfdd::DevStatus* hs = (sfdd::DevStatus*)c->host_stage;
@@ -222,6 +243,9 @@ void sf_destroy(sf_context* c) {
         if (p) (void)hipFree(p);
     if (c->host_stage) (void)hipHostFree(c->host_stage);
     if (c->host_fail) (void)hipHostFree(c->host_fail);
+    if (c->host_poll) (void)hipHostFree(c->host_poll);
+    for (hipEvent_t e : c->poll_ev)
+        if (e) (void)hipEventDestroy(e);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     release_graph_resources(c);
     delete c;
@@ -469,6 +493,17 @@ int sf_create(const sf_config* cfg, void* stream, sf_context** out) {
         sf_destroy(c);
         return SF_ERR_OOM;
     }
+    if (hipHostMalloc(&c->host_poll, 2 * poll_slot_bytes(c->B), hipHostMallocDefault) != hipSuccess) {
+        c->host_poll = nullptr;
+        sf_destroy(c);
+        return SF_ERR_OOM;
+    }
+    for (hipEvent_t& e : c->poll_ev)
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+            e = nullptr;
+            sf_destroy(c);
+            return SF_ERR_HIP;
+        }
     // uploads and clears go on the context's stream, so the synchronisation
     // below covers them also when that stream does not wait for the null stream
     if (hipMemcpyAsync(c->d_subs, c->subs.data(), c->subs.size() * sizeof(SubDesc), hipMemcpyHostToDevice,
@@ -669,12 +704,15 @@ static int loop_prologue(sf_context* c, double* U, const double* rhs_n2) {
 }
 
 // Iterations k0 .. max_sweeps, one launch each (residual + convergence test,
-// then a sweep); the host looks at the done flags every 4 sweeps.
+// then a sweep).  Every 4 sweeps the done flags and the status are copied to
+// a host slot behind an event; the host reads the previous check while the
+// next 4 iterations are already queued, so the device never waits for the
+// host.  A pair that is done makes every kernel of the pair return at once,
+// so the iterations queued past convergence cost their launches only.
 static int loop_iterations(sf_context* c, double* U, const double* rhs, const double* rhs_n2, double rtol,
                            int32_t max_sweeps, int k0) {
-    int32_t* hd = (int32_t*)stage_a(c);
     const int check_every = 4;
-    sfdd::DevStatus* hst = (sfdd::DevStatus*)c->host_stage;
+    int nchk = 0;
     for (int k = k0; k <= max_sweeps; ++k) {
         SF_TRY(sfdd::prof_begin(c, sfdd::PROF_RESIDUAL));
         SF_TRY(sfdd::launch_residual(c, U, c->r, 1, rtol, k, max_sweeps, rhs, rhs_n2));
@@ -684,14 +722,13 @@ static int loop_iterations(sf_context* c, double* U, const double* rhs, const do
         SF_TRY(sfdd::launch_sweep(c, U, c->r, -1, nullptr, nullptr));
         SF_TRY(sfdd::prof_end(c));
         if ((k + 1) % check_every == 0) {
-            SF_HIP(hipMemcpyAsync(hd, c->done_d, c->B * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
-            SF_HIP(hipMemcpyAsync(hst, c->status_d, sizeof(sfdd::DevStatus), hipMemcpyDeviceToHost, c->stream));
-            SF_HIP(hipStreamSynchronize(c->stream));
-            SF_TRY(sfdd::prof_harvest(c));
-            if (hst->code != SF_OK) break;   // a device wait was abandoned
-            bool all = true;
-            for (int b = 0; b < c->B; ++b) all = all && hd[b];
-            if (all) break;
+            SF_TRY(poll_record(c, nchk & 1));
+            ++nchk;
+            if (nchk >= 2) {
+                bool stop = false;
+                SF_TRY(poll_check(c, (nchk - 2) & 1, &stop));
+                if (stop) break;
+            }
         }
     }
     return SF_OK;
@@ -761,14 +798,24 @@ static int graph_iterations(sf_context* c, double* U, double rtol, int32_t max_s
     c->graph_capture = 0;
     if (hipStreamEndCapture(c->stream, &g) != hipSuccess && rc == SF_OK) rc = SF_ERR_HIP;
     if (rc == SF_OK && hipGraphInstantiate(&ge, g, nullptr, nullptr, 0) != hipSuccess) rc = SF_ERR_HIP;
+    // Replays are queued one ahead: after queueing replay r the host waits
+    // for replay r - 1 only.  The flags it then reads were copied by replay
+    // r - 1 or, already, by replay r: done flags and the status only ever
+    // change towards "stop", so either is a valid check.
     int k = 0, replays = 0;
     while (rc == SF_OK && k + GRAPH_CHUNK <= max_sweeps) {
-        if (hipGraphLaunch(ge, c->stream) != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess) {
+        if (hipGraphLaunch(ge, c->stream) != hipSuccess ||
+            hipEventRecord(c->poll_ev[replays & 1], c->stream) != hipSuccess) {
             rc = SF_ERR_HIP;
             break;
         }
         ++replays;
         k += GRAPH_CHUNK;
+        if (replays < 2) continue;
+        if (hipEventSynchronize(c->poll_ev[(replays - 2) & 1]) != hipSuccess) {
+            rc = SF_ERR_HIP;
+            break;
+        }
         bool all = true;
         for (int b = 0; b < c->B; ++b) all = all && hd[b];
         if (hst->code != SF_OK || all) {
@@ -776,8 +823,20 @@ static int graph_iterations(sf_context* c, double* U, double rtol, int32_t max_s
             break;
         }
     }
+    // the last replays have not been looked at: one more check once they end
+    if (rc == SF_OK && k <= max_sweeps && replays > 0) {
+        if (hipStreamSynchronize(c->stream) != hipSuccess) {
+            rc = SF_ERR_HIP;
+        } else {
+            bool all = true;
+            for (int b = 0; b < c->B; ++b) all = all && hd[b];
+            if (hst->code != SF_OK || all) k = max_sweeps + 1;
+        }
+    }
     // the replays used tag bases e0 .. e0 + (GRAPH_CHUNK replays - 1) inc
     c->sweep_epoch = std::max(c->sweep_epoch, e0 + (uint32_t)(GRAPH_CHUNK * replays) * inc);
+    // (a replay may still be running: the executable graph goes once it ends)
+    if (replays > 0 && hipStreamSynchronize(c->stream) != hipSuccess && rc == SF_OK) rc = SF_ERR_HIP;
     if (ge) (void)hipGraphExecDestroy(ge);
     if (g) (void)hipGraphDestroy(g);
     *k_next = k;

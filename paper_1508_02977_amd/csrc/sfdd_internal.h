@@ -104,6 +104,11 @@ struct sf_context {
     sfdd::DevStatus status_h;       // last error detail
     // host staging (pinned)
     void *host_stage;
+    // convergence checks of the Schwarz loop: two pinned slots of [status,
+    // done flags [B]], each written behind its event, so that the host reads
+    // one check while the iterations after it are already queued
+    void *host_poll;
+    hipEvent_t poll_ev[2];
     void *host_fail;                // [nsub] failure flags of the FP32 factorisation
     int fp64_fallbacks;             // subdomains of the last factorisation refactored in FP64
     // device address of the allocation-free entry point's static scratch array
