@@ -136,3 +136,35 @@ def test_library_built_from_the_current_sources():
     from paper_1508_02977_amd import build
     assert api.lib().sf_build_digest().decode() == build.source_digest()
     assert len(build.sources()) >= 8 and any(s.endswith("sfdd.h") for s in build.sources())
+
+
+def test_config_struct_layout_matches_header(tmp_path):
+    # the binding's ctypes sf_config against the C compiler's layout of the header
+    fields = [f[0] for f in api.sf_config._fields_]
+    cname = {"lambda_": "lambda"}
+    src = tmp_path / "layout.c"
+    body = "".join(f'    printf("%s %zu\\n", "{f}", offsetof(sf_config, {cname.get(f, f)}));\n' for f in fields)
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "sfdd.h"\nint main(void) {\n'
+                   '    printf("size %zu\\n", sizeof(sf_config));\n' + body + "    return 0;\n}\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = dict(line.split() for line in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                         check=True).stdout.splitlines())
+    import ctypes
+    assert int(out["size"]) == ctypes.sizeof(api.sf_config)
+    for f in fields:
+        assert int(out[f]) == getattr(api.sf_config, f).offset, f
+
+
+def test_config_validation_host_only():
+    # sf_memory_bytes validates the configuration without a device
+    import ctypes
+    _ensure_built()
+    n = ctypes.c_int64()
+    good = api.make_config(64, 64, 1, 2, 2, 4, deferred_status=1)
+    assert api.lib().sf_memory_bytes(ctypes.byref(good), ctypes.byref(n)) == api.SF_OK and n.value > 0
+    for bad in (api.make_config(64, 64, 1, 2, 2, 4, deferred_status=2),
+                api.make_config(64, 64, 1, 2, 2, 4, pivot_tol=1.0),
+                api.make_config(64, 64, 1, 2, 2, 4, factor_precision=3),
+                api.make_config(64, 64, 1, 2, 2, 4, rho=-1.0)):
+        assert api.lib().sf_memory_bytes(ctypes.byref(bad), ctypes.byref(n)) == api.SF_ERR_INVALID
