@@ -82,6 +82,22 @@ __device__ __forceinline__ void load_tile(const float* __restrict__ T, float tv[
     }
 }
 
+// The exchange words: a pair of tagged 64-bit words (low and high half of a
+// double) moved as one 16-byte buffer access with the device-scope cache
+// policy (sc1: stores write through to memory, loads are not served by a
+// possibly stale L1), what relaxed atomics at device scope do, for half the
+// memory requests of two 8-byte accesses.  A torn pair is caught by the tags.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t words_rsrc(const void* base, int bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, bytes, 0x00020000);
+}
+__device__ __forceinline__ u32x4 words_load16(__amdgpu_buffer_rsrc_t r, int byte_off) {
+    return __builtin_amdgcn_raw_buffer_load_b128(r, byte_off, 0, 16 /* sc1 */);
+}
+__device__ __forceinline__ void words_store16(u32x4 v, __amdgpu_buffer_rsrc_t r, int byte_off) {
+    __builtin_amdgcn_raw_buffer_store_b128(v, r, byte_off, 0, 16 /* sc1 */);
+}
+
 // Lane exchanges of the row reductions, kept in the VALU (no LDS crossbar round
 // trip).  Within each 16-lane row, DPP gives partners 15 - c (row mirror),
 // c ^ 7 inside each half row (half mirror), c ^ 2 and c ^ 1 (quad permutes).
@@ -263,7 +279,7 @@ __global__ void __launch_bounds__(64 * NWV) k_sweep(SweepArgs A) {
     // published rows: per group [3][mp] pairs of 64-bit words (tag << 32 | half
     // of a double); slots 0/1 by phase parity, slot 2 for the last forward line
     uint64_t* __restrict__ pub = reinterpret_cast<uint64_t*>(A.work + d.poff);
-    uint64_t* __restrict__ mypub = pub + (int64_t)grp * 6 * mp;
+    const __amdgpu_buffer_rsrc_t pubr = words_rsrc(pub, 12 * mp * 8);
     DevStatus* st = A.status;
     const long long spin = A.spin_limit;
     const uint32_t epoch = A.epoch_dev ? *A.epoch_dev : A.epoch;
@@ -407,7 +423,7 @@ __global__ void __launch_bounds__(64 * NWV) k_sweep(SweepArgs A) {
     // at most GMAX words per lane in flight (registers), group after group
     auto gather = [&](int g, int q, double* dst) -> int {
         const uint32_t tag = tag_of(g, q);
-        const uint64_t* pbuf = slot_of(g, q);
+        const int pb0 = (int)(slot_of(g, q) - pub) * 8;    // byte offset of the slot
         constexpr int NG = LMAX / 64, GMAX = 6;
         long long n = 0;
 #pragma unroll 1
@@ -423,10 +439,9 @@ __global__ void __launch_bounds__(64 * NWV) k_sweep(SweepArgs A) {
                 for (int v = 0; v < GW; ++v)
                     if (pending & (1u << v)) {
                         const int a = lane + 64 * (u0 + v);
-                        lo[v] = __hip_atomic_load(const_cast<uint64_t*>(pbuf + 2 * a), __ATOMIC_RELAXED,
-                                                  __HIP_MEMORY_SCOPE_AGENT);
-                        hi[v] = __hip_atomic_load(const_cast<uint64_t*>(pbuf + 2 * a + 1), __ATOMIC_RELAXED,
-                                                  __HIP_MEMORY_SCOPE_AGENT);
+                        const u32x4 w = words_load16(pubr, pb0 + 16 * a);
+                        lo[v] = ((uint64_t)w[1] << 32) | w[0];
+                        hi[v] = ((uint64_t)w[3] << 32) | w[2];
                     }
 #pragma unroll
                 for (int v = 0; v < GW; ++v)
@@ -614,10 +629,9 @@ __global__ void __launch_bounds__(64 * NWV) k_sweep(SweepArgs A) {
                     }
                     if (back) y = pw[i] - y;               // x_t = w_t - S_t^{-1} v
                     const uint64_t bits = (uint64_t)__double_as_longlong(y);
-                    __hip_atomic_store(pout + 2 * crow[i], tag | (bits & 0xffffffffull), __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
-                    __hip_atomic_store(pout + 2 * crow[i] + 1, tag | (bits >> 32), __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
+                    const uint32_t tg = (uint32_t)(tag >> 32);
+                    const u32x4 w = {(uint32_t)bits, tg, (uint32_t)(bits >> 32), tg};
+                    words_store16(w, pubr, (int)(pout - pub) * 8 + 16 * crow[i]);
                     if (keep) wt[crow[i]] = y;                     // w_t or x_t
                 }
             }
