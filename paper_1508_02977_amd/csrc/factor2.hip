@@ -306,23 +306,6 @@ __device__ __forceinline__ void f2_tile_of(int q, const F2Own& o, int& I, int& J
     else           { I = o.rowB; J = o.h + o.sp * (q - o.ntA); }
 }
 
-// Publish one 16x16 block (qi, qj) of tile (I, J) if the tile lies in block
-// column `col`: into the exchange slot xb[J] = S_{J,col} (32x32 row-major),
-// as is for J == col, transposed for I == col.
-template <typename T>
-__device__ __forceinline__ void f2_publish_block(const typename F2T<T>::V4& v, T* xb, int col, int I, int J, int qi,
-                                                 int qj, int cr, int cc) {
-    if (J == col) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-            xstore(xb + (int64_t)I * TSZ + (16 * qi + F2T<T>::row(cr, q)) * TS + 16 * qj + cc, v[q]);
-    } else if (I == col) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-            xstore(xb + (int64_t)J * TSZ + (16 * qj + cc) * TS + 16 * qi + F2T<T>::row(cr, q), v[q]);
-    }
-}
-
 // Publish block column `col` of the current matrix (the own blocks in it)
 // into the exchange slots xb[J] = S_{J,col} (32x32 row-major).
 template <typename T>
@@ -974,11 +957,6 @@ __global__ void __launch_bounds__(F2_THREADS) k_factor2(FactorArgs A) {
                     #pragma unroll
                     for (int q = 0; q < 4; ++q) acc[b][q] = -piv[(16 * qi + F2T<T>::row(cr, q)) * LDPT + 16 * qj + cc];
                 }
-                // the next pivot column, block by block as soon as each is
-                // final, so that the stores' acknowledgements (which the
-                // signal below waits for) overlap the remaining updates
-                if (pass == 1 && kn < NT)
-                    f2_publish_block<T>(acc[b], xch + (int64_t)(phase & 1) * NT * TSZ, kn, I, J, qi, qj, cr, cc);
                 // keep the scheduler from hoisting the operand loads of all
                 // blocks at once (register budget)
                 __builtin_amdgcn_sched_barrier(0);
@@ -986,7 +964,10 @@ __global__ void __launch_bounds__(F2_THREADS) k_factor2(FactorArgs A) {
             if (pass == 0)
                 f2_publish_diag<T>(acc, dslot + ((npiv + 1) & 1) * 2 * TSZ, A.epoch + npiv + 1, kn, nblk, own, wv, cr,
                                 cc);
-            if (pass == 1 && kn < NT) f2_signal(cnt);
+            if (pass == 1 && kn < NT) {
+                f2_publish<T>(acc, xch + (int64_t)(phase & 1) * NT * TSZ, kn, nblk, own, wv, cr, cc);
+                f2_signal(cnt);
+            }
             }
             if (kn >= NT) {
                 // ---------- line done: blocks hold -S_t^{-1} ----------------------
