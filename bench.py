@@ -77,11 +77,12 @@ def measured_traffic():
         return None
 
 
-def measured_factor_mfma():
+def measured_factor_mfma(prefix=""):
     """MFMA utilisation of k_factor2 (SQ_VALU_MFMA_BUSY_CYCLES over the
-    GUI-active cycles of all SIMDs) and its executed FP64 MFMA flops per
-    launch from the committed counter summary; None when the factor's sources
-    have changed since the counters were taken."""
+    GUI-active cycles of all SIMDs) and its executed MFMA flops per launch
+    from the committed counter summary (prefix "fp32_": the factorisation in
+    FP32 arithmetic); None when the factor's sources have changed since the
+    counters were taken."""
     try:
         kv = {}
         with open(FACTOR_MFMA_FILE) as f:
@@ -91,8 +92,8 @@ def measured_factor_mfma():
                     kv[k.strip()] = v.strip()
         if kv.get("factor_source_sha256") != source_digest(FACTOR_SOURCES):
             return None
-        return {"mfma_util_pct": float(kv["mfma_util_pct"]),
-                "mfma_flop_per_launch": float(kv["mfma_flop_per_launch"]),
+        return {"mfma_util_pct": float(kv[prefix + "mfma_util_pct"]),
+                "mfma_flop_per_launch": float(kv[prefix + "mfma_flop_per_launch"]),
                 "source": "profiles/k_factor2_plain640_mfma.txt (rocprofv3 --pmc)"}
     except (OSError, KeyError, ValueError):
         return None
@@ -574,10 +575,11 @@ def main():
         # exit at once: time per working launch = all sweep time / sweeps done
         sw_ms, sw_n = prof["sweep"]
         sweeps_timed = sum(max(s) for r in results for s in r.sweeps)
+        fallbacks = api.sf_factor_fallbacks(ctx)
         ctx.close()
         return dict(ms_step=(t1 - t0) * 1e3 / args.steps, last=last, prof=prof, plan=plan, U=U.clone(), alpha=Al.clone(),
                     sw_ms=sw_ms, sw_n=sw_n, sweeps_timed=sweeps_timed,
-                    avg_sweep_ms=sw_ms / max(sweeps_timed, 1))
+                    avg_sweep_ms=sw_ms / max(sweeps_timed, 1), fallbacks=fallbacks)
 
     def phases(form):
         """HIP-event time per step of every kernel class, and the rest of the
@@ -672,6 +674,8 @@ def main():
             "sweep_avg_launch_ms": ch["avg_sweep_ms"],
             "sweep_bytes_per_launch": b32,
             "sweep_achieved_GBs": b32 / (ch["avg_sweep_ms"] * 1e-3) / 1e9,
+            "fp64_fallback_subdomains": ch["fallbacks"],
+            "factor_counters": measured_factor_mfma("fp32_"),
             "phase_ms_per_step": phases(ch),
         }
         out["fp32_tiles_form"] = {
