@@ -98,6 +98,13 @@ __device__ __forceinline__ void words_store16(u32x4 v, __amdgpu_buffer_rsrc_t r,
     __builtin_amdgcn_raw_buffer_store_b128(v, r, byte_off, 0, 16 /* sc1 */);
 }
 
+// Global-to-LDS copy of 16 bytes per lane (no registers): lane l's bytes land
+// at lds + 16 l.  Kept out of the kernel template: its LDS address-space cast
+// has no meaning in the host compilation.
+__device__ __forceinline__ void sw_dma16(const void* src, void* lds) {
+    __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)lds, 16, 0, 0);
+}
+
 // Lane exchanges of the row reductions, kept in the VALU (no LDS crossbar round
 // trip).  Within each 16-lane row, DPP gives partners 15 - c (row mirror),
 // c ^ 7 inside each half row (half mirror), c ^ 2 and c ^ 1 (quad permutes).
@@ -241,6 +248,14 @@ __global__ void __launch_bounds__(64 * NWV) k_sweep(SweepArgs A) {
     __shared__ double vdn[LMAX];                   // vector of the line below (t + 1)
     __shared__ double yw[NWT][RMAX * TS];
     __shared__ int sh_ok;
+    // Staged tiles (FP32 tiles, two-row fast form): the next line's tiles are
+    // copied from memory straight into LDS at the start of a phase (112 KB per
+    // workgroup, so one workgroup per CU), where they stream in while the phase
+    // synchronises.  A tile takes 4 copies of 16 bytes per lane (copy j: lane l
+    // the row 8 j + l / 8, columns 4 (l % 8) .. + 3), so the staged tile is the
+    // stored tile, row-major.
+    constexpr bool STAGE = FAST && RMAX == 2 && sizeof(TT) == 4;
+    __shared__ __attribute__((aligned(16))) TT stg[STAGE ? NWT * PF * TSZ : 1];
 
     const int mode = A.mode, G = A.groups;
     int sub, grp, rank;
@@ -419,6 +434,36 @@ __global__ void __launch_bounds__(64 * NWV) k_sweep(SweepArgs A) {
         for (int p = 0; p < PF; ++p)
             if (slot_ok(p)) load_tile(Tl + toff[p], pre[p]);
     };
+    // staged slots: copy the tiles of phase q into LDS (every slot, a slot
+    // without a tile copies tile 0 of the line, unused, so that the number of
+    // copies is fixed) / from LDS into registers
+    const int lanepart = (8 * (lane >> 4)) * TS + 2 * (lane & 15);   // of tile_lane_offset
+    auto stage_issue = [&](int q) {
+        const TT* Tl = Tb + (int64_t)line_of(q) * tstride;
+#pragma unroll
+        for (int p = 0; p < PF; ++p) {
+            const int tb = slot_ok(p) ? toff[p] - lanepart : 0;     // the tile's first element
+            TT* dst = stg + (wv * PF + p) * TSZ;
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                sw_dma16(Tl + tb + (8 * j + (lane >> 3)) * TS + 4 * (lane & 7), dst + j * 256);
+        }
+    };
+    auto stage_read = [&]() {
+        const int h = lane >> 4, c = lane & 15;
+#pragma unroll
+        for (int p = 0; p < PF; ++p) {
+            if (!slot_ok(p)) continue;
+            const TT* src = stg + (wv * PF + p) * TSZ + h * 256 + 2 * (c & 1);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                // row 8h + i, columns 2c, 2c + 1: copy h, lane 8 i + c / 2, half c % 2
+                const float2 v = *reinterpret_cast<const float2*>(src + 4 * (8 * i + (c >> 1)));
+                pre[p][2 * i] = v.x;
+                pre[p][2 * i + 1] = v.y;
+            }
+        }
+    };
     // control wave: poll the published words of (group g, phase q) into dst,
     // at most GMAX words per lane in flight (registers), group after group
     auto gather = [&](int g, int q, double* dst) -> int {
@@ -464,11 +509,17 @@ __global__ void __launch_bounds__(64 * NWV) k_sweep(SweepArgs A) {
     for (int i = 0; i < NRC; ++i) pw[i] = 0.0;
 
     for (int i = tid; i < NWT * RMAX * TS; i += NTHR) (&yw[0][0])[i] = 0.0;
-    if (!ctl) prefetch(0, true);
+    if (!ctl) {
+        prefetch(0, true);
+        if constexpr (STAGE)
+            if (nphase > 1) stage_issue(1);
+    }
     // Phase structure (B = workgroup barrier):
     //   control wave: [gather(q)] B z B  .  B [finish, publish(q)]
     //   tile waves:              B z B [compute(q)] B [prefetch(q+1)]
-    //   (FP64 tiles: the tiles of q+1 are loaded inside compute(q), slot by slot)
+    //   (FP64 tiles: the tiles of q+1 are loaded inside compute(q), slot by slot;
+    //    staged FP32 tiles: phase q starts by taking its tiles from LDS and
+    //    copying those of q+1 there)
     // Rows are exchanged as tagged 64-bit words (32-bit tag, 32-bit half of a
     // double): a reader polls the words it needs until both halves carry the
     // tag of the wanted phase, so one memory round trip both synchronises and
@@ -478,6 +529,19 @@ __global__ void __launch_bounds__(64 * NWV) k_sweep(SweepArgs A) {
         const int t = line_of(q);
         const bool back = q > L;
         const bool up = has_up(q, t), dn = has_dn(q, t);
+        if constexpr (STAGE) {
+            if (!ctl && q > 0) {
+                // this phase's tiles, copied into LDS during the previous phase
+                // (vmcnt 0: the copies have landed, and so have the vectors
+                // prefetched for this phase), into registers; once those LDS
+                // reads are done (lgkmcnt 0) the slots take the next phase's
+                // tiles, which stream in under this phase's synchronisation
+                __builtin_amdgcn_s_waitcnt(0x0F70);
+                stage_read();
+                __builtin_amdgcn_s_waitcnt(0xC07F);
+                if (q + 1 < nphase) stage_issue(q + 1);
+            }
+        }
         if (up || dn) {
             if (ctl) {
                 int ok = 1;
@@ -497,7 +561,10 @@ __global__ void __launch_bounds__(64 * NWV) k_sweep(SweepArgs A) {
                 }
             }
             __syncthreads();
-            if (!sh_ok) return;
+            if (!sh_ok) {
+                if constexpr (STAGE) __builtin_amdgcn_s_waitcnt(0);   // no copy into LDS left in flight
+                return;
+            }
         }
         // z: forward / middle r_t - (coupling terms); backward the coupling term
         if (!ctl) {
@@ -605,7 +672,7 @@ __global__ void __launch_bounds__(64 * NWV) k_sweep(SweepArgs A) {
         __syncthreads();
         if (!ctl) {
             // (with RELOAD the tile slots have already been reloaded for the next line)
-            if (q + 1 < nphase) prefetch(q + 1, !RELOAD);
+            if (q + 1 < nphase) prefetch(q + 1, !RELOAD && !STAGE);
         } else {
             // finish and publish this rank's rows; keep them; prefetch w
             const uint64_t tag = (uint64_t)tag_of(grp, q) << 32;
