@@ -128,6 +128,15 @@ int sf_assemble(sf_context* ctx, const double* I0, const double* I1, const doubl
  * value as it would have been without deferral (SF_OK if nothing pends).  */
 int sf_sync(sf_context* ctx);
 
+/* Bound every device-side wait of the context's later launches (the factor's
+ * and the sweep's exchanges between workgroups) to `polls` unsuccessful polls
+ * (default 2^20, about a second); a launch whose wait exceeds it stops every
+ * workgroup and its call returns SF_ERR_DEVICE (sf_error_detail: subdomain).
+ * After SF_ERR_DEVICE from the factorisation the context is back to
+ * assembled; from a solve, U holds a partial update and the factors stay
+ * usable.  polls < 0 gives SF_ERR_INVALID.                                  */
+int sf_set_wait_limit(sf_context* ctx, int64_t polls);
+
 /* Section 3.2, local problems: factor every subdomain matrix A_i = A[S_i,S_i]
  * (ordering: lines along the shorter box side, 3 unknowns per node, band
  * half-width 3*ms+5).  Block LDL^T over the lines: S_t = A_tt -

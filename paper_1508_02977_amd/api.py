@@ -66,6 +66,7 @@ _SIGS = {
     "sf_assemble": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "sf_factor_subdomains": (c_int32, [c_void_p]),
     "sf_sync": (c_int32, [c_void_p]),
+    "sf_set_wait_limit": (c_int32, [c_void_p, ctypes.c_int64]),
     "sf_schwarz_solve": (c_int32, [c_void_p, c_void_p, c_double, c_int32, c_void_p, c_void_p]),
     "sf_schwarz_solve_graph": (c_int32, [c_void_p, c_void_p, c_double, c_int32, c_void_p, c_void_p]),
     "sf_autotune": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p]),
@@ -247,6 +248,13 @@ def sf_sync(ctx: Context) -> None:
     """Wait for the context's stream; raises the status that a deferred
     sf_assemble / sf_factor_subdomains left pending."""
     _check(lib().sf_sync(ctx.handle), "sf_sync", ctx)
+
+
+def sf_set_wait_limit(ctx: Context, polls: int) -> None:
+    """Bound every device-side wait of the context's later launches to
+    `polls` unsuccessful polls (default 2**20); a call whose wait exceeds it
+    raises SF_ERR_DEVICE."""
+    _check(lib().sf_set_wait_limit(ctx.handle, int(polls)), "sf_set_wait_limit", ctx)
 
 
 def sf_schwarz_solve(ctx: Context, U, rtol: float, max_sweeps: int):

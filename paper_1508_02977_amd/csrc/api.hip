@@ -346,6 +346,7 @@ int sf_create(const sf_config* cfg, void* stream, sf_context** out) {
     c->W = k.width;
     c->H = k.height;
     c->B = k.batch;
+    c->wait_limit = 1ll << 20;
     if (hipGetDevice(&c->device) != hipSuccess) { sf_destroy(c); return SF_ERR_HIP; }
     // the allocation-free entry point's static array: its address on this
     // device (looked up once per device, with the device current)
@@ -688,6 +689,12 @@ int sf_sync(sf_context* c) {
     const int code = settle(c);
     if (code != SF_OK) return code;
     SF_HIP(hipStreamSynchronize(c->stream));
+    return SF_OK;
+}
+
+int sf_set_wait_limit(sf_context* c, int64_t polls) {
+    if (!c || polls < 0) return SF_ERR_INVALID;
+    c->wait_limit = (long long)polls;
     return SF_OK;
 }
 

@@ -1071,7 +1071,7 @@ int launch_factor2(sf_context* c, int sub0, int nsub_chunk, int Pf, int fp32_ari
     a.W = c->W;
     a.H = c->H;
     a.lam = c->cfg.lambda;
-    a.spin_limit = 1ll << 20;
+    a.spin_limit = c->wait_limit;
     a.ptol = ptol;
     a.fail = c->fail_d;
     a.sublist = sublist;

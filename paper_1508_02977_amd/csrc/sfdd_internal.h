@@ -61,6 +61,7 @@ struct sf_context {
     int nsub;                       // over all pairs
     int state;                      // 0 created, 1 assembled, 2 factored
     int pending;                    // deferred status: PENDING_ASSEMBLE | PENDING_FACTOR
+    long long wait_limit;           // unsuccessful polls of a device-side wait before it gives up
     std::vector<sfdd::SubDesc> subs;
     sfdd::SubDesc* d_subs;
     int maxP;                       // sweep workgroups per chain

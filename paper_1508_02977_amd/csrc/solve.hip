@@ -784,7 +784,7 @@ int launch_sweep(sf_context* c, double* U, const double* r, int single_sub, cons
     a.H = c->H;
     a.mode = single_sub >= 0 ? 1 : 0;
     a.groups = c->groups;
-    a.spin_limit = 1ll << 20;
+    a.spin_limit = c->wait_limit;
     // tags must differ from every tag left in the exchange buffers by earlier
     // launches: advance by more than the tags of one sweep (2 per phase).  The
     // launches of one sweep's chunks share the tag base: their subdomains'
