@@ -97,6 +97,13 @@ __device__ __forceinline__ u32x4 words_load16(__amdgpu_buffer_rsrc_t r, int byte
 __device__ __forceinline__ void words_store16(u32x4 v, __amdgpu_buffer_rsrc_t r, int byte_off) {
     __builtin_amdgcn_raw_buffer_store_b128(v, r, byte_off, 0, 16 /* sc1 */);
 }
+// The same pair written with the default policy: it stays in the writer's
+// XCD L2, where device-scope loads on that XCD see it (loads elsewhere only
+// once the line is written back).  Used when every rank of a subdomain runs
+// on one XCD; the tags keep any other placement correct, only slower.
+__device__ __forceinline__ void words_store16_l2(u32x4 v, __amdgpu_buffer_rsrc_t r, int byte_off) {
+    __builtin_amdgcn_raw_buffer_store_b128(v, r, byte_off, 0, 0);
+}
 
 // Global-to-LDS copy of 16 bytes per lane (no registers): lane l's bytes land
 // at lds + 16 l.  Kept out of the kernel template: its LDS address-space cast
@@ -295,6 +302,9 @@ __global__ void __launch_bounds__(64 * NWV) k_sweep(SweepArgs A) {
     // of a double); slots 0/1 by phase parity, slot 2 for the last forward line
     uint64_t* __restrict__ pub = reinterpret_cast<uint64_t*>(A.work + d.poff);
     const __amdgpu_buffer_rsrc_t pubr = words_rsrc(pub, 12 * mp * 8);
+    // 8 subdomains side by side: workgroup g runs on XCD g mod 8, so all
+    // ranks of a subdomain share one L2 and the published words can stay there
+    const bool pub_l2 = A.lanes == 8;
     DevStatus* st = A.status;
     const long long spin = A.spin_limit;
     const uint32_t epoch = A.epoch_dev ? *A.epoch_dev : A.epoch;
@@ -434,15 +444,14 @@ __global__ void __launch_bounds__(64 * NWV) k_sweep(SweepArgs A) {
         for (int p = 0; p < PF; ++p)
             if (slot_ok(p)) load_tile(Tl + toff[p], pre[p]);
     };
-    // staged slots: copy the tiles of phase q into LDS (every slot, a slot
-    // without a tile copies tile 0 of the line, unused, so that the number of
-    // copies is fixed) / from LDS into registers
+    // staged slots: copy the tiles of phase q into LDS / from LDS into registers
     const int lanepart = (8 * (lane >> 4)) * TS + 2 * (lane & 15);   // of tile_lane_offset
     auto stage_issue = [&](int q) {
         const TT* Tl = Tb + (int64_t)line_of(q) * tstride;
 #pragma unroll
         for (int p = 0; p < PF; ++p) {
-            const int tb = slot_ok(p) ? toff[p] - lanepart : 0;     // the tile's first element
+            if (!slot_ok(p)) continue;
+            const int tb = toff[p] - lanepart;                      // the tile's first element
             TT* dst = stg + (wv * PF + p) * TSZ;
 #pragma unroll
             for (int j = 0; j < 4; ++j)
@@ -698,7 +707,8 @@ __global__ void __launch_bounds__(64 * NWV) k_sweep(SweepArgs A) {
                     const uint64_t bits = (uint64_t)__double_as_longlong(y);
                     const uint32_t tg = (uint32_t)(tag >> 32);
                     const u32x4 w = {(uint32_t)bits, tg, (uint32_t)(bits >> 32), tg};
-                    words_store16(w, pubr, (int)(pout - pub) * 8 + 16 * crow[i]);
+                    if (pub_l2) words_store16_l2(w, pubr, (int)(pout - pub) * 8 + 16 * crow[i]);
+                    else words_store16(w, pubr, (int)(pout - pub) * 8 + 16 * crow[i]);
                     if (keep) wt[crow[i]] = y;                     // w_t or x_t
                 }
             }
