@@ -255,13 +255,13 @@ __global__ void __launch_bounds__(64 * NWV) k_sweep(SweepArgs A) {
     __shared__ double vdn[LMAX];                   // vector of the line below (t + 1)
     __shared__ double yw[NWT][RMAX * TS];
     __shared__ int sh_ok;
-    // Staged tiles (FP32 tiles, two-row fast form): the next line's tiles are
-    // copied from memory straight into LDS at the start of a phase (112 KB per
-    // workgroup, so one workgroup per CU), where they stream in while the phase
-    // synchronises.  A tile takes 4 copies of 16 bytes per lane (copy j: lane l
-    // the row 8 j + l / 8, columns 4 (l % 8) .. + 3), so the staged tile is the
-    // stored tile, row-major.
-    constexpr bool STAGE = FAST && RMAX == 2 && sizeof(TT) == 4;
+    // Staged tiles (FP32 tiles, fast forms): the next line's tiles are copied
+    // from memory straight into LDS at the start of a phase (NWT x PF tiles,
+    // 112 KB per workgroup; the fast forms run one workgroup per CU anyway),
+    // where they stream in while the phase synchronises.  A tile takes 4 copies
+    // of 16 bytes per lane (copy j: lane l the row 8 j + l / 8, columns
+    // 4 (l % 8) .. + 3), so the staged tile is the stored tile, row-major.
+    constexpr bool STAGE = FAST && sizeof(TT) == 4;
     __shared__ __attribute__((aligned(16))) TT stg[STAGE ? NWT * PF * TSZ : 1];
 
     const int mode = A.mode, G = A.groups;
