@@ -168,3 +168,12 @@ def test_config_validation_host_only():
                 api.make_config(64, 64, 1, 2, 2, 4, factor_precision=3),
                 api.make_config(64, 64, 1, 2, 2, 4, rho=-1.0)):
         assert api.lib().sf_memory_bytes(ctypes.byref(bad), ctypes.byref(n)) == api.SF_ERR_INVALID
+
+
+def test_null_context_calls_are_invalid_host_only():
+    # entry points given no context return SF_ERR_INVALID without touching a device
+    _ensure_built()
+    lib = api.lib()
+    assert lib.sf_set_wait_limit(None, 10) == api.SF_ERR_INVALID
+    assert lib.sf_sync(None) == api.SF_ERR_INVALID
+    assert lib.sf_factor_subdomains(None) == api.SF_ERR_INVALID
