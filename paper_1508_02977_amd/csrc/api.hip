@@ -313,6 +313,21 @@ static void chunk_shape(int capacity, int per, int nsub, int cap_chunk, int* lan
     *chunk = std::min(ch, L * ((nsub + L - 1) / L));
 }
 
+// Factor launch shape, `per` co-resident workgroups per subdomain: `main`
+// subdomains side by side in groups of `lanes` (chunk_shape), then as many
+// more as the co-resident workgroups left over hold, each on `per`
+// contiguous workgroups (its ranks spread over XCDs; the factor's exchanges
+// are device-scope, so only their latency differs).
+static void factor_shape(int capacity, int per, int nsub, int cap_chunk, int* lanes, int* main, int* chunk) {
+    int ch = 0;
+    chunk_shape(capacity, per, nsub, cap_chunk, lanes, &ch);
+    const int L = *lanes;
+    *main = per >= 1 && per <= capacity ? L * (capacity / (L * per)) : 0;
+    if (*main == 0) { *chunk = 0; return; }
+    const int tail = (capacity - *main * per) / per;
+    *chunk = std::min(std::min(*main + tail, cap_chunk), nsub);
+}
+
 // Sweep workgroups per chain P and the launch shape that follows (chunks of
 // subdomains whose G P ranks each fit co-resident); host side only.
 static void set_sweep_shape(sf_context* c, int P) {
@@ -405,12 +420,14 @@ int sf_create(const sf_config* cfg, void* stream, sf_context** out) {
     if (maxnt <= sfdd::F2_MAX_NT && occ2 >= 1 && Pf + 1 <= fcap) {
         c->factor_pf = Pf;
         if (8 * 2 * (Pf + 1) <= fcap && 8 * 2 * Pfast <= capacity) c->groups = 2;
-        chunk_shape(fcap, c->groups * (Pf + 1), c->nsub, sfdd::FACTOR_WS_SLOTS, &c->factor_lanes, &c->factor_chunk);
+        factor_shape(fcap, c->groups * (Pf + 1), c->nsub, sfdd::FACTOR_WS_SLOTS, &c->factor_lanes, &c->factor_main,
+                     &c->factor_chunk);
     } else {
         // one workgroup per subdomain (line matrices up to 512)
         if (maxmp > 512) { sf_destroy(c); return SF_ERR_INVALID; }
         c->factor_pf = 0;
         c->factor_lanes = 1;
+        c->factor_main = 1;
         c->factor_chunk = std::min(c->nsub, sfdd::FACTOR_WS_SLOTS);
     }
     const int G = c->groups;
@@ -606,7 +623,8 @@ int sf_factor_subdomains(sf_context* c) {
         for (int s0 = 0; s0 < c->nsub; s0 += c->factor_chunk) {
             const int n = std::min(c->factor_chunk, c->nsub - s0);
             SF_TRY(zero_factor_counters(c));
-            SF_TRY(sfdd::launch_factor2(c, s0, n, c->factor_pf, fp32_arith, nullptr, c->factor_lanes, ptol));
+            SF_TRY(sfdd::launch_factor2(c, s0, n, c->factor_pf, fp32_arith, nullptr, c->factor_lanes, c->factor_main,
+                                        ptol));
         }
     } else {
         SF_TRY(sfdd::launch_factor(c));
@@ -643,7 +661,7 @@ static int factor_status(sf_context* c) {
             hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(1), 0, c->stream, c->sublist_d, 1, (int32_t)i);
             SF_HIP(hipGetLastError());
             SF_TRY(zero_factor_counters(c));
-            SF_TRY(sfdd::launch_factor2(c, 0, 1, sfdd::f2_ranks(c->subs[i].NT), 0, c->sublist_d, 1, 1e-13));
+            SF_TRY(sfdd::launch_factor2(c, 0, 1, sfdd::f2_ranks(c->subs[i].NT), 0, c->sublist_d, 1, 1, 1e-13));
         }
         SF_TRY(sfdd::prof_end(c));
         code = pull_status(c);

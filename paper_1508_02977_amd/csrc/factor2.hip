@@ -127,8 +127,10 @@ __device__ __forceinline__ int colk_at_t(int slot, int r, int c) {
 
 struct FactorArgs {
     const SubDesc* subs;
-    int sub0, nsub;           // subdomains [sub0, nsub) of this launch; sub0 % lanes == 0
+    int sub0, nsub;           // subdomains [sub0, nsub) of this launch
     int lanes;                // subdomains side by side in the grid (8: one XCD each)
+    int nmain;                // the first nmain of them side by side; each later one takes
+                              // the next groups x (pf + 1) workgroups (ranks spread over XCDs)
     int pf;                   // rank slots per chain (the largest f2_ranks(NT))
     int groups;               // chains per subdomain: 1 (top to bottom) or 2 (twisted)
     int fp32;                 // 1: store the inverse tiles in single precision
@@ -533,11 +535,24 @@ __global__ void __launch_bounds__(F2_THREADS) k_factor2(FactorArgs A) {
     __shared__ int sh_ok;
 
     // workgroup g runs on XCD g % 8: with A.lanes = 8 the ranks of subdomain
-    // i are the slots with g % 8 == i % 8, so its exchange stays inside one L2
-    // per chain: ranks 0..pf-1 and the pivot server (rank pf)
-    const int ps = A.pf + 1, slot = blockIdx.x / A.lanes, per = A.groups * ps;
-    const int local = (int)(blockIdx.x % A.lanes) + A.lanes * (slot / per);
-    const int chain = (slot % per) / ps, rank = slot % ps;
+    // i < nmain are the slots with g % 8 == i % 8, so its exchange stays
+    // inside one L2; a subdomain i >= nmain (filling the workgroups that the
+    // side-by-side groups leave) has per contiguous workgroups.  Per chain:
+    // ranks 0..pf-1 and the pivot server (rank pf)
+    const int ps = A.pf + 1, per = A.groups * ps;
+    const int mainwg = A.lanes * ((A.nmain + A.lanes - 1) / A.lanes) * per;
+    int local, within;
+    if ((int)blockIdx.x < mainwg) {
+        const int slot = blockIdx.x / A.lanes;
+        local = (int)(blockIdx.x % A.lanes) + A.lanes * (slot / per);
+        within = slot % per;
+        if (local >= A.nmain) return;                    // idle slot
+    } else {
+        const int b = (int)blockIdx.x - mainwg;
+        local = A.nmain + b / per;
+        within = b % per;
+    }
+    const int chain = within / ps, rank = within % ps;
     const bool server = rank == A.pf;
     if (local >= A.nsub - A.sub0) return;                // idle slot
     const int sub = A.sublist ? A.sublist[local] : A.sub0 + local;
@@ -1053,12 +1068,13 @@ int launch_line_coeffs(sf_context* c) {
 // arithmetic (fp32_arith; the tiles are then stored in FP32), with the pivot
 // threshold ptol; rejected pivots flag their subdomain in c->fail_d.
 int launch_factor2(sf_context* c, int sub0, int nsub_chunk, int Pf, int fp32_arith, const int32_t* sublist,
-                   int lanes, double ptol) {
+                   int lanes, int main_cap, double ptol) {
     FactorArgs a;
     a.subs = c->d_subs;
     a.sub0 = sublist ? 0 : sub0;
     a.nsub = a.sub0 + nsub_chunk;
     a.lanes = lanes;
+    a.nmain = std::min(nsub_chunk, main_cap);
     a.pf = Pf;
     a.groups = c->groups;
     a.fp32 = c->cfg.factor_precision != SF_FP64 ? 1 : 0;
@@ -1081,9 +1097,10 @@ int launch_factor2(sf_context* c, int sub0, int nsub_chunk, int Pf, int fp32_ari
     for (const auto& d : c->subs) maxpiv = std::max(maxpiv, d.nt * d.NT);
     c->factor_epoch += (uint32_t)maxpiv + 4;
     void* args[] = {&a};
-    const int L = lanes;
-    if (hipLaunchCooperativeKernel(factor2_kernel(fp32_arith), dim3(L * ((nsub_chunk + L - 1) / L) * c->groups * (Pf + 1)),
-                                   dim3(F2_THREADS), args, 0, c->stream) != hipSuccess)
+    const int L = lanes, per = c->groups * (Pf + 1);
+    const int grid = L * ((a.nmain + L - 1) / L) * per + (nsub_chunk - a.nmain) * per;
+    if (hipLaunchCooperativeKernel(factor2_kernel(fp32_arith), dim3(grid), dim3(F2_THREADS), args, 0, c->stream) !=
+        hipSuccess)
         return SF_ERR_HIP;
     return SF_OK;
 }

@@ -71,8 +71,10 @@ struct sf_context {
     int groups;                     // chains per subdomain: 2 = twisted factorisation, 1 = top to bottom
     int sweep_rows;                 // largest number of block rows a sweep workgroup owns
     int factor_pf;                  // workgroups per subdomain in the cooperative factor (0: one-WG factor)
-    int factor_chunk;               // subdomains per cooperative factor launch (a multiple of factor_lanes)
+    int factor_chunk;               // subdomains per cooperative factor launch
     int factor_lanes;               // subdomains side by side in a factor grid (8: each on one XCD)
+    int factor_main;                // of a launch's subdomains, at most this many side by side
+                                    // (a multiple of factor_lanes); the rest with contiguous ranks
     uint32_t sweep_epoch;           // tag base for the sweep's published rows
     uint32_t factor_epoch;          // tag base for the factor's pivot blocks and inverses
     double* blur_w;                 // presmoothing weights, 2 blur_r + 1 (sigma > 0)
@@ -151,7 +153,7 @@ int launch_alpha_update(sf_context* c, const double* eta, double* alpha_out, dou
                         double eta_thr, double alpha_th);
 int launch_factor(sf_context* c);
 int launch_factor2(sf_context* c, int sub0, int nsub_chunk, int Pf, int fp32_arith, const int32_t* sublist,
-                   int lanes, double ptol);
+                   int lanes, int main_cap, double ptol);
 int launch_line_coeffs(sf_context* c);
 const void* factor2_kernel(int fp32);
 int launch_sweep(sf_context* c, double* U, const double* r, int single_sub, const double* b_local,

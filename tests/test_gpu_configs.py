@@ -124,7 +124,9 @@ def test_precision_workload_full_size_pair(gpu):
     p = synth.make_pair_4k(4, device=torch.device("cuda"))
     al = synth.constant_alpha(W, H)
     print("prec4k at full size", flush=True)
-    check_full_pair(p.I0, p.I1, al, W, H, 16, 9, 16, [0, 75], inner_nodes(W, H, 12, 6))
+    # subdomain 69 is the last of the factor launch of subdomains 60..69: 8 of
+    # them side by side (one XCD each), 68 and 69 on the workgroups left over
+    check_full_pair(p.I0, p.I1, al, W, H, 16, 9, 16, [0, 69], inner_nodes(W, H, 12, 6))
 
 
 def test_precision_workload_crop_matches_oracle(gpu):

@@ -106,3 +106,31 @@ def test_chunked_factor_and_sweep_launches(gpu):
     api.sf_schwarz_solve_graph(ctx, Ug, 0.0, nsw)
     assert torch.equal(Ug, U)
     ctx.close()
+
+
+def test_factor_launch_tail(gpu):
+    # 164-168-node lines (16 block rows): a subdomain's factor takes 17 co-resident
+    # workgroups (16 split ranks and the pivot server), so a launch holds 8
+    # subdomains side by side (one XCD each) and the ninth on the workgroups
+    # left over, its ranks spread over XCDs.  Every local solve to the FP64
+    # backward-error bar, and the solve to 1e-8
+    W = H = 480
+    p = synth.make_pair("plain640", 23, W=W, H=H)
+    al = synth.random_alpha(W, H, 6)
+    ctx = api.sf_create(W, H, 1, 3, 3, 8)
+    api.sf_assemble(ctx, dev(p.I0[None]), dev(p.I1[None]), dev(al[None]))
+    api.sf_factor_subdomains(ctx)
+    A, _ = fem.assemble(p.I0, p.I1, al, 1.0)
+    subs = schwarz.decompose(W, H, 3, 3, 8)
+    assert {-(-3 * min(s.box[1] - s.box[0], s.box[3] - s.box[2]) // 32) for s in subs} == {16}
+    rng = np.random.default_rng(8)
+    for i, s in enumerate(subs):
+        b = rng.normal(size=s.n)
+        x = torch.empty(s.n, dtype=torch.float64, device="cuda")
+        api.sf_subdomain_solve(ctx, i, dev(b), x)
+        Ai = schwarz.local_matrix(A, s)
+        assert np.linalg.norm(b - Ai @ host(x)) <= 1e-13 * np.linalg.norm(b), i
+    U = torch.zeros(ctx.field_shape(), dtype=torch.float64, device="cuda")
+    code, sw, rr = api.sf_schwarz_solve(ctx, U, 1e-8, 500)
+    assert code == api.SF_OK and rr[0] <= 1e-8
+    ctx.close()
