@@ -313,12 +313,12 @@ static void chunk_shape(int capacity, int per, int nsub, int cap_chunk, int* lan
     *chunk = std::min(ch, L * ((nsub + L - 1) / L));
 }
 
-// Factor launch shape, `per` co-resident workgroups per subdomain: `main`
-// subdomains side by side in groups of `lanes` (chunk_shape), then as many
-// more as the co-resident workgroups left over hold, each on `per`
-// contiguous workgroups (its ranks spread over XCDs; the factor's exchanges
-// are device-scope, so only their latency differs).
-static void factor_shape(int capacity, int per, int nsub, int cap_chunk, int* lanes, int* main, int* chunk) {
+// Shape of a factor or sweep launch, `per` co-resident workgroups per
+// subdomain: `main` subdomains side by side in groups of `lanes`
+// (chunk_shape), then as many more as the co-resident workgroups left over
+// hold, each on `per` contiguous workgroups (its ranks spread over XCDs: the
+// exchanges between them are device-scope, so only their latency differs).
+static void launch_shape(int capacity, int per, int nsub, int cap_chunk, int* lanes, int* main, int* chunk) {
     int ch = 0;
     chunk_shape(capacity, per, nsub, cap_chunk, lanes, &ch);
     const int L = *lanes;
@@ -338,7 +338,7 @@ static void set_sweep_shape(sf_context* c, int P) {
     P = std::max(1, std::min(std::min(P, maxnt), 255));
     if (G * P > c->sweep_capacity) P = std::max(1, c->sweep_capacity / G);
     c->maxP = P;
-    chunk_shape(c->sweep_capacity, G * P, c->nsub, 1 << 30, &c->sweep_lanes, &c->sweep_chunk);
+    launch_shape(c->sweep_capacity, G * P, c->nsub, 1 << 30, &c->sweep_lanes, &c->sweep_main, &c->sweep_chunk);
     c->sweep_rows = 0;
     for (int r = 0; r < P; ++r) {
         int R = 0;
@@ -420,7 +420,7 @@ int sf_create(const sf_config* cfg, void* stream, sf_context** out) {
     if (maxnt <= sfdd::F2_MAX_NT && occ2 >= 1 && Pf + 1 <= fcap) {
         c->factor_pf = Pf;
         if (8 * 2 * (Pf + 1) <= fcap && 8 * 2 * Pfast <= capacity) c->groups = 2;
-        factor_shape(fcap, c->groups * (Pf + 1), c->nsub, sfdd::FACTOR_WS_SLOTS, &c->factor_lanes, &c->factor_main,
+        launch_shape(fcap, c->groups * (Pf + 1), c->nsub, sfdd::FACTOR_WS_SLOTS, &c->factor_lanes, &c->factor_main,
                      &c->factor_chunk);
     } else {
         // one workgroup per subdomain (line matrices up to 512)

@@ -67,7 +67,9 @@ struct sf_context {
     int maxP;                       // sweep workgroups per chain
     int sweep_capacity;             // co-resident sweep workgroups on the device
     int sweep_lanes;                // subdomains side by side in a sweep grid (8: each on one XCD)
-    int sweep_chunk;                // subdomains per sweep launch (a multiple of sweep_lanes)
+    int sweep_chunk;                // subdomains per sweep launch
+    int sweep_main;                 // of a launch's subdomains, at most this many side by side
+                                    // (a multiple of sweep_lanes); the rest with contiguous ranks
     int groups;                     // chains per subdomain: 2 = twisted factorisation, 1 = top to bottom
     int sweep_rows;                 // largest number of block rows a sweep workgroup owns
     int factor_pf;                  // workgroups per subdomain in the cooperative factor (0: one-WG factor)

@@ -33,9 +33,11 @@ constexpr int MAXMP = 768;
 
 struct SweepArgs {
     const SubDesc* subs;
-    int sub0;               // first subdomain of this launch (mode 0; a multiple of lanes)
+    int sub0;               // first subdomain of this launch (mode 0)
     int nsub;               // end of this launch's subdomains (mode 0) ; the single subdomain index (mode 1)
     int lanes;              // subdomains side by side in the grid (8: the ranks of one on one XCD)
+    int nmain;              // mode 0: the first nmain subdomains side by side; each later one
+                            // takes the next groups x P workgroups (ranks spread over XCDs)
     const double* factors;
     double* work;
     const double* r;        // global residual [B][3][H][W] (mode 0)
@@ -266,18 +268,32 @@ __global__ void __launch_bounds__(64 * NWV) k_sweep(SweepArgs A) {
 
     const int mode = A.mode, G = A.groups;
     int sub, grp, rank;
+    bool side_by_side = false;                     // with 8 lanes: every rank of sub on one XCD
     {
-        const int x = blockIdx.x % A.lanes, slot = blockIdx.x / A.lanes;
-        const int P0 = A.subs[0].P;
+        const int P0 = A.subs[0].P, per = G * P0;
         if (mode == 1) {
+            const int x = blockIdx.x % A.lanes, slot = blockIdx.x / A.lanes;
             if (x != 0) return;                        // idle slot
             sub = A.nsub;
             grp = slot / P0;
             rank = slot % P0;
         } else {
-            sub = A.sub0 + x + A.lanes * (slot / (G * P0));
-            grp = (slot % (G * P0)) / P0;
-            rank = slot % P0;
+            const int mainwg = A.lanes * ((A.nmain + A.lanes - 1) / A.lanes) * per;
+            int local, within;
+            if ((int)blockIdx.x < mainwg) {
+                const int x = blockIdx.x % A.lanes, slot = blockIdx.x / A.lanes;
+                local = x + A.lanes * (slot / per);
+                within = slot % per;
+                if (local >= A.nmain) return;          // idle slot
+                side_by_side = true;
+            } else {
+                const int b = (int)blockIdx.x - mainwg;
+                local = A.nmain + b / per;
+                within = b % per;
+            }
+            sub = A.sub0 + local;
+            grp = within / P0;
+            rank = within % P0;
             if (sub >= A.nsub) return;                 // idle slot
         }
     }
@@ -304,7 +320,7 @@ __global__ void __launch_bounds__(64 * NWV) k_sweep(SweepArgs A) {
     const __amdgpu_buffer_rsrc_t pubr = words_rsrc(pub, 12 * mp * 8);
     // 8 subdomains side by side: workgroup g runs on XCD g mod 8, so all
     // ranks of a subdomain share one L2 and the published words can stay there
-    const bool pub_l2 = A.lanes == 8;
+    const bool pub_l2 = A.lanes == 8 && side_by_side;
     DevStatus* st = A.status;
     const long long spin = A.spin_limit;
     const uint32_t epoch = A.epoch_dev ? *A.epoch_dev : A.epoch;
@@ -825,16 +841,19 @@ int launch_sweep(sf_context* c, double* U, const double* r, int single_sub, cons
         a.sub0 = 0;
         a.nsub = single_sub;
         a.lanes = 1;
+        a.nmain = 1;
         return launch(ranks);
     }
-    // chunks of subdomains whose ranks fit co-resident, one launch each
+    // chunks of subdomains whose ranks fit co-resident, one launch each: the
+    // first side by side in groups of L, the rest on contiguous workgroups
     const int L = c->sweep_lanes, chunk = c->sweep_chunk;
     a.lanes = L;
     for (int s0 = 0; s0 < c->nsub; s0 += chunk) {
         const int n = std::min(chunk, c->nsub - s0);
         a.sub0 = s0;
         a.nsub = s0 + n;
-        SF_TRY_SWEEP(launch(L * ((n + L - 1) / L) * ranks));
+        a.nmain = std::min(n, c->sweep_main);
+        SF_TRY_SWEEP(launch(L * ((a.nmain + L - 1) / L) * ranks + (n - a.nmain) * ranks));
     }
     return SF_OK;
 }

@@ -134,3 +134,30 @@ def test_factor_launch_tail(gpu):
     code, sw, rr = api.sf_schwarz_solve(ctx, U, 1e-8, 500)
     assert code == api.SF_OK and rr[0] <= 1e-8
     ctx.close()
+
+
+def test_sweep_launch_tail_matches_oracle(gpu):
+    # 5x5 subdomains of 6 block rows, 5 sweep workgroups per chain, two
+    # chains: 10 co-resident workgroups per subdomain, so a sweep launch holds
+    # 24 subdomains side by side in groups of 8 (one XCD each) and the 25th on
+    # the workgroups left over, its ranks spread over XCDs (device-scope
+    # exchange).  20 RAS iterates element by element against the oracle
+    W = H = 280
+    p = synth.make_pair("plain640", 29, W=W, H=H)
+    al = synth.random_alpha(W, H, 7)
+    ctx = api.sf_create(W, H, 1, 5, 5, 4, band_tile=5)
+    api.sf_assemble(ctx, dev(p.I0[None]), dev(p.I1[None]), dev(al[None]))
+    api.sf_factor_subdomains(ctx)
+    geo = api.sf_subdomain_geometry(ctx, 24)
+    assert geo["P"] == 5 and geo["chains"] == 2, geo
+    A, F = fem.assemble(p.I0, p.I1, al, 1.0)
+    facs = schwarz.factor_subdomains(A, schwarz.decompose(W, H, 5, 5, 4))
+    nsw = 20
+    U = torch.zeros(ctx.field_shape(), dtype=torch.float64, device="cuda")
+    api.sf_schwarz_solve(ctx, U, 0.0, nsw)
+    res = schwarz.ras_solve(A, F, facs, rtol=0.0, max_sweeps=nsw)
+    assert emax(host(U)[0], planes(res.U, W, H)) <= 1e-10
+    Ug = torch.zeros_like(U)
+    api.sf_schwarz_solve_graph(ctx, Ug, 0.0, nsw)
+    assert torch.equal(Ug, U)
+    ctx.close()
