@@ -318,6 +318,7 @@ static void chunk_shape(int capacity, int per, int nsub, int cap_chunk, int* lan
 // (chunk_shape), then as many more as the co-resident workgroups left over
 // hold, each on `per` contiguous workgroups (its ranks spread over XCDs: the
 // exchanges between them are device-scope, so only their latency differs).
+// `chunk` is the launch size that needs the fewest launches, balanced.
 static void launch_shape(int capacity, int per, int nsub, int cap_chunk, int* lanes, int* main, int* chunk) {
     int ch = 0;
     chunk_shape(capacity, per, nsub, cap_chunk, lanes, &ch);
@@ -325,7 +326,10 @@ static void launch_shape(int capacity, int per, int nsub, int cap_chunk, int* la
     *main = per >= 1 && per <= capacity ? L * (capacity / (L * per)) : 0;
     if (*main == 0) { *chunk = 0; return; }
     const int tail = (capacity - *main * per) / per;
-    *chunk = std::min(std::min(*main + tail, cap_chunk), nsub);
+    const int most = std::max(1, std::min(std::min(*main + tail, cap_chunk), nsub));
+    // the fewest launches, balanced: a tail is used only where it saves a launch
+    const int launches = (nsub + most - 1) / most;
+    *chunk = std::max(1, (nsub + launches - 1) / launches);
 }
 
 // Sweep workgroups per chain P and the launch shape that follows (chunks of
