@@ -436,18 +436,27 @@ int sf_create(const sf_config* cfg, void* stream, sf_context** out) {
     }
     const int G = c->groups;
 
-    // sweep workgroups per chain: the most with which every subdomain fits one
-    // launch, balanced over the block rows, while that keeps a fast form;
-    // otherwise the fast forms' count, in chunks of subdomains
+    // sweep workgroups per chain: the fast forms' count, or more where that
+    // keeps a fast form (lines up to 14 block rows; some ranks then own one
+    // block row and others two) and needs no more launches per sweep
     int P;
     if (k.band_tile > 0) {
         P = k.band_tile;
     } else {
-        const int nsx = (c->nsub + 7) / 8;
-        P = std::max(1, std::min(capacity / (8 * nsx * G), maxnt));
-        const int rows = (maxnt + P - 1) / P;
-        if (rows > 2 || (rows == 2 && maxnt > 14)) P = Pfast;
-        else P = (maxnt + rows - 1) / rows;
+        auto launches = [&](int p) {
+            int L = 0, m = 0, ch = 0;
+            launch_shape(capacity, G * p, c->nsub, 1 << 30, &L, &m, &ch);
+            return ch > 0 ? (c->nsub + ch - 1) / ch : c->nsub + 1;
+        };
+        P = Pfast;
+        if (maxnt <= 14) {
+            const int n0 = launches(Pfast);
+            for (int p = maxnt; p > Pfast; --p)
+                if (G * p <= capacity && launches(p) <= n0) {
+                    P = p;
+                    break;
+                }
+        }
     }
     set_sweep_shape(c, P);
 

@@ -68,11 +68,12 @@ def full(gpu):
 
 
 def test_full_size_launch_shape(full):
-    # the shapes the benchmark runs: 16 subdomains, two chains of 6 workgroups each
+    # the shapes the benchmark runs: 16 subdomains, two chains of 8 workgroups each
+    # (all 256 CUs: ranks 0-3 own one block row of the 12, ranks 4-7 two)
     ctx = full["ctx"]
     assert api.sf_num_subdomains(ctx) == 16
     g = api.sf_subdomain_geometry(ctx, 5)
-    assert g["chains"] == 2 and g["P"] == 6
+    assert g["chains"] == 2 and g["P"] == 8
 
 
 def test_full_size_rhs_and_residual(full):
