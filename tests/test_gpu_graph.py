@@ -154,14 +154,16 @@ def test_graph_solve_with_fp32_tiles_equals_ordinary_solve(gpu):
     ctx.close()
 
 
-def test_solves_beside_a_busy_stream(gpu):
+@pytest.mark.parametrize("W,H", [(160, 120), (640, 480)])
+def test_solves_beside_a_busy_stream(gpu, W, H):
     # The sweeps are ordinary launches whose workgroups wait on each other
     # (their grid fits the co-resident capacity measured at creation); here
     # the kernels of another stream hold CUs while they start, so some
-    # workgroups wait for others that are not yet resident.  Every wait is
-    # bounded; the solves (replayed and ordinary) must still end with the
-    # iterate of the solve on an idle device.
-    ctx, _ = context("plain640", 3, 160, 120, 4, 4, 8)
+    # workgroups wait for others that are not yet resident (at 640x480 the
+    # sweep takes every CU: 16 subdomains x 2 chains x 8 workgroups).  Every
+    # wait is bounded; the solves (replayed and ordinary) must still end with
+    # the iterate of the solve on an idle device.
+    ctx, _ = context("plain640", 3, W, H, 4, 4, 8)
     Ue = torch.zeros(ctx.field_shape(), dtype=torch.float64, device="cuda")
     re = api.sf_schwarz_solve(ctx, Ue, 1e-9, 500)
     assert re[0] == api.SF_OK
