@@ -2,6 +2,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "sfdd_internal.h"
@@ -881,11 +882,36 @@ static int graph_iterations(sf_context* c, double* U, double rtol, int32_t max_s
     return rc;
 }
 
+// Sweeps of different contexts do not run at the same time on one device: a
+// sweep launch may take the device's whole co-resident capacity and its
+// workgroups wait on each other, so two overlapping sweeps could each hold
+// part of the device while waiting for workgroups that cannot become
+// resident (until the wait bound ends them with SF_ERR_DEVICE).  Every call
+// that launches sweeps holds its device's lock until its streams have
+// drained; within one process such calls therefore run one at a time per
+// device.
+static std::mutex& sweep_mutex(int device) {
+    static std::mutex m[64];
+    return m[device & 63];
+}
+struct SweepLock {
+    sf_context* c;
+    explicit SweepLock(sf_context* ctx) : c(ctx) { sweep_mutex(c->device).lock(); }
+    ~SweepLock() {
+        (void)hipStreamSynchronize(c->stream);
+        if (c->gstream) (void)hipStreamSynchronize(c->gstream);
+        sweep_mutex(c->device).unlock();
+    }
+    SweepLock(const SweepLock&) = delete;
+    SweepLock& operator=(const SweepLock&) = delete;
+};
+
 int sf_schwarz_solve_graph(sf_context* c, double* U, double rtol, int32_t max_sweeps, int32_t* sweeps,
                            double* relres) {
     if (!c || !U || max_sweeps < 0 || !(rtol >= 0.0)) return SF_ERR_INVALID;
     SF_SETTLE(c);
     if (c->state != ST_FACTORED) return SF_ERR_STATE;
+    SweepLock lock(c);
     if (!c->gstream) {
         // created together on first use; a failure leaves none of them, so a
         // later call never runs with a missing counter
@@ -928,6 +954,7 @@ int sf_schwarz_solve(sf_context* c, double* U, double rtol, int32_t max_sweeps, 
     if (!c || !U || max_sweeps < 0 || !(rtol >= 0.0)) return SF_ERR_INVALID;
     SF_SETTLE(c);
     if (c->state != ST_FACTORED) return SF_ERR_STATE;
+    SweepLock lock(c);
     return schwarz_loop(c, U, c->F, c->Fn2, rtol, max_sweeps, sweeps, relres);
 }
 
@@ -935,6 +962,7 @@ int sf_autotune(sf_context* c, double* U, int32_t trials, int32_t* band_tile) {
     if (!c || !U || trials < 1) return SF_ERR_INVALID;
     SF_SETTLE(c);
     if (c->state != ST_FACTORED) return SF_ERR_STATE;
+    SweepLock lock(c);
     int maxnt = 0;
     for (const auto& d : c->subs) maxnt = std::max(maxnt, d.NT);
     // candidates: for every number of block rows per workgroup, the fewest
@@ -998,6 +1026,7 @@ int sf_adjoint(sf_context* c, const double* U, const double* G, double* P, doubl
     if (c->blur_r > 0 || c->coef) return SF_ERR_INVALID;
     SF_SETTLE(c);
     if (c->state != ST_FACTORED) return SF_ERR_STATE;
+    SweepLock lock(c);
     SF_TRY(sfdd::launch_norm2(c, G, c->Gn2));
     const int rc = schwarz_loop(c, P, G, c->Gn2, rtol, max_sweeps, sweeps, relres);
     if (rc != SF_OK && rc != SF_NOT_CONVERGED) return rc;
@@ -1190,6 +1219,7 @@ int sf_subdomain_solve(sf_context* c, int32_t sub, const double* b, double* x) {
     if (!c || !b || !x || sub < 0 || sub >= c->nsub || b == x) return SF_ERR_INVALID;
     SF_SETTLE(c);
     if (c->state != ST_FACTORED) return SF_ERR_STATE;
+    SweepLock lock(c);
     hipLaunchKernelGGL(k_zero_status_api, dim3(1), dim3(1), 0, c->stream, c->status_d);
     SF_HIP(hipGetLastError());
     SF_TRY(sfdd::launch_sweep(c, nullptr, nullptr, sub, b, x));

@@ -180,3 +180,47 @@ def test_solves_beside_a_busy_stream(gpu, W, H):
         assert r == re and torch.equal(U, Ue), solve.__name__
     assert torch.isfinite(a).all()
     ctx.close()
+
+
+def test_contexts_solving_from_two_threads(gpu):
+    # two 640x480 contexts on their own streams, solved from two host threads
+    # at once (ctypes releases the interpreter lock): every sweep launch takes
+    # the whole device, and the per-device lock runs the calls one at a time,
+    # so both end with their sequential results bit for bit
+    import threading
+    ctxs, refs = [], []
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    for i, st in enumerate(streams):
+        p = synth.make_pair("plain640", 40 + i, W=640, H=480)
+        with torch.cuda.stream(st):
+            ctx = api.sf_create(640, 480, 1, 4, 4, 8, stream=st)
+            api.sf_assemble(ctx, dev(p.I0[None]), dev(p.I1[None]), dev(synth.random_alpha(640, 480, 40 + i)[None]))
+            api.sf_factor_subdomains(ctx)
+        ctxs.append(ctx)
+    torch.cuda.synchronize()
+    for ctx in ctxs:
+        U = torch.zeros(ctx.field_shape(), dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        refs.append((api.sf_schwarz_solve(ctx, U, 1e-9, 500), U))
+    torch.cuda.synchronize()
+    out = [None, None]
+
+    def run(i, solve, U):
+        out[i] = (solve(ctxs[i], U, 1e-9, 500), U)
+
+    for solves in ((api.sf_schwarz_solve, api.sf_schwarz_solve),
+                   (api.sf_schwarz_solve_graph, api.sf_schwarz_solve)):
+        Us = [torch.zeros(ctx.field_shape(), dtype=torch.float64, device="cuda") for ctx in ctxs]
+        torch.cuda.synchronize()
+        out = [None, None]
+        th = [threading.Thread(target=run, args=(i, solves[i], Us[i])) for i in range(2)]
+        for t in th:
+            t.start()
+        for t in th:
+            t.join(timeout=120)
+        torch.cuda.synchronize()
+        for i in range(2):
+            assert out[i] is not None, (i, solves[i].__name__)
+            assert out[i][0] == refs[i][0] and torch.equal(out[i][1], refs[i][1]), (i, solves[i].__name__)
+    for ctx in ctxs:
+        ctx.close()
