@@ -827,9 +827,11 @@ int launch_sweep(sf_context* c, double* U, const double* r, int single_sub, cons
     void* args[] = {&a};
     // An ordinary launch, captured or not: the grid fits the co-resident
     // capacity measured at creation, so every workgroup becomes resident once
-    // the work ahead of it on the device drains, and every wait is bounded (a
-    // cooperative launch guarantees the same residency at a higher cost per
-    // launch: 283 against 279 ms per step of the 640x480 workload).
+    // the work ahead of it on the device drains (the sweeps of other contexts
+    // do not overlap: the calls that launch sweeps hold a per-device lock),
+    // and every wait is bounded.  A cooperative launch guarantees the same
+    // residency at a higher cost per launch (283 against 279 ms per step of
+    // the 640x480 workload).
     auto launch = [&](int grid) -> int {
         if (hipLaunchKernel(kern, dim3(grid), dim3(threads), args, 0, c->stream) != hipSuccess) return SF_ERR_HIP;
         return SF_OK;
