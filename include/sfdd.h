@@ -153,11 +153,13 @@ int sf_factor_subdomains(sf_context* ctx);
  * [B] are HOST arrays (either may be NULL).  A pair with F = 0 gets
  * U = 0 after 0 sweeps.  Returns SF_NOT_CONVERGED if a pair stopped on
  * max_sweeps above rtol (U still written), SF_NONFINITE on a NaN norm.
- * A sweep launch may take the device's whole co-resident capacity, so the
- * calls that run sweeps (this one, sf_schwarz_solve_graph, sf_autotune,
- * sf_adjoint, sf_subdomain_solve) hold a per-device lock of the process
- * until their streams have drained: those of different contexts on one
- * device run one at a time.                                                */
+ * A sweep or factor launch may take the device's whole co-resident
+ * capacity, so the calls that run them (this one, sf_schwarz_solve_graph,
+ * sf_autotune, sf_adjoint, sf_subdomain_solve, and sf_factor_subdomains
+ * unless deferred_status = 1) hold a per-device lock of the process until
+ * their streams have drained: those of different contexts on one device run
+ * one at a time.  A deferred factorisation only enqueues and takes no lock:
+ * order it before other contexts' work on the device with events.         */
 int sf_schwarz_solve(sf_context* ctx, double* U, double rtol, int32_t max_sweeps,
                      int32_t* sweeps, double* relres);
 

@@ -4,6 +4,7 @@
 #include <cstring>
 #include <mutex>
 #include <new>
+#include <optional>
 
 #include "sfdd_internal.h"
 #include "factor2_layout.h"
@@ -616,11 +617,40 @@ int sf_assemble(sf_context* c, const double* I0, const double* I1, const double*
     return SF_OK;
 }
 
+// Sweeps and factorisations of different contexts do not run at the same
+// time on one device: a sweep or factor launch may take the device's whole
+// co-resident capacity and its workgroups wait on each other, so two
+// overlapping launches could each hold part of the device while waiting for
+// workgroups that cannot become resident (until the wait bound ends them
+// with SF_ERR_DEVICE).  Every call that launches them (and waits for them)
+// holds its device's lock until its streams have drained; within one process
+// such calls therefore run one at a time per device.  Recursive: the FP64
+// refactorisation inside a factorisation's status collection takes it again.
+static std::recursive_mutex& sweep_mutex(int device) {
+    static std::recursive_mutex m[64];
+    return m[device & 63];
+}
+struct SweepLock {
+    sf_context* c;
+    explicit SweepLock(sf_context* ctx) : c(ctx) { sweep_mutex(c->device).lock(); }
+    ~SweepLock() {
+        (void)hipStreamSynchronize(c->stream);
+        if (c->gstream) (void)hipStreamSynchronize(c->gstream);
+        sweep_mutex(c->device).unlock();
+    }
+    SweepLock(const SweepLock&) = delete;
+    SweepLock& operator=(const SweepLock&) = delete;
+};
+
 static int factor_status(sf_context* c);
 
 int sf_factor_subdomains(sf_context* c) {
     if (!c) return SF_ERR_INVALID;
     if (c->state < ST_ASSEMBLED) return SF_ERR_STATE;
+    // waiting for the status: the launches are serialised with other contexts'
+    // (with deferred status the call only enqueues and takes no lock)
+    std::optional<SweepLock> lock;
+    if (!c->cfg.deferred_status) lock.emplace(c);
     c->state = ST_ASSEMBLED;                // until the new factors are complete
     SF_TRY(sfdd::prof_begin(c, sfdd::PROF_FACTOR));
     const int fp32_arith = c->cfg.factor_precision == SF_FP32_FACTOR && c->factor_pf > 0;
@@ -662,6 +692,7 @@ static int factor_status(sf_context* c) {
     if (fp32_arith && code == SF_NOT_SPD) {
         // FP64 fallback, subdomain by subdomain (each one alone in its launch,
         // so the factor workspace slots cannot collide)
+        SweepLock lock(c);
         int32_t* hf = (int32_t*)c->host_fail;
         SF_HIP(hipMemcpyAsync(hf, c->fail_d, c->nsub * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
         SF_HIP(hipStreamSynchronize(c->stream));
@@ -881,30 +912,6 @@ static int graph_iterations(sf_context* c, double* U, double rtol, int32_t max_s
     *k_next = k;
     return rc;
 }
-
-// Sweeps of different contexts do not run at the same time on one device: a
-// sweep launch may take the device's whole co-resident capacity and its
-// workgroups wait on each other, so two overlapping sweeps could each hold
-// part of the device while waiting for workgroups that cannot become
-// resident (until the wait bound ends them with SF_ERR_DEVICE).  Every call
-// that launches sweeps holds its device's lock until its streams have
-// drained; within one process such calls therefore run one at a time per
-// device.
-static std::mutex& sweep_mutex(int device) {
-    static std::mutex m[64];
-    return m[device & 63];
-}
-struct SweepLock {
-    sf_context* c;
-    explicit SweepLock(sf_context* ctx) : c(ctx) { sweep_mutex(c->device).lock(); }
-    ~SweepLock() {
-        (void)hipStreamSynchronize(c->stream);
-        if (c->gstream) (void)hipStreamSynchronize(c->gstream);
-        sweep_mutex(c->device).unlock();
-    }
-    SweepLock(const SweepLock&) = delete;
-    SweepLock& operator=(const SweepLock&) = delete;
-};
 
 int sf_schwarz_solve_graph(sf_context* c, double* U, double rtol, int32_t max_sweeps, int32_t* sweeps,
                            double* relres) {

@@ -183,10 +183,11 @@ def test_solves_beside_a_busy_stream(gpu, W, H):
 
 
 def test_contexts_solving_from_two_threads(gpu):
-    # two 640x480 contexts on their own streams, solved from two host threads
-    # at once (ctypes releases the interpreter lock): every sweep launch takes
-    # the whole device, and the per-device lock runs the calls one at a time,
-    # so both end with their sequential results bit for bit
+    # two 640x480 contexts on their own streams, solved (and one refactored
+    # while the other solves) from two host threads at once (ctypes releases
+    # the interpreter lock): every sweep launch takes the whole device, and
+    # the per-device lock runs the calls one at a time, so both end with their
+    # sequential results bit for bit
     import threading
     ctxs, refs = [], []
     streams = [torch.cuda.Stream(), torch.cuda.Stream()]
@@ -222,5 +223,20 @@ def test_contexts_solving_from_two_threads(gpu):
         for i in range(2):
             assert out[i] is not None, (i, solves[i].__name__)
             assert out[i][0] == refs[i][0] and torch.equal(out[i][1], refs[i][1]), (i, solves[i].__name__)
+    # one context refactored while the other solves
+    U1 = torch.zeros(ctxs[1].field_shape(), dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    out = [None, None]
+    ta = threading.Thread(target=lambda: out.__setitem__(0, api.sf_factor_subdomains(ctxs[0])))
+    tb = threading.Thread(target=run, args=(1, api.sf_schwarz_solve, U1))
+    ta.start()
+    tb.start()
+    ta.join(timeout=120)
+    tb.join(timeout=120)
+    torch.cuda.synchronize()
+    assert out[1] is not None and out[1][0] == refs[1][0] and torch.equal(out[1][1], refs[1][1])
+    U0 = torch.zeros(ctxs[0].field_shape(), dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    assert api.sf_schwarz_solve(ctxs[0], U0, 1e-9, 500) == refs[0][0] and torch.equal(U0, refs[0][1])
     for ctx in ctxs:
         ctx.close()
