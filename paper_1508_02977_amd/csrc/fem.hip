@@ -118,11 +118,19 @@ __global__ void k_residual(const double* __restrict__ f0, const double* __restri
         double out[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) out[c] = F[(pair * 3 + c) * nn + node];
+        // plain data term: branch-free over the six elements (so that all
+        // their loads are in flight together): an element outside the image
+        // is evaluated on the nearest cell and contributes an exact zero
+        // (x - 0 = x, so the sum is the one over the elements that exist, in
+        // the same order).  The smoothed term (more loads per element) keeps
+        // the skip, which needs fewer registers.
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
             const Around a = around(k);
-            const int cx = x + a.dcx, cy = y + a.dcy;
-            if (cx < 0 || cy < 0 || cx >= W - 1 || cy >= H - 1) continue;
+            const int cx0 = x + a.dcx, cy0 = y + a.dcy;
+            const bool inside = cx0 >= 0 && cy0 >= 0 && cx0 < W - 1 && cy0 < H - 1;
+            if (CLG && !inside) continue;
+            const int cx = min(max(cx0, 0), W - 2), cy = min(max(cy0, 0), H - 2);
             double u[3][3];
 #pragma unroll
             for (int v = 0; v < 3; ++v) {
@@ -139,9 +147,9 @@ __global__ void k_residual(const double* __restrict__ f0, const double* __restri
                 Elem e = load_elem(fp, ap, W, H, cx, cy, a.t);
                 elem_apply_row(e, a.t, a.v, u, lam, o);
             }
-            out[0] -= o[0];
-            out[1] -= o[1];
-            out[2] -= o[2];
+            out[0] -= inside ? o[0] : 0.0;
+            out[1] -= inside ? o[1] : 0.0;
+            out[2] -= inside ? o[2] : 0.0;
         }
 #pragma unroll
         for (int c = 0; c < 3; ++c) r[(pair * 3 + c) * nn + node] = out[c];
